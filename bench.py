@@ -1,0 +1,141 @@
+"""Throughput of the fused D2Q9 stream-and-collide step on one MI355X.
+
+Workload: 4096 x 4096 periodic double shear layer (Ma = 0.1, rho0 = 1, Re = 3e4 so
+nu = U L / Re), populations stored as shifted FP32 deviations, REG relaxation rates.  One
+bench step advances the grid by one time step with each of the eight collision models (eight
+independent grids, one launch each), so `value` is the aggregate MLUPS over the models and
+`per_model` gives each model's own rate.  Inputs are resident in HBM before timing starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec f32|f64|f16] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E spec
+
+
+def bytes_per_cell(prec: str) -> int:
+    return 18 * {"f64": 8, "f32": 4, "f16": 2}[prec]
+
+
+def cpu_baseline(models, budget_s: float = 16.0):
+    """The oracle (single-threaded FP64) on a bounded sample: 256 x 256 double shear layer,
+    each model run for whole steps until its share of the time budget is used."""
+    import oracle
+    from paper_2002_05265_amd import inputs
+
+    n = 256
+    rho, ux, uy = inputs.dsl_fields(n, n, 0.1)
+    omega = inputs.rates(inputs.dsl_nu(n), "REG")
+    f0 = oracle.init_eq(4, rho, ux, uy)
+    updates, elapsed, steps_done = 0, 0.0, {}
+    for name in models:
+        t0 = time.perf_counter()
+        f, k = f0, 0
+        while True:
+            f = oracle.step(f, oracle.MODELS[name], 4, omega, 1)
+            k += 1
+            if time.perf_counter() - t0 > budget_s / len(models):
+                break
+        elapsed += time.perf_counter() - t0
+        updates += n * n * k
+        steps_done[name] = k
+    return {"value": updates / elapsed / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{n}x{n} double shear layer, FP64, steps per model {steps_done}, "
+                      f"{elapsed:.1f} s total"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--prec", default="f32", choices=["f32", "f64", "f16"])
+    ap.add_argument("--models", default="BGK,RM,HM,CM,CHM,K,PR,RR")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the grid would shard as y-slabs with a one-row halo; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2002_05265_amd import inputs
+    from paper_2002_05265_amd.sim import Sim
+
+    torch.cuda.set_device(0)
+    models = args.models.split(",")
+    n = args.n
+    mach = 0.1
+    nu = inputs.dsl_nu(n, mach)
+    omega = inputs.rates(nu, "REG")
+    rho, ux, uy = inputs.dsl_fields(n, n, mach)
+    sims = {m: Sim(rho, ux, uy, prec=args.prec, eq_order=4, device="cuda:0") for m in models}
+    for m, s in sims.items():
+        s.step(m, omega, args.warmup)
+    torch.cuda.synchronize()
+
+    ev = {m: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for m in models}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for m, s in sims.items():
+        ev[m][0].record()
+        s.step(m, omega, args.steps)
+        ev[m][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    cells = n * n
+    per_model = {}
+    for m in models:
+        ms = ev[m][0].elapsed_time(ev[m][1])
+        mlups = cells * args.steps / (ms * 1e-3) / 1e6
+        gbs = mlups * 1e6 * bytes_per_cell(args.prec) / 1e9
+        per_model[m] = {"mlups": round(mlups, 1), "us_per_step": round(ms * 1e3 / args.steps, 2),
+                        "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    status = {m: s.status() for m, s in sims.items()}
+    value = cells * args.steps * len(models) / wall / 1e6
+    dominant = max(models, key=lambda m: per_model[m]["us_per_step"])
+    dom_us = per_model[dominant]["us_per_step"]
+    achieved = cells * bytes_per_cell(args.prec) / (dom_us * 1e-6) / 1e9
+    line = {
+        "metric": "MLUPS per collision model at 4096^2 FP32 + % HBM roofline",
+        "value": round(value, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32": "f32", "f64": "f64", "f16": "f16-storage/f32"}[args.prec],
+        "data": "synthetic: analytic double shear layer initial condition",
+        "config": {"workload": f"D2Q9 periodic double shear layer {n}x{n}, Ma=0.1, Re=3e4, "
+                               f"{'shifted ' if args.prec != 'f64' else ''}{args.prec} populations, "
+                               f"REG rates, 8 collision models (one grid each)",
+                   "nx": n, "ny": n, "models": models, "omega": [round(w, 6) for w in omega]},
+        "roofline": {"bound": "hbm", "kernel": f"k_step<{dominant}>", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+        "per_model": per_model,
+        "blowup": {m: st[1] for m, st in status.items()},
+    }
+    for s in sims.values():
+        s.close()
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(models)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

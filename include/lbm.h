@@ -1,0 +1,138 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) D2Q9 stream-and-collide library (liblbm.so).
+ *
+ * The method is the periodic stream-and-collide lattice Boltzmann scheme
+ *     f_i(x + xi_i, t + 1) = f*_i(x, t)                                (eq. StreamCollide)
+ * with the post-collision populations f* produced by one of the collision models of
+ * Coreixas, Wissocq, Chopard & Latt (2020), Appendix B: each is a per-cell moment transform,
+ * a relaxation toward the (extended) equilibrium, and a back-transform to populations.
+ *
+ * Conventions shared by every entry point
+ *   - Lattice: D2Q9, velocities in the index order
+ *       i = 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1) 7:(-1,-1) 8:(1,-1),
+ *     c_s^2 = 1/3 (Section 2 and eq. extendedFeq).
+ *   - Grid: nx x ny nodes, periodic in both directions.  Scalar fields are [y][x] row-major
+ *     (x fastest), FP64.  Population arrays exchanged with the caller are [q][y][x], FP64.
+ *   - State: the state at step n is the PRE-collision populations f(., n).  One step is
+ *     collide-then-stream.  The initial state is f(., 0) = f^eq_N(rho(x), u(x)).
+ *   - Pointers documented "device" must be device memory of the current HIP device (for
+ *     example torch CUDA tensors); "host" pointers are ordinary CPU memory.
+ *   - Every function returns LBM_OK (0) or a negative status and never throws or aborts;
+ *     lbm_last_error() gives a message for the last failure on the calling thread.
+ *   - Asynchrony: work is enqueued on the stream given at lbm_init (NULL = default stream).
+ *     Functions that return host values (lbm_moments, lbm_status) synchronise that stream.
+ *   - Threading: one context must not be used by two threads at the same time.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_Q 9
+#define LBM_NOMEGA 5 /* {omega_nu, omega_b, omega_21, omega_12, omega_22} */
+
+/* Collision models (Appendix B).  LBM_STREAM_ONLY copies f* = f (exact permutation test). */
+enum {
+    LBM_BGK = 0, /* single relaxation toward f^eq_N with omega_nu                          */
+    LBM_RM = 1,  /* raw moments, eq. RMcoll                                                 */
+    LBM_HM = 2,  /* Hermite moments, relaxed then mapped by eq. HM2RM_Q9                    */
+    LBM_CM = 3,  /* central moments (equilibrium order 4 only)                              */
+    LBM_CHM = 4, /* central Hermite moments, eq. CHMcoll / eq. CHM2HM_Q9 (order 4 only)     */
+    LBM_K = 5,   /* cumulants (order 4 only)                                                */
+    LBM_PR = 6,  /* standard regularisation = HM with omega_21 = omega_12 = omega_22 = 1     */
+    LBM_RR = 7,  /* recursive regularisation, eq. HMColl_Q9 with eq. RRformulas_D2Q9        */
+    LBM_STREAM_ONLY = 99
+};
+
+/* Storage precision of the populations. */
+enum {
+    LBM_F64 = 0,         /* f_i stored in FP64, FP64 arithmetic                               */
+    LBM_F32_SHIFTED = 1, /* h_i = f_i - w_i rho0 stored in FP32, FP32 arithmetic, FP64 rho     */
+    LBM_F16_SHIFTED = 2  /* h_i stored in FP16, FP32 arithmetic, FP64 rho                      */
+};
+
+/* Status codes. */
+enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,      /* bad argument (size, pointer, rate, model/precision code)          */
+    LBM_EUNSUPPORTED = -2,/* valid but unsupported combination (e.g. CM with eq_order < 4)     */
+    LBM_EHIP = -3,        /* a HIP runtime call or kernel launch failed                        */
+    LBM_ESTATE = -4       /* context not initialised / wrong state                             */
+};
+
+typedef struct lbm_ctx lbm_ctx; /* opaque, host-side, owned by the library */
+
+/* Bytes of device memory the caller must provide for the populations of an nx x ny grid at
+ * precision prec (two copies of the nine population planes, each plane padded to 256 bytes).
+ * Returns 0 for invalid arguments. */
+size_t lbm_population_bytes(int nx, int ny, int prec);
+
+/* Create a context and set f(., 0) = f^eq_N(rho, u) (eq. extendedFeq; N = eq_order, the
+ * Hermite equilibrium truncated above order N: 2 = standard second order, 3 = with A21/A12,
+ * 4 = extended product form).
+ *   out        host: receives the new context (NULL on failure)
+ *   nx, ny     grid size, each >= 2, nx * ny * 9 < 2^31
+ *   prec       LBM_F64 / LBM_F32_SHIFTED / LBM_F16_SHIFTED
+ *   eq_order   2, 3 or 4
+ *   rho0       reference density; shifted precisions store f_i - w_i rho0 (must be > 0);
+ *              ignored by LBM_F64, which stores f_i unshifted
+ *   rho,ux,uy  device, nx*ny FP64 each, [y][x]: initial density and velocity (read only,
+ *              not retained)
+ *   pop_buf    device, caller-owned, >= lbm_population_bytes(nx, ny, prec) bytes, 256-byte
+ *              aligned; must stay allocated until lbm_destroy
+ *   pop_bytes  size of pop_buf in bytes
+ *   hip_stream hipStream_t on which all work of this context is enqueued (NULL = default)
+ * The library allocates only a small reduction scratch; it never frees pop_buf. */
+int lbm_init(lbm_ctx** out, int nx, int ny, int prec, int eq_order, double rho0,
+             const double* rho, const double* ux, const double* uy, void* pop_buf,
+             size_t pop_bytes, void* hip_stream);
+
+/* Advance nsteps >= 0 steps of stream-and-collide with the given model (eq. StreamCollide).
+ *   omega  host, LBM_NOMEGA doubles in [0, 2]: (omega_nu, omega_b, omega_21, omega_12,
+ *          omega_22).  omega_nu = 1 / (nu / c_s^2 + 1/2) (Section 4c).  The paper's SRT
+ *          preset is all five equal to omega_nu; its REG preset is omega_b = omega_nu and
+ *          omega_21 = omega_12 = omega_22 = 1.  BGK uses omega_nu only; PR ignores the last
+ *          three (forced to 1).
+ * CM, CHM and K require eq_order == 4 (LBM_EUNSUPPORTED otherwise).
+ * Every step also checks the state it reads for a node with !(rho > 0) (this catches NaN);
+ * the first such step is reported by lbm_status.  Asynchronous. */
+int lbm_step(lbm_ctx* ctx, int model, const double* omega, int nsteps);
+
+/* Macroscopic fields of the current state f(., n) and their totals.
+ *   rho, ux, uy  device, nx*ny FP64 each, [y][x], or NULL to skip a field
+ *   totals       host, 6 doubles or NULL: {sum rho, sum rho ux, sum rho uy,
+ *                sum rho |u|^2 / 2, mean |u|^2 (unweighted domain mean), n}
+ * rho = sum_i f_i and rho u = sum_i xi_i f_i (eq. RMcoll), all in FP64.  Synchronises the
+ * stream when totals != NULL. */
+int lbm_moments(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* totals);
+
+/* Step counter n of the current state and the first step whose state had a node with
+ * !(rho > 0) (-1 if none so far).  A bad state n is detected when it is next read: by
+ * lbm_step (state n is read by the step that leaves it) or by lbm_moments.
+ * Synchronises the stream.  step and blowup_step are host pointers, either may be NULL. */
+int lbm_status(lbm_ctx* ctx, long long* step, long long* blowup_step);
+
+/* Copy the current state f(., n) out as unshifted FP64 populations.
+ *   f  device, 9*nx*ny FP64, [q][y][x].  Asynchronous. */
+int lbm_get_state(lbm_ctx* ctx, double* f);
+
+/* Replace the current state by f (device, 9*nx*ny FP64, [q][y][x], unshifted) and set the
+ * step counter to step (>= 0).  The blow-up record is cleared.  Asynchronous. */
+int lbm_set_state(lbm_ctx* ctx, const double* f, long long step);
+
+/* Release the context (not pop_buf).  NULL is accepted.  Synchronises the stream. */
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Message for the last failure on the calling thread ("" if none).  Owned by the library,
+ * valid until the next call on this thread. */
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

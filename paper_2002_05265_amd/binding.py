@@ -1,0 +1,133 @@
+"""ctypes binding of liblbm.so (the C ABI in include/lbm.h).
+
+Argument marshalling only: every function has the C name and forwards plain integers, floats
+and pointers.  Device pointers are passed as Python ints (for example ``tensor.data_ptr()``).
+A non-zero status raises :class:`LbmError` carrying the library's message.  There is no
+fallback: if the HIP library is not built, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import pathlib
+
+LIB_PATH = pathlib.Path(__file__).resolve().with_name("liblbm.so")
+
+LBM_Q = 9
+LBM_NOMEGA = 5
+LBM_BGK, LBM_RM, LBM_HM, LBM_CM, LBM_CHM, LBM_K, LBM_PR, LBM_RR = range(8)
+LBM_STREAM_ONLY = 99
+LBM_F64, LBM_F32_SHIFTED, LBM_F16_SHIFTED = 0, 1, 2
+PRECISIONS = {"f64": LBM_F64, "f32": LBM_F32_SHIFTED, "f16": LBM_F16_SHIFTED}
+STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_EUNSUPPORTED", -3: "LBM_EHIP", -4: "LBM_ESTATE"}
+
+# every symbol declared in include/lbm.h and include/lbm_batch.h / lbm_adjoint.h
+EXPORTS = (
+    "lbm_population_bytes", "lbm_init", "lbm_step", "lbm_moments", "lbm_status",
+    "lbm_get_state", "lbm_set_state", "lbm_destroy", "lbm_last_error",
+)
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code: int, what: str, message: str):
+        super().__init__(f"{what}: {STATUS.get(code, code)}: {message}")
+        self.code = code
+
+
+_lib = None
+_vp, _i, _d, _sz, _ll = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_longlong
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def _declare(L: ctypes.CDLL):
+    sig = {
+        "lbm_population_bytes": (_sz, [_i, _i, _i]),
+        "lbm_init": (_i, [ctypes.POINTER(_vp), _i, _i, _i, _i, _d, _vp, _vp, _vp, _vp, _sz, _vp]),
+        "lbm_step": (_i, [_vp, _i, _dp, _i]),
+        "lbm_moments": (_i, [_vp, _vp, _vp, _vp, _dp]),
+        "lbm_status": (_i, [_vp, ctypes.POINTER(_ll), ctypes.POINTER(_ll)]),
+        "lbm_get_state": (_i, [_vp, _vp]),
+        "lbm_set_state": (_i, [_vp, _vp, _ll]),
+        "lbm_destroy": (None, [_vp]),
+        "lbm_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    for name, (res, args) in EXTRA_SIGNATURES.items():
+        if hasattr(L, name):
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+
+
+EXTRA_SIGNATURES: dict = {}
+
+
+def lib() -> ctypes.CDLL:
+    """Load liblbm.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(there is no CPU fallback)")
+        L = ctypes.CDLL(str(LIB_PATH))
+        _declare(L)
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise LbmError(rc, what, lib().lbm_last_error().decode(errors="replace"))
+
+
+def _omega(omega):
+    w = [float(v) for v in omega]
+    if len(w) != LBM_NOMEGA:
+        raise ValueError(f"omega must have {LBM_NOMEGA} entries")
+    return (ctypes.c_double * LBM_NOMEGA)(*w)
+
+
+def lbm_population_bytes(nx: int, ny: int, prec: int) -> int:
+    return int(lib().lbm_population_bytes(nx, ny, prec))
+
+
+def lbm_init(nx: int, ny: int, prec: int, eq_order: int, rho0: float, rho: int, ux: int, uy: int,
+             pop_buf: int, pop_bytes: int, stream: int) -> int:
+    ctx = _vp()
+    _check(lib().lbm_init(ctypes.byref(ctx), nx, ny, prec, eq_order, rho0, rho, ux, uy, pop_buf,
+                          pop_bytes, stream or None), "lbm_init")
+    return ctx.value
+
+
+def lbm_step(ctx: int, model: int, omega, nsteps: int):
+    _check(lib().lbm_step(ctx, model, _omega(omega), nsteps), "lbm_step")
+
+
+def lbm_moments(ctx: int, rho: int | None, ux: int | None, uy: int | None, want_totals=True):
+    tot = (ctypes.c_double * 6)() if want_totals else None
+    _check(lib().lbm_moments(ctx, rho, ux, uy, tot), "lbm_moments")
+    return list(tot) if want_totals else None
+
+
+def lbm_status(ctx: int):
+    step, blow = _ll(), _ll()
+    _check(lib().lbm_status(ctx, ctypes.byref(step), ctypes.byref(blow)), "lbm_status")
+    return step.value, blow.value
+
+
+def lbm_get_state(ctx: int, f: int):
+    _check(lib().lbm_get_state(ctx, f), "lbm_get_state")
+
+
+def lbm_set_state(ctx: int, f: int, step: int):
+    _check(lib().lbm_set_state(ctx, f, step), "lbm_set_state")
+
+
+def lbm_destroy(ctx: int):
+    lib().lbm_destroy(ctx)
+
+
+def lbm_last_error() -> str:
+    return lib().lbm_last_error().decode(errors="replace")

@@ -1,0 +1,428 @@
+// liblbm: fused periodic D2Q9 stream-and-collide for gfx950, and the C ABI declared in lbm.h.
+//
+// Data layout in HBM: two copies of nine population planes, plane q of copy c at
+//   base + (c * 9 + q) * plane elements, plane = nx * ny rounded up to 256 bytes,
+// each plane [y][x] with x fastest.  A wavefront (64 lanes) handles 64 consecutive x of one
+// row, so every population load and store of a wave is one contiguous 64-element segment.
+//
+// Time stepping (eq. StreamCollide) is a pull scheme: the buffer of copy `cur` holds the
+// post-collision populations f*(., n-1); a step gathers f_i(x, n) = f*_i(x - xi_i, n-1) with
+// periodic wrap, collides in registers and writes f*(x, n) to the other copy.  Streaming is a
+// pure permutation of stored values, so it is exact.  The initial state is written
+// pre-streamed backwards (stored_i(x) = f^eq_i(x + xi_i)) so that the first pull yields f^eq(x).
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <type_traits>
+
+#include "lbm.h"
+#include "lbm_cell.hpp"
+#include "lbm_internal.hpp"
+
+using namespace lbm;
+
+namespace lbm {
+
+thread_local std::string g_err;
+
+int set_error(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int check_hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return LBM_OK;
+    return set_error(LBM_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+Launch launch_for(int nx, int ny) {
+    int bw = 256;
+    while (bw > 64 && bw / 2 >= nx) bw /= 2;
+    const int bh = 256 / bw;
+    Launch l;
+    l.block = dim3(bw, bh, 1);
+    l.grid = dim3((nx + bw - 1) / bw, (ny + bh - 1) / bh, 1);
+    return l;
+}
+
+long long plane_elems(int nx, int ny, int prec) {
+    const long long align = 256 / elem_size(prec);
+    const long long n = (long long)nx * ny;
+    return (n + align - 1) / align * align;
+}
+
+int validate_omega(const double* w) {
+    if (!w) return set_error(LBM_EINVAL, "omega is NULL");
+    for (int k = 0; k < LBM_NOMEGA; ++k)
+        if (!(w[k] >= 0.0 && w[k] <= 2.0))
+            return set_error(LBM_EINVAL, "omega[%d] = %g outside [0, 2]", k, w[k]);
+    return LBM_OK;
+}
+
+int validate_model(int model, int eq_order) {
+    switch (model) {
+        case LBM_BGK: case LBM_RM: case LBM_HM: case LBM_PR: case LBM_RR: case LBM_STREAM_ONLY:
+            return LBM_OK;
+        case LBM_CM: case LBM_CHM: case LBM_K:
+            if (eq_order != 4)
+                return set_error(LBM_EUNSUPPORTED,
+                                 "model %d relaxes central quantities and needs eq_order 4 (got %d)",
+                                 model, eq_order);
+            return LBM_OK;
+        default:
+            return set_error(LBM_EINVAL, "unknown model %d", model);
+    }
+}
+
+}  // namespace lbm
+
+namespace {
+
+// ---------------------------------------------------------------------------------------------
+// kernels
+
+template <int MODEL, int PREC>
+__global__ __launch_bounds__(256) void k_step(const typename Store<PREC>::S* __restrict__ src,
+                                              typename Store<PREC>::S* __restrict__ dst, Geom g,
+                                              Coef<typename Store<PREC>::R> c, double rho_s,
+                                              int N, int step, int* __restrict__ blowup) {
+    using R = typename Store<PREC>::R;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= g.nx || y >= g.ny) return;
+    const Nbr nb = neighbours(x, y, g.nx, g.ny);
+    R h[9];
+    pull_load(src, g.plane, nb, h);
+    double rho_d;
+    const Macro<R> m = macro_of(h, rho_s, rho_d);
+    flag_bad(!(rho_d > 0.0), blowup, step);
+    collide<MODEL>(h, m, c, N);
+    store_cell(dst, g.plane, nb.r0 + (unsigned)x, h);
+}
+
+// Macroscopic fields of the state f(., n) (pulled from the post-collision copy) and per-block
+// partial sums of {rho, rho ux, rho uy, rho |u|^2 / 2, |u|^2} in FP64.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_moments(const typename Store<PREC>::S* __restrict__ src,
+                                                 Geom g, double rho_s, double* __restrict__ rho,
+                                                 double* __restrict__ ux, double* __restrict__ uy,
+                                                 double* __restrict__ partials, int step,
+                                                 int* __restrict__ blowup) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (x < g.nx && y < g.ny) {
+        const Nbr nb = neighbours(x, y, g.nx, g.ny);
+        double h[9];
+        pull_load(src, g.plane, nb, h);
+        double r = rho_s + (((h[0] + (h[1] + h[3])) + (h[2] + h[4])) + ((h[5] + h[7]) + (h[6] + h[8])));
+        const double jx = (h[1] + h[5] + h[8]) - (h[3] + h[6] + h[7]);
+        const double jy = (h[2] + h[5] + h[6]) - (h[4] + h[7] + h[8]);
+        const double u = jx / r, w = jy / r;
+        const unsigned c = nb.r0 + (unsigned)x;
+        if (rho) rho[c] = r;
+        if (ux) ux[c] = u;
+        if (uy) uy[c] = w;
+        const double u2 = u * u + w * w;
+        v[0] = r; v[1] = r * u; v[2] = r * w; v[3] = 0.5 * r * u2; v[4] = u2;
+        flag_bad(!(r > 0.0), blowup, step);
+    }
+    block_sum<5>(v, partials + 5 * (size_t)(blockIdx.y * gridDim.x + blockIdx.x));
+}
+
+// Sum nblocks rows of 5 partials in a fixed order (one block of 256 threads).
+__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partials, int nblocks,
+                                                  double* __restrict__ out) {
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+        for (int k = 0; k < 5; ++k) v[k] += partials[5 * (size_t)b + k];
+    block_sum<5>(v, out);
+}
+
+// Unshifted FP64 pre-collision populations, [q][y][x] dense.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_get_state(const typename Store<PREC>::S* __restrict__ src,
+                                                   Geom g, double rho_s, double* __restrict__ f) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= g.nx || y >= g.ny) return;
+    const Nbr nb = neighbours(x, y, g.nx, g.ny);
+    double h[9];
+    pull_load(src, g.plane, nb, h);
+    const size_t cells = (size_t)g.nx * g.ny, c = nb.r0 + (size_t)x;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i * cells + c] = h[i] + rho_s * rest_weight(i);
+}
+
+// Store pre-collision populations f (unshifted FP64, [q][y][x]) pre-streamed backwards so that
+// the next pull returns f(x): value i of node x goes to node x - xi_i.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_set_state(typename Store<PREC>::S* __restrict__ dst,
+                                                   Geom g, double rho_s,
+                                                   const double* __restrict__ f) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= g.nx || y >= g.ny) return;
+    const size_t cells = (size_t)g.nx * g.ny, c = (size_t)y * g.nx + x;
+    double h[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) h[i] = f[i * cells + c] - rho_s * rest_weight(i);
+    prestream_store(dst, g, x, y, h);
+}
+
+// f(., 0) = f^eq_N(rho, u), stored pre-streamed like k_set_state.  FP64 arithmetic.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_init_eq(typename Store<PREC>::S* __restrict__ dst, Geom g,
+                                                 double rho_s, int N, const double* __restrict__ rho,
+                                                 const double* __restrict__ ux,
+                                                 const double* __restrict__ uy) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= g.nx || y >= g.ny) return;
+    const size_t c = (size_t)y * g.nx + x;
+    Macro<double> m;
+    m.rho = rho[c];
+    m.ux = ux[c];
+    m.uy = uy[c];
+    m.drho = m.rho - rho_s;
+    m.jx = m.rho * m.ux;
+    m.jy = m.rho * m.uy;
+    const Eq<double> e = hermite_eq(m, N);
+    double h[9];
+    hermite_to_pop(m, e.e20, e.e02, e.e11, e.e21, e.e12, e.e22, h);
+    prestream_store(dst, g, x, y, h);
+}
+
+// ---------------------------------------------------------------------------------------------
+// host side
+
+template <int MODEL, int PREC>
+void launch_step_t(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c) {
+    using S = typename Store<PREC>::S;
+    const Launch l = launch_for(ctx->nx, ctx->ny);
+    const S* src = reinterpret_cast<const S*>(ctx->copy(ctx->cur));
+    S* dst = reinterpret_cast<S*>(ctx->copy(ctx->cur ^ 1));
+    hipLaunchKernelGGL((k_step<MODEL, PREC>), l.grid, l.block, 0, ctx->stream, src, dst,
+                       ctx->geom(), c, ctx->rho_s, ctx->eq_order, (int)ctx->step, ctx->d_flag);
+}
+
+template <int PREC>
+void launch_step_p(lbm_ctx* ctx, int model, const double* w) {
+    const Coef<typename Store<PREC>::R> c = make_coef<typename Store<PREC>::R>(w);
+    switch (model) {
+        case LBM_BGK: launch_step_t<kBGK, PREC>(ctx, c); break;
+        case LBM_RM: launch_step_t<kRM, PREC>(ctx, c); break;
+        case LBM_HM: launch_step_t<kHM, PREC>(ctx, c); break;
+        case LBM_CM: launch_step_t<kCM, PREC>(ctx, c); break;
+        case LBM_CHM: launch_step_t<kCHM, PREC>(ctx, c); break;
+        case LBM_K: launch_step_t<kK, PREC>(ctx, c); break;
+        case LBM_PR: launch_step_t<kPR, PREC>(ctx, c); break;
+        case LBM_RR: launch_step_t<kRR, PREC>(ctx, c); break;
+        default: launch_step_t<kStreamOnly, PREC>(ctx, c); break;
+    }
+}
+
+template <int PREC>
+void launch_moments_p(lbm_ctx* ctx, double* rho, double* ux, double* uy) {
+    using S = typename Store<PREC>::S;
+    const Launch l = launch_for(ctx->nx, ctx->ny);
+    hipLaunchKernelGGL((k_moments<PREC>), l.grid, l.block, 0, ctx->stream,
+                       reinterpret_cast<const S*>(ctx->copy(ctx->cur)), ctx->geom(), ctx->rho_s, rho,
+                       ux, uy, ctx->d_part, (int)ctx->step, ctx->d_flag);
+}
+
+template <int PREC>
+void launch_get_p(lbm_ctx* ctx, double* f) {
+    using S = typename Store<PREC>::S;
+    const Launch l = launch_for(ctx->nx, ctx->ny);
+    hipLaunchKernelGGL((k_get_state<PREC>), l.grid, l.block, 0, ctx->stream,
+                       reinterpret_cast<const S*>(ctx->copy(ctx->cur)), ctx->geom(), ctx->rho_s, f);
+}
+
+template <int PREC>
+void launch_set_p(lbm_ctx* ctx, const double* f) {
+    using S = typename Store<PREC>::S;
+    const Launch l = launch_for(ctx->nx, ctx->ny);
+    hipLaunchKernelGGL((k_set_state<PREC>), l.grid, l.block, 0, ctx->stream,
+                       reinterpret_cast<S*>(ctx->copy(ctx->cur)), ctx->geom(), ctx->rho_s, f);
+}
+
+template <int PREC>
+void launch_init_p(lbm_ctx* ctx, const double* rho, const double* ux, const double* uy) {
+    using S = typename Store<PREC>::S;
+    const Launch l = launch_for(ctx->nx, ctx->ny);
+    hipLaunchKernelGGL((k_init_eq<PREC>), l.grid, l.block, 0, ctx->stream,
+                       reinterpret_cast<S*>(ctx->copy(ctx->cur)), ctx->geom(), ctx->rho_s,
+                       ctx->eq_order, rho, ux, uy);
+}
+
+#define LBM_DISPATCH_PREC(prec, fn, ...)                      \
+    do {                                                      \
+        switch (prec) {                                       \
+            case LBM_F64: fn<kF64>(__VA_ARGS__); break;       \
+            case LBM_F32_SHIFTED: fn<kF32>(__VA_ARGS__); break; \
+            default: fn<kF16>(__VA_ARGS__); break;            \
+        }                                                     \
+    } while (0)
+
+__global__ void k_fill_int(int* __restrict__ p, int n, int v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+int reset_flag(lbm_ctx* ctx) {
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ctx->stream, ctx->d_flag, 1, INT_MAX);
+    return check_hip(hipGetLastError(), "reset blow-up flag");
+}
+
+}  // namespace
+
+// -------------------------------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+size_t lbm_population_bytes(int nx, int ny, int prec) {
+    if (nx < 2 || ny < 2 || prec < LBM_F64 || prec > LBM_F16_SHIFTED) return 0;
+    if ((long long)nx * ny * 9 >= (1LL << 31)) return 0;
+    return (size_t)(2 * 9 * plane_elems(nx, ny, prec) * elem_size(prec));
+}
+
+int lbm_init(lbm_ctx** out, int nx, int ny, int prec, int eq_order, double rho0, const double* rho,
+             const double* ux, const double* uy, void* pop_buf, size_t pop_bytes,
+             void* hip_stream) {
+    if (!out) return set_error(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nx < 2 || ny < 2) return set_error(LBM_EINVAL, "grid %d x %d: each side must be >= 2", nx, ny);
+    if ((long long)nx * ny * 9 >= (1LL << 31))
+        return set_error(LBM_EINVAL, "grid %d x %d too large (9 nx ny must be < 2^31)", nx, ny);
+    if (prec < LBM_F64 || prec > LBM_F16_SHIFTED) return set_error(LBM_EINVAL, "unknown precision %d", prec);
+    if (eq_order < 2 || eq_order > 4) return set_error(LBM_EINVAL, "eq_order %d not in {2,3,4}", eq_order);
+    if (prec != LBM_F64 && !(rho0 > 0.0)) return set_error(LBM_EINVAL, "rho0 must be > 0 (got %g)", rho0);
+    if (!rho || !ux || !uy) return set_error(LBM_EINVAL, "rho/ux/uy must be device pointers");
+    if (!pop_buf) return set_error(LBM_EINVAL, "pop_buf is NULL");
+    if (reinterpret_cast<uintptr_t>(pop_buf) % 256 != 0)
+        return set_error(LBM_EINVAL, "pop_buf must be 256-byte aligned");
+    const size_t need = lbm_population_bytes(nx, ny, prec);
+    if (pop_bytes < need)
+        return set_error(LBM_EINVAL, "pop_bytes %zu < required %zu", pop_bytes, need);
+
+    lbm_ctx* ctx = new lbm_ctx();
+    ctx->nx = nx;
+    ctx->ny = ny;
+    ctx->prec = prec;
+    ctx->eq_order = eq_order;
+    ctx->rho_s = prec == LBM_F64 ? 0.0 : rho0;
+    ctx->buf = static_cast<char*>(pop_buf);
+    ctx->bytes = pop_bytes;
+    ctx->plane = plane_elems(nx, ny, prec);
+    ctx->esize = elem_size(prec);
+    ctx->cur = 0;
+    ctx->step = 0;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    const Launch l = launch_for(nx, ny);
+    ctx->nblocks = (int)(l.grid.x * l.grid.y);
+    int rc = check_hip(hipGetDevice(&ctx->device), "hipGetDevice");
+    if (rc == LBM_OK) rc = check_hip(hipMalloc(&ctx->d_flag, sizeof(int)), "hipMalloc(flag)");
+    if (rc == LBM_OK)
+        rc = check_hip(hipMalloc(&ctx->d_part, sizeof(double) * 5 * (size_t)ctx->nblocks), "hipMalloc(partials)");
+    if (rc == LBM_OK) rc = check_hip(hipMalloc(&ctx->d_tot, sizeof(double) * 5), "hipMalloc(totals)");
+    if (rc == LBM_OK) rc = reset_flag(ctx);
+    if (rc == LBM_OK) {
+        LBM_DISPATCH_PREC(prec, launch_init_p, ctx, rho, ux, uy);
+        rc = check_hip(hipGetLastError(), "init kernel launch");
+    }
+    if (rc != LBM_OK) {
+        lbm_destroy(ctx);
+        return rc;
+    }
+    *out = ctx;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* ctx, int model, const double* omega, int nsteps) {
+    if (!ctx) return set_error(LBM_ESTATE, "context is NULL");
+    if (nsteps < 0) return set_error(LBM_EINVAL, "nsteps %d < 0", nsteps);
+    int rc = validate_model(model, ctx->eq_order);
+    if (rc != LBM_OK) return rc;
+    rc = validate_omega(omega);
+    if (rc != LBM_OK) return rc;
+    if (ctx->step + nsteps >= INT_MAX) return set_error(LBM_EINVAL, "step counter would overflow");
+    for (int s = 0; s < nsteps; ++s) {
+        LBM_DISPATCH_PREC(ctx->prec, launch_step_p, ctx, model, omega);
+        ctx->cur ^= 1;
+        ctx->step += 1;
+    }
+    return check_hip(hipGetLastError(), "step kernel launch");
+}
+
+int lbm_moments(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* totals) {
+    if (!ctx) return set_error(LBM_ESTATE, "context is NULL");
+    LBM_DISPATCH_PREC(ctx->prec, launch_moments_p, ctx, rho, ux, uy);
+    int rc = check_hip(hipGetLastError(), "moments kernel launch");
+    if (rc != LBM_OK || !totals) return rc;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, ctx->stream, ctx->d_part, ctx->nblocks,
+                       ctx->d_tot);
+    rc = check_hip(hipGetLastError(), "finalize kernel launch");
+    double t[5];
+    if (rc == LBM_OK)
+        rc = check_hip(hipMemcpyAsync(t, ctx->d_tot, sizeof(t), hipMemcpyDeviceToHost, ctx->stream),
+                       "copy totals");
+    if (rc == LBM_OK) rc = check_hip(hipStreamSynchronize(ctx->stream), "synchronise");
+    if (rc != LBM_OK) return rc;
+    for (int k = 0; k < 4; ++k) totals[k] = t[k];
+    totals[4] = t[4] / ((double)ctx->nx * (double)ctx->ny);
+    totals[5] = (double)ctx->step;
+    return LBM_OK;
+}
+
+int lbm_status(lbm_ctx* ctx, long long* step, long long* blowup_step) {
+    if (!ctx) return set_error(LBM_ESTATE, "context is NULL");
+    int flag = INT_MAX;
+    int rc = check_hip(hipMemcpyAsync(&flag, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream),
+                       "copy blow-up flag");
+    if (rc == LBM_OK) rc = check_hip(hipStreamSynchronize(ctx->stream), "synchronise");
+    if (rc != LBM_OK) return rc;
+    if (step) *step = ctx->step;
+    if (blowup_step) *blowup_step = flag == INT_MAX ? -1 : (long long)flag;
+    return LBM_OK;
+}
+
+int lbm_get_state(lbm_ctx* ctx, double* f) {
+    if (!ctx) return set_error(LBM_ESTATE, "context is NULL");
+    if (!f) return set_error(LBM_EINVAL, "f is NULL");
+    LBM_DISPATCH_PREC(ctx->prec, launch_get_p, ctx, f);
+    return check_hip(hipGetLastError(), "get_state kernel launch");
+}
+
+int lbm_set_state(lbm_ctx* ctx, const double* f, long long step) {
+    if (!ctx) return set_error(LBM_ESTATE, "context is NULL");
+    if (!f) return set_error(LBM_EINVAL, "f is NULL");
+    if (step < 0 || step >= INT_MAX) return set_error(LBM_EINVAL, "step %lld out of range", step);
+    LBM_DISPATCH_PREC(ctx->prec, launch_set_p, ctx, f);
+    int rc = check_hip(hipGetLastError(), "set_state kernel launch");
+    if (rc != LBM_OK) return rc;
+    ctx->step = step;
+    return reset_flag(ctx);
+}
+
+void lbm_destroy(lbm_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->d_flag) (void)hipFree(ctx->d_flag);
+    if (ctx->d_part) (void)hipFree(ctx->d_part);
+    if (ctx->d_tot) (void)hipFree(ctx->d_tot);
+    delete ctx;
+}
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,171 @@
+// Internal helpers of liblbm shared by the plain, batched and adjoint kernels: storage types,
+// periodic neighbour addressing, pull loads / stores, conserved quantities, block reductions
+// and the context structure behind the opaque lbm_ctx handle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <type_traits>
+
+#include "lbm.h"
+#include "lbm_cell.hpp"
+
+namespace lbm {
+
+// Storage type S and arithmetic type R of each precision.
+template <int PREC> struct Store;
+template <> struct Store<kF64> { using S = double; using R = double; };
+template <> struct Store<kF32> { using S = float; using R = float; };
+template <> struct Store<kF16> { using S = _Float16; using R = float; };
+
+inline size_t elem_size(int prec) { return prec == LBM_F64 ? 8 : (prec == LBM_F32_SHIFTED ? 4 : 2); }
+
+struct Geom {
+    int nx, ny;
+    long long plane;  // elements per population plane
+};
+
+struct Launch {
+    dim3 grid, block;
+};
+
+// Row offsets of rows y, y-1, y+1 and columns x, x-1, x+1 with periodic wrap.
+struct Nbr {
+    unsigned r0, rm, rp;
+    unsigned x, xm, xp;
+};
+
+__device__ __forceinline__ Nbr neighbours(int x, int y, int nx, int ny) {
+    Nbr n;
+    const int ym = y == 0 ? ny - 1 : y - 1;
+    const int yp = y == ny - 1 ? 0 : y + 1;
+    n.r0 = (unsigned)y * (unsigned)nx;
+    n.rm = (unsigned)ym * (unsigned)nx;
+    n.rp = (unsigned)yp * (unsigned)nx;
+    n.x = (unsigned)x;
+    n.xm = (unsigned)(x == 0 ? nx - 1 : x - 1);
+    n.xp = (unsigned)(x == nx - 1 ? 0 : x + 1);
+    return n;
+}
+
+// Gather f_i(x) = stored_i(x - xi_i).
+template <typename S, typename R>
+__device__ __forceinline__ void pull_load(const S* __restrict__ src, long long plane, const Nbr& n,
+                                          R (&h)[9]) {
+    h[0] = R(src[0 * plane + n.r0 + n.x]);
+    h[1] = R(src[1 * plane + n.r0 + n.xm]);
+    h[2] = R(src[2 * plane + n.rm + n.x]);
+    h[3] = R(src[3 * plane + n.r0 + n.xp]);
+    h[4] = R(src[4 * plane + n.rp + n.x]);
+    h[5] = R(src[5 * plane + n.rm + n.xm]);
+    h[6] = R(src[6 * plane + n.rm + n.xp]);
+    h[7] = R(src[7 * plane + n.rp + n.xp]);
+    h[8] = R(src[8 * plane + n.rp + n.xm]);
+}
+
+template <typename S, typename R>
+__device__ __forceinline__ void store_cell(S* __restrict__ dst, long long plane, unsigned c,
+                                           const R (&h)[9]) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) dst[i * plane + c] = S(h[i]);
+}
+
+// Store value i of node (x, y) where the next pull of node (x, y) reads it, i.e. at node
+// (x, y) - xi_i: the buffer then holds the state pre-streamed backwards by one step.
+template <typename S, typename R>
+__device__ __forceinline__ void prestream_store(S* __restrict__ dst, const Geom& g, int x, int y,
+                                                const R (&h)[9]) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        int xd = x - cx(i), yd = y - cy(i);
+        xd = xd < 0 ? g.nx - 1 : (xd >= g.nx ? 0 : xd);
+        yd = yd < 0 ? g.ny - 1 : (yd >= g.ny ? 0 : yd);
+        dst[i * g.plane + (long long)yd * g.nx + xd] = S(h[i]);
+    }
+}
+
+// Conserved quantities of a cell.  The density is always recovered in FP64:
+// rho = rho_s + sum_i h_i; rho_d returns it for the blow-up test.
+template <typename R>
+__device__ __forceinline__ Macro<R> macro_of(const R (&h)[9], double rho_s, double& rho_d) {
+    Macro<R> m;
+    if constexpr (std::is_same<R, double>::value) {
+        m.drho = ((h[0] + (h[1] + h[3])) + (h[2] + h[4])) + ((h[5] + h[7]) + (h[6] + h[8]));
+        m.rho = rho_s + m.drho;
+        rho_d = m.rho;
+    } else {
+        const double d = (((double)h[0] + ((double)h[1] + (double)h[3])) + ((double)h[2] + (double)h[4])) +
+                         (((double)h[5] + (double)h[7]) + ((double)h[6] + (double)h[8]));
+        rho_d = rho_s + d;
+        m.drho = (R)d;
+        m.rho = (R)rho_d;
+    }
+    m.jx = ((h[1] + h[5]) + h[8]) - ((h[3] + h[6]) + h[7]);
+    m.jy = ((h[2] + h[5]) + h[6]) - ((h[4] + h[7]) + h[8]);
+    m.ux = m.jx / m.rho;
+    m.uy = m.jy / m.rho;
+    return m;
+}
+
+// Record `step` in *flag (atomic min) if any lane of the wave saw a bad node.
+__device__ __forceinline__ void flag_bad(bool bad, int* flag, int step) {
+    const unsigned long long b = __ballot(bad);
+    if (b != 0ull) {
+        const int first = __ffsll((unsigned long long)b) - 1;
+        if ((int)__lane_id() == first) atomicMin(flag, step);
+    }
+}
+
+// Sum K doubles over the block (any 1D/2D shape up to 1024 threads) and write them to out[]
+// from thread 0.  Fixed reduction order: deterministic.
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* __restrict__ out) {
+    __shared__ double sh[16][K];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    const int nthreads = blockDim.x * blockDim.y * blockDim.z;
+    const int lane = tid & 63, wave = tid >> 6;
+    if (lane == 0)
+        for (int k = 0; k < K; ++k) sh[wave][k] = v[k];
+    __syncthreads();
+    if (tid == 0) {
+        const int nw = (nthreads + 63) >> 6;
+        for (int k = 0; k < K; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s += sh[w][k];
+            out[k] = s;
+        }
+    }
+}
+
+int set_error(int code, const char* fmt, ...);
+int check_hip(hipError_t e, const char* what);
+Launch launch_for(int nx, int ny);
+long long plane_elems(int nx, int ny, int prec);
+int validate_omega(const double* w);
+int validate_model(int model, int eq_order);
+
+}  // namespace lbm
+
+struct lbm_ctx {
+    int nx = 0, ny = 0, prec = 0, eq_order = 4;
+    double rho_s = 0.0;           // storage shift: h_i = f_i - w_i rho_s
+    char* buf = nullptr;          // caller-owned population buffer (two copies)
+    size_t bytes = 0;
+    long long plane = 0;          // elements per population plane
+    size_t esize = 8;             // bytes per stored population
+    int cur = 0;                  // copy holding f*(., n - 1)
+    long long step = 0;           // n
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int nblocks = 0;              // blocks of the per-cell launch
+    int* d_flag = nullptr;        // first bad step (INT_MAX = none)
+    double* d_part = nullptr;     // per-block partial sums, 5 per block
+    double* d_tot = nullptr;      // 5 totals
+
+    char* copy(int c) const { return buf + (size_t)c * 9 * (size_t)plane * esize; }
+    lbm::Geom geom() const { return lbm::Geom{nx, ny, plane}; }
+};
