@@ -52,6 +52,90 @@ def cpu_baseline(models, budget_s: float = 16.0):
                       f"{elapsed:.1f} s total"}
 
 
+def time_models(prec: str, n: int, models, steps: int, warmup: int, omega, fields):
+    """Per-model timing of `steps` launches on an n x n grid (HIP events on the launch stream)."""
+    import torch
+
+    from paper_2002_05265_amd.sim import Sim
+
+    out = {}
+    for m in models:
+        s = Sim(*fields, prec=prec, eq_order=4, device="cuda:0")
+        s.step(m, omega, warmup)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        s.step(m, omega, steps)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / steps
+        mlups = n * n / us
+        gbs = mlups * 1e6 * bytes_per_cell(prec) / 1e9
+        out[m] = {"mlups": round(mlups, 1), "us_per_step": round(us, 2), "hbm_gbs": round(gbs, 1),
+                  "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "blowup": s.status()[1]}
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    return out
+
+
+def batched_sweep(steps: int, plain_f64_mlups: float, n_inst: int = 512):
+    """Random stability sweep: n_inst instances (side in {64..512}, Ma in [0, 0.6], log10 nu in
+    [-7, -2], model uniform over the eight, one Fourier-mode perturbation of amplitude 1e-3),
+    FP64, advanced by one persistent launch.  Throughput counts the nodes actually updated
+    (an instance stops after the step at which it blew up)."""
+    import torch
+
+    from paper_2002_05265_amd import inputs
+    from paper_2002_05265_amd.batch import Batch
+    from paper_2002_05265_amd.sim import Sim
+
+    insts = inputs.sweep_instances(n_inst)
+    for k, d in enumerate(insts):
+        d["omega"] = inputs.rates(d["nu"], "SRT" if k % 2 == 0 else "REG")
+        d["eq_order"] = 4
+    fields = [inputs.sweep_fields(d) for d in insts]
+    b = Batch(insts, fields, prec="f64", device="cuda:0")
+    tuned = b.autotune(3)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    b.run(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3
+    _, blow = b.status()
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    updates = sum(d["nx"] * d["ny"] * (steps if bl < 0 else min(bl + 1, steps)) for d, bl in zip(insts, blow))
+    mlups = updates / sec / 1e6
+    # the same instances through the plain kernel, one launch per instance and step
+    ps = 50
+    sims = [Sim(*f, prec="f64", eq_order=4, device="cuda:0") for f in fields]
+    torch.cuda.synchronize()
+    e0.record()
+    for d, s in zip(insts, sims):
+        s.step(d["model"], d["omega"], ps)
+    e1.record()
+    torch.cuda.synchronize()
+    plain_sec = e0.elapsed_time(e1) * 1e-3
+    plain_updates = sum(d["nx"] * d["ny"] * ps for d in insts)
+    for s in sims:
+        s.close()
+    del sims
+    torch.cuda.empty_cache()
+    return {"instances": n_inst, "steps": steps, "seconds": round(sec, 3),
+            "active_updates": updates, "mlups": round(mlups, 1),
+            "vs_plain_f64_4096": round(mlups / plain_f64_mlups, 3),
+            "plain_same_instances_mlups": round(plain_updates / plain_sec / 1e6, 1),
+            "vs_plain_same_instances": round(mlups / (plain_updates / plain_sec / 1e6), 3),
+            "blown_up": int(sum(1 for bl in blow if bl >= 0)),
+            "blowup_steps_first10": blow[:10],
+            "autotuned": {"nodes_per_thread": tuned[0], "groups_per_cu": tuned[1]},
+            "precision": "f64"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,6 +145,11 @@ def main():
     ap.add_argument("--prec", default="f32", choices=["f32", "f64", "f16"])
     ap.add_argument("--models", default="BGK,RM,HM,CM,CHM,K,PR,RR")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the FP64/FP16, batched and adjoint measurements")
+    ap.add_argument("--batch-steps", type=int, default=20000)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -73,6 +162,16 @@ def main():
     from paper_2002_05265_amd.sim import Sim
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        # a plain copy of known size: 1 GiB read + 1 GiB written per launch
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 1 << 30, "copy_probe_bytes_written": 1 << 30,
+                          "launches": 5}), flush=True)
+        return
     models = args.models.split(",")
     n = args.n
     mach = 0.1
@@ -132,6 +231,14 @@ def main():
     }
     for s in sims.values():
         s.close()
+    del sims
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        fields = (rho, ux, uy)
+        extra_steps = max(20, args.steps // 2)
+        line["precisions"] = {p: time_models(p, n, models, extra_steps, 5, omega, fields) for p in ("f64", "f16")}
+        f64_mlups = min(v["mlups"] for v in line["precisions"]["f64"].values())
+        line["batched"] = batched_sweep(args.batch_steps, f64_mlups)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(models)
     print(json.dumps(line), flush=True)

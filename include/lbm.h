@@ -124,6 +124,21 @@ int lbm_get_state(lbm_ctx* ctx, double* f);
  * step counter to step (>= 0).  The blow-up record is cleared.  Asynchronous. */
 int lbm_set_state(lbm_ctx* ctx, const double* f, long long step);
 
+/* Launch shape of the step kernel for one model (model code, or LBM_STREAM_ONLY):
+ *   rows  nodes per thread along y: 1, 2 or 4
+ *   xcd   0 = hardware block order, 1 = blocks renumbered so that each of the eight XCDs
+ *         owns one contiguous band of tiles
+ * Results do not depend on the shape (every node is computed by the same arithmetic). */
+int lbm_set_launch(lbm_ctx* ctx, int model, int rows, int xcd);
+
+/* Autotune the launch shape of `model` on this context's grid: every candidate shape
+ * (rows in {1, 2, 4} x xcd in {0, 1}) is timed with HIP events over `trials` (>= 1) launches
+ * that recompute the current step from the same input copy, so the state and the step
+ * counter are unchanged.  The fastest shape is kept for the model and returned through
+ * rows_out / xcd_out / us_per_step (host pointers, each may be NULL).  Synchronises. */
+int lbm_autotune(lbm_ctx* ctx, int model, const double* omega, int trials, int* rows_out,
+                 int* xcd_out, double* us_per_step);
+
 /* Release the context (not pop_buf).  NULL is accepted.  Synchronises the stream. */
 void lbm_destroy(lbm_ctx* ctx);
 

@@ -1,0 +1,91 @@
+/*
+ * lbm_batch.h - many independent periodic D2Q9 simulations advanced by one persistent launch.
+ *
+ * Each instance is a stream-and-collide run (eq. StreamCollide) with its own grid size,
+ * collision model (Appendix B), equilibrium order and relaxation rates, as in the paper's
+ * numerical stability study (Section 5b-c: one simulation per (model, Ma, nu) point, with a
+ * blow-up test).  Instances share nothing; their nodes are cut into tiles of 256 consecutive
+ * nodes, and one persistent grid of co-resident workgroups sweeps all tiles of all instances
+ * every step, with a grid-wide barrier between steps.  The launch is captured once in a
+ * hipGraph and replayed.
+ *
+ * Per-instance arithmetic is exactly that of lbm_step (same device code, same rounding): an
+ * instance of the batch is bit-identical to the same run through lbm_init / lbm_step.
+ * Blow-up: at every step each instance's state is checked for a node with !(rho > 0); the
+ * first such step is recorded and the instance is frozen from the next step on.
+ *
+ * Conventions (grid layout, state, pointers, errors, streams) are those of lbm.h.
+ */
+#ifndef LBM_BATCH_H
+#define LBM_BATCH_H
+
+#include <stddef.h>
+
+#include "lbm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One instance. */
+typedef struct {
+    int nx, ny;                /* grid, each >= 2 */
+    int model;                 /* LBM_BGK .. LBM_RR (not LBM_STREAM_ONLY) */
+    int eq_order;              /* 2, 3 or 4 (4 for CM, CHM, K) */
+    double omega[LBM_NOMEGA];  /* (omega_nu, omega_b, omega_21, omega_12, omega_22) in [0, 2] */
+    double rho0;               /* storage shift for shifted precisions (> 0), ignored in FP64 */
+} lbm_instance_desc;
+
+typedef struct lbm_batch lbm_batch; /* opaque, host-side, owned by the library */
+
+/* Bytes of device memory for the populations of all n instances at precision prec (two
+ * copies, every instance's planes padded to 256 bytes).  0 for invalid arguments. */
+size_t lbm_batch_population_bytes(const lbm_instance_desc* desc, int n, int prec);
+
+/* Create a batch and set every instance to f^eq(rho, u) of its own equilibrium order.
+ *   desc        host, n descriptors (copied)
+ *   prec        LBM_F64 / LBM_F32_SHIFTED / LBM_F16_SHIFTED
+ *   rho,ux,uy   device FP64: the initial fields of all instances concatenated in instance
+ *               order, each instance's block [y][x] (sum of nx*ny values each); read only
+ *   pop_buf     device, caller-owned, >= lbm_batch_population_bytes bytes, 256-byte aligned
+ *   hip_stream  stream for all work of this batch (NULL = default)
+ * Allocates descriptor and tile tables, the barrier counter and the blow-up record
+ * (O(number of tiles) bytes). */
+int lbm_batch_create(lbm_batch** out, const lbm_instance_desc* desc, int n, int prec,
+                     const double* rho, const double* ux, const double* uy, void* pop_buf,
+                     size_t pop_bytes, void* hip_stream);
+
+/* Advance every live instance by nsteps >= 0 steps in one persistent launch (replayed from a
+ * hipGraph captured for this nsteps).  Asynchronous.  A grid barrier that does not complete
+ * within two seconds (co-residency lost) stops the launch; lbm_batch_status then reports
+ * LBM_EHIP. */
+int lbm_batch_run(lbm_batch* b, int nsteps);
+
+/* Step counter and, per instance, the first step whose state had a node with !(rho > 0)
+ * (-1 if none).  blowup_steps: host, n values, or NULL.  Synchronises the stream. */
+int lbm_batch_status(lbm_batch* b, long long* step, long long* blowup_steps);
+
+/* Current state of one instance as unshifted FP64 populations (device, 9*nx*ny, [q][y][x]).
+ * Asynchronous. */
+int lbm_batch_get_state(lbm_batch* b, int instance, double* f);
+
+/* Launch shape of the persistent kernel: nodes per thread per tile (1, 2 or 4) and resident
+ * workgroups per CU (1 .. the occupancy limit; 0 = the limit).  Takes effect at the next
+ * lbm_batch_run. */
+int lbm_batch_set_launch(lbm_batch* b, int nodes_per_thread, int groups_per_cu);
+
+/* Autotune the persistent launch: each candidate (nodes per thread in {1, 2, 4} x groups per
+ * CU in {limit, limit/2}) runs `trials` (>= 1) steps that all recompute the current step from
+ * the same input copy, so states, counters and blow-up records are unchanged.  Keeps and
+ * returns the fastest shape.  Synchronises. */
+int lbm_batch_autotune(lbm_batch* b, int trials, int* nodes_per_thread, int* groups_per_cu,
+                       double* us_per_step);
+
+/* Release the batch (not pop_buf).  NULL is accepted.  Synchronises the stream. */
+void lbm_batch_destroy(lbm_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_BATCH_H */

@@ -1,0 +1,68 @@
+"""Torch-facing wrapper of the batched persistent sweep (include/lbm_batch.h)."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import binding as B
+from .inputs import MODEL_CODES
+
+
+class Batch:
+    """Independent periodic simulations advanced together by one persistent launch.
+
+    instances: list of dicts with nx, ny, model (name or code), eq_order, omega (5 rates),
+    optional rho0; fields: list of (rho, ux, uy) arrays [ny, nx], one per instance."""
+
+    def __init__(self, instances, fields, prec: str = "f64", device="cuda",
+                 stream: torch.cuda.Stream | None = None):
+        self.device = torch.device(device)
+        descs = []
+        for d in instances:
+            m = d["model"]
+            descs.append({**d, "model": MODEL_CODES[m] if isinstance(m, str) else int(m)})
+        self.shapes = [(int(d["nx"]), int(d["ny"])) for d in descs]
+        self.n = len(descs)
+        self.descs = B.make_descs(descs)
+        self.prec = B.PRECISIONS[prec]
+        cat = [np.concatenate([np.asarray(f[k], dtype=np.float64).ravel() for f in fields]) for k in range(3)]
+        dev = [torch.from_numpy(c).to(self.device) for c in cat]
+        nbytes = B.lbm_batch_population_bytes(self.descs, self.prec)
+        if nbytes == 0:
+            raise ValueError("invalid batch description")
+        self.pop = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        self.handle = B.lbm_batch_create(self.descs, self.prec, *(t.data_ptr() for t in dev),
+                                         self.pop.data_ptr(), nbytes, self.stream.cuda_stream)
+        self.stream.synchronize()
+
+    def run(self, nsteps: int):
+        B.lbm_batch_run(self.handle, nsteps)
+
+    def status(self):
+        """(step, [blow-up step per instance, -1 if none])"""
+        return B.lbm_batch_status(self.handle, self.n)
+
+    def state(self, j: int) -> torch.Tensor:
+        nx, ny = self.shapes[j]
+        f = torch.empty((9, ny, nx), dtype=torch.float64, device=self.device)
+        B.lbm_batch_get_state(self.handle, j, f.data_ptr())
+        self.stream.synchronize()
+        return f
+
+    def set_launch(self, nodes_per_thread: int, groups_per_cu: int = 0):
+        B.lbm_batch_set_launch(self.handle, nodes_per_thread, groups_per_cu)
+
+    def autotune(self, trials: int = 5):
+        return B.lbm_batch_autotune(self.handle, trials)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            B.lbm_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

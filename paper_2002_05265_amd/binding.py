@@ -20,11 +20,20 @@ LBM_F64, LBM_F32_SHIFTED, LBM_F16_SHIFTED = 0, 1, 2
 PRECISIONS = {"f64": LBM_F64, "f32": LBM_F32_SHIFTED, "f16": LBM_F16_SHIFTED}
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_EUNSUPPORTED", -3: "LBM_EHIP", -4: "LBM_ESTATE"}
 
-# every symbol declared in include/lbm.h and include/lbm_batch.h / lbm_adjoint.h
+# every symbol declared in include/*.h
 EXPORTS = (
     "lbm_population_bytes", "lbm_init", "lbm_step", "lbm_moments", "lbm_status",
-    "lbm_get_state", "lbm_set_state", "lbm_destroy", "lbm_last_error",
+    "lbm_get_state", "lbm_set_state", "lbm_set_launch", "lbm_autotune", "lbm_destroy",
+    "lbm_last_error",
+    "lbm_batch_population_bytes", "lbm_batch_create", "lbm_batch_run", "lbm_batch_status",
+    "lbm_batch_get_state", "lbm_batch_set_launch", "lbm_batch_autotune", "lbm_batch_destroy",
 )
+
+
+class InstanceDesc(ctypes.Structure):
+    """lbm_instance_desc (include/lbm_batch.h)."""
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("model", ctypes.c_int),
+                ("eq_order", ctypes.c_int), ("omega", ctypes.c_double * 5), ("rho0", ctypes.c_double)]
 
 
 class LbmError(RuntimeError):
@@ -47,8 +56,19 @@ def _declare(L: ctypes.CDLL):
         "lbm_status": (_i, [_vp, ctypes.POINTER(_ll), ctypes.POINTER(_ll)]),
         "lbm_get_state": (_i, [_vp, _vp]),
         "lbm_set_state": (_i, [_vp, _vp, _ll]),
+        "lbm_set_launch": (_i, [_vp, _i, _i, _i]),
+        "lbm_autotune": (_i, [_vp, _i, _dp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), _dp]),
         "lbm_destroy": (None, [_vp]),
         "lbm_last_error": (ctypes.c_char_p, []),
+        "lbm_batch_population_bytes": (_sz, [ctypes.POINTER(InstanceDesc), _i, _i]),
+        "lbm_batch_create": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(InstanceDesc), _i, _i, _vp, _vp,
+                                  _vp, _vp, _sz, _vp]),
+        "lbm_batch_run": (_i, [_vp, _i]),
+        "lbm_batch_status": (_i, [_vp, ctypes.POINTER(_ll), ctypes.POINTER(_ll)]),
+        "lbm_batch_get_state": (_i, [_vp, _i, _vp]),
+        "lbm_batch_set_launch": (_i, [_vp, _i, _i]),
+        "lbm_batch_autotune": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), _dp]),
+        "lbm_batch_destroy": (None, [_vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -125,8 +145,72 @@ def lbm_set_state(ctx: int, f: int, step: int):
     _check(lib().lbm_set_state(ctx, f, step), "lbm_set_state")
 
 
+def lbm_set_launch(ctx: int, model: int, rows: int, xcd: int):
+    _check(lib().lbm_set_launch(ctx, model, rows, xcd), "lbm_set_launch")
+
+
+def lbm_autotune(ctx: int, model: int, omega, trials: int):
+    rows, xcd, us = _i(), _i(), _d()
+    _check(lib().lbm_autotune(ctx, model, _omega(omega), trials, ctypes.byref(rows),
+                              ctypes.byref(xcd), ctypes.byref(us)), "lbm_autotune")
+    return rows.value, xcd.value, us.value
+
+
 def lbm_destroy(ctx: int):
     lib().lbm_destroy(ctx)
+
+
+def make_descs(descs) -> ctypes.Array:
+    """Array of InstanceDesc from dicts with nx, ny, model (code), eq_order, omega, rho0."""
+    arr = (InstanceDesc * len(descs))()
+    for a, d in zip(arr, descs):
+        a.nx, a.ny, a.model, a.eq_order = int(d["nx"]), int(d["ny"]), int(d["model"]), int(d["eq_order"])
+        for k in range(5):
+            a.omega[k] = float(d["omega"][k])
+        a.rho0 = float(d.get("rho0", 1.0))
+    return arr
+
+
+def lbm_batch_population_bytes(descs: ctypes.Array, prec: int) -> int:
+    return int(lib().lbm_batch_population_bytes(descs, len(descs), prec))
+
+
+def lbm_batch_create(descs: ctypes.Array, prec: int, rho: int, ux: int, uy: int, pop_buf: int,
+                     pop_bytes: int, stream: int) -> int:
+    b = _vp()
+    _check(lib().lbm_batch_create(ctypes.byref(b), descs, len(descs), prec, rho, ux, uy, pop_buf,
+                                  pop_bytes, stream or None), "lbm_batch_create")
+    return b.value
+
+
+def lbm_batch_run(b: int, nsteps: int):
+    _check(lib().lbm_batch_run(b, nsteps), "lbm_batch_run")
+
+
+def lbm_batch_status(b: int, n: int):
+    step = _ll()
+    blow = (_ll * n)()
+    _check(lib().lbm_batch_status(b, ctypes.byref(step), blow), "lbm_batch_status")
+    return step.value, list(blow)
+
+
+def lbm_batch_get_state(b: int, instance: int, f: int):
+    _check(lib().lbm_batch_get_state(b, instance, f), "lbm_batch_get_state")
+
+
+def lbm_batch_set_launch(b: int, nodes_per_thread: int, groups_per_cu: int):
+    _check(lib().lbm_batch_set_launch(b, nodes_per_thread, groups_per_cu), "lbm_batch_set_launch")
+
+
+def lbm_batch_autotune(b: int, trials: int):
+    npt, gpc, us = _i(), _i(), _d()
+    _check(lib().lbm_batch_autotune(b, trials, ctypes.byref(npt), ctypes.byref(gpc), ctypes.byref(us)),
+           "lbm_batch_autotune")
+    return npt.value, gpc.value, us.value
+
+
+def lbm_batch_destroy(b: int):
+    lib().lbm_batch_destroy(b)
 
 
 def lbm_last_error() -> str:

@@ -1,0 +1,585 @@
+// Batched stability sweep: many independent D2Q9 runs advanced by one persistent launch.
+//
+// Work decomposition.  Instance j owns `cells_j = nx_j * ny_j` nodes, cut into tiles of
+// 256 * NPT consecutive nodes (linear index y * nx + x).  All tiles of all instances form one
+// list; a persistent grid of G co-resident workgroups takes tiles t = blockIdx.x + k G every
+// step, then all workgroups meet at a grid barrier before the next step reads what this one
+// wrote.  The barrier is a monotonic counter: workgroup arrivals after step s bring it to
+// G (s + 1).  Agent-scope release / acquire fences around it make the populations written on
+// one XCD visible to the others.  Its spin is bounded in wall-clock time, so every wave exits
+// even if co-residency were lost.
+//
+// Each node runs exactly the code of the plain kernel (pull_load / macro_of / collide /
+// store_cell with the same coefficients), so an instance is bit-identical to its plain run.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_batch.h"
+#include "lbm_cell.hpp"
+#include "lbm_internal.hpp"
+
+using namespace lbm;
+
+namespace {
+
+constexpr int kTileThreads = 256;
+
+template <typename R>
+struct BDesc {
+    int nx, ny, model, N;
+    int cells, tile0;       // node count, first tile of this instance (for the current NPT)
+    long long off;          // element offset of the instance inside each copy
+    long long plane;        // elements per population plane of the instance
+    long long foff;         // offset of the instance's initial fields
+    double rho_s;
+    float inv_nx;
+    Coef<R> c;
+};
+
+__device__ __forceinline__ int row_of(int c, int nx, float inv_nx) {
+    int y = (int)((float)c * inv_nx);
+    if (y * nx > c) --y;
+    else if ((y + 1) * nx <= c) ++y;
+    return y;
+}
+
+template <int MODEL, typename R>
+__device__ __forceinline__ void collide_as(R (&h)[9], const Macro<R>& m, const Coef<R>& c, int N) {
+    collide<MODEL>(h, m, c, N);
+}
+
+template <typename R>
+__device__ __forceinline__ void collide_model(int model, R (&h)[9], const Macro<R>& m,
+                                              const Coef<R>& c, int N) {
+    switch (model) {
+        case kBGK: collide_as<kBGK>(h, m, c, N); break;
+        case kRM: collide_as<kRM>(h, m, c, N); break;
+        case kHM: collide_as<kHM>(h, m, c, N); break;
+        case kCM: collide_as<kCM>(h, m, c, N); break;
+        case kCHM: collide_as<kCHM>(h, m, c, N); break;
+        case kK: collide_as<kK>(h, m, c, N); break;
+        case kPR: collide_as<kPR>(h, m, c, N); break;
+        default: collide_as<kRR>(h, m, c, N); break;
+    }
+}
+
+// Grid-wide barrier; returns false if the launch must stop (timeout here or elsewhere).
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned target, int* err,
+                                             long long timeout_ticks) {
+    __shared__ int ok;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const long long t0 = wall_clock64();
+        int good = 1;
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                good = 0;
+                break;
+            }
+            if (wall_clock64() - t0 > timeout_ticks) {
+                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                good = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        ok = good;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return ok != 0;
+}
+
+template <int PREC, int NPT>
+__global__ __launch_bounds__(kTileThreads) void k_batch(
+    typename Store<PREC>::S* __restrict__ base, long long copy_elems,
+    const BDesc<typename Store<PREC>::R>* __restrict__ desc, const int* __restrict__ tile_inst,
+    int ntiles, int* __restrict__ blowup, unsigned* __restrict__ bar, int* __restrict__ err,
+    long long* __restrict__ step_ctr, int nsteps, int advance, long long timeout_ticks) {
+    using S = typename Store<PREC>::S;
+    using R = typename Store<PREC>::R;
+    const long long n0 = *step_ctr;
+    const int G = (int)gridDim.x;
+    const int tid = threadIdx.x;
+    for (int s = 0; s < nsteps; ++s) {
+        const long long n = n0 + (advance ? s : 0);
+        const int sc = (int)(n & 1);
+        const S* src = base + sc * copy_elems;
+        S* dst = base + (sc ^ 1) * copy_elems;
+        for (int t = blockIdx.x; t < ntiles; t += G) {
+            const int j = tile_inst[t];
+            const BDesc<R>& d = desc[j];
+            const int frozen = __hip_atomic_load(blowup + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((long long)frozen < n) continue;  // blew up at an earlier step
+            const int first = (t - d.tile0) * NPT * kTileThreads + tid;
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
+                const int c = first + k * kTileThreads;
+                if (c < d.cells) {
+                    const int y = row_of(c, d.nx, d.inv_nx);
+                    const int x = c - y * d.nx;
+                    const Nbr nb = neighbours(x, y, d.nx, d.ny);
+                    R h[9];
+                    pull_load(src + d.off, d.plane, nb, h);
+                    double rho_d;
+                    const Macro<R> m = macro_of(h, d.rho_s, rho_d);
+                    flag_bad(!(rho_d > 0.0), blowup + j, (int)n);
+                    collide_model(d.model, h, m, d.c, d.N);
+                    store_cell(dst + d.off, d.plane, (unsigned)c, h);
+                }
+            }
+        }
+        if (!grid_barrier(bar, (unsigned)G * (unsigned)(s + 1), err, timeout_ticks)) return;
+    }
+    if (advance && blockIdx.x == 0 && tid == 0) *step_ctr = n0 + nsteps;
+}
+
+// f(., 0) = f^eq of every instance, stored pre-streamed into copy 0.  One block per tile of
+// the NPT = 1 table.
+template <int PREC>
+__global__ __launch_bounds__(kTileThreads) void k_batch_init(
+    typename Store<PREC>::S* __restrict__ base, const BDesc<typename Store<PREC>::R>* __restrict__ desc,
+    const int* __restrict__ tile_inst, const double* __restrict__ rho, const double* __restrict__ ux,
+    const double* __restrict__ uy) {
+    const int j = tile_inst[blockIdx.x];
+    const BDesc<typename Store<PREC>::R>& d = desc[j];
+    const int c = (blockIdx.x - d.tile0) * kTileThreads + threadIdx.x;
+    if (c >= d.cells) return;
+    const int y = row_of(c, d.nx, d.inv_nx);
+    const int x = c - y * d.nx;
+    Macro<double> m;
+    m.rho = rho[d.foff + c];
+    m.ux = ux[d.foff + c];
+    m.uy = uy[d.foff + c];
+    m.drho = m.rho - d.rho_s;
+    m.jx = m.rho * m.ux;
+    m.jy = m.rho * m.uy;
+    const Eq<double> e = hermite_eq(m, d.N);
+    double h[9];
+    hermite_to_pop(m, e.e20, e.e02, e.e11, e.e21, e.e12, e.e22, h);
+    prestream_store(base + d.off, Geom{d.nx, d.ny, d.plane}, x, y, h);
+}
+
+template <int PREC>
+__global__ __launch_bounds__(256) void k_batch_get(const typename Store<PREC>::S* __restrict__ src,
+                                                   Geom g, double rho_s, double* __restrict__ f) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= g.nx || y >= g.ny) return;
+    const Nbr nb = neighbours(x, y, g.nx, g.ny);
+    double h[9];
+    pull_load(src, g.plane, nb, h);
+    const size_t cells = (size_t)g.nx * g.ny, c = nb.r0 + (size_t)x;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i * cells + c] = h[i] + rho_s * rest_weight(i);
+}
+
+// Reset the barrier counter before each replay.  The error flag is sticky (cleared only at
+// creation) so that a stopped launch stays reported.
+__global__ void k_batch_reset(unsigned* __restrict__ bar) {
+    if (threadIdx.x == 0) *bar = 0u;
+}
+
+__global__ void k_clear_i32(int* __restrict__ p) {
+    if (threadIdx.x == 0) *p = 0;
+}
+
+__global__ void k_fill_i32(int* __restrict__ p, int n, int v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+struct lbm_batch {
+    int n = 0, prec = 0;
+    std::vector<lbm_instance_desc> hdesc;
+    std::vector<long long> off, plane, foff;
+    long long copy_elems = 0;
+    char* buf = nullptr;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;      // caller's stream
+    hipStream_t cap = nullptr;         // private stream used only for graph capture
+    int cus = 0, occ[3] = {0, 0, 0};   // CUs, occupancy limit per NPT index
+    int npt = 1, gpc = 0;              // launch shape (gpc 0 = occupancy limit)
+    long long step = 0;                // host mirror of the step counter
+    void* d_desc[3] = {nullptr, nullptr, nullptr};  // descriptors per NPT (tile0 differs)
+    int* d_tiles[3] = {nullptr, nullptr, nullptr};
+    int ntiles[3] = {0, 0, 0};
+    int* d_blowup = nullptr;
+    unsigned* d_bar = nullptr;
+    int* d_err = nullptr;
+    long long* d_step = nullptr;
+    long long timeout_ticks = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int g_nsteps = -1, g_npt = -1, g_G = -1, g_adv = -1;
+};
+
+namespace {
+
+int npt_index(int npt) { return npt == 4 ? 2 : (npt == 2 ? 1 : 0); }
+
+template <int PREC>
+const void* batch_kernel(int npt) {
+    switch (npt) {
+        case 4: return reinterpret_cast<const void*>(&k_batch<PREC, 4>);
+        case 2: return reinterpret_cast<const void*>(&k_batch<PREC, 2>);
+        default: return reinterpret_cast<const void*>(&k_batch<PREC, 1>);
+    }
+}
+
+const void* batch_kernel_p(int prec, int npt) {
+    switch (prec) {
+        case LBM_F64: return batch_kernel<kF64>(npt);
+        case LBM_F32_SHIFTED: return batch_kernel<kF32>(npt);
+        default: return batch_kernel<kF16>(npt);
+    }
+}
+
+template <int PREC, int NPT>
+void launch_batch_t(lbm_batch* b, hipStream_t s, int G, int nsteps, int advance) {
+    using S = typename Store<PREC>::S;
+    using R = typename Store<PREC>::R;
+    const int k = npt_index(NPT);
+    hipLaunchKernelGGL((k_batch<PREC, NPT>), dim3(G), dim3(kTileThreads), 0, s,
+                       reinterpret_cast<S*>(b->buf), b->copy_elems,
+                       reinterpret_cast<const BDesc<R>*>(b->d_desc[k]), b->d_tiles[k], b->ntiles[k],
+                       b->d_blowup, b->d_bar, b->d_err, b->d_step, nsteps, advance, b->timeout_ticks);
+}
+
+template <int PREC>
+void launch_batch_p(lbm_batch* b, hipStream_t s, int G, int nsteps, int advance) {
+    switch (b->npt) {
+        case 4: launch_batch_t<PREC, 4>(b, s, G, nsteps, advance); break;
+        case 2: launch_batch_t<PREC, 2>(b, s, G, nsteps, advance); break;
+        default: launch_batch_t<PREC, 1>(b, s, G, nsteps, advance); break;
+    }
+}
+
+int grid_size(lbm_batch* b) {
+    const int lim = b->occ[npt_index(b->npt)];
+    const int per = (b->gpc <= 0 || b->gpc > lim) ? lim : b->gpc;
+    return b->cus * per;
+}
+
+// Capture (reset kernel + persistent kernel) for this shape once, then replay.
+int run_graph(lbm_batch* b, int nsteps, int advance) {
+    const int G = grid_size(b);
+    if (!(b->exec && b->g_nsteps == nsteps && b->g_npt == b->npt && b->g_G == G && b->g_adv == advance)) {
+        if (b->exec) (void)hipGraphExecDestroy(b->exec);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+        int rc = check_hip(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture");
+        if (rc != LBM_OK) return rc;
+        hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, b->cap, b->d_bar);
+        switch (b->prec) {
+            case LBM_F64: launch_batch_p<kF64>(b, b->cap, G, nsteps, advance); break;
+            case LBM_F32_SHIFTED: launch_batch_p<kF32>(b, b->cap, G, nsteps, advance); break;
+            default: launch_batch_p<kF16>(b, b->cap, G, nsteps, advance); break;
+        }
+        rc = check_hip(hipStreamEndCapture(b->cap, &b->graph), "end capture");
+        if (rc != LBM_OK) return rc;
+        rc = check_hip(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "instantiate graph");
+        if (rc != LBM_OK) return rc;
+        b->g_nsteps = nsteps;
+        b->g_npt = b->npt;
+        b->g_G = G;
+        b->g_adv = advance;
+    }
+    return check_hip(hipGraphLaunch(b->exec, b->stream), "graph launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_batch_population_bytes(const lbm_instance_desc* desc, int n, int prec) {
+    if (!desc || n < 1 || prec < LBM_F64 || prec > LBM_F16_SHIFTED) return 0;
+    long long total = 0;
+    for (int j = 0; j < n; ++j) {
+        if (desc[j].nx < 2 || desc[j].ny < 2 || (long long)desc[j].nx * desc[j].ny >= (1LL << 24)) return 0;
+        total += 9 * plane_elems(desc[j].nx, desc[j].ny, prec);
+    }
+    if (2 * total >= (1LL << 40)) return 0;
+    return (size_t)(2 * total * (long long)elem_size(prec));
+}
+
+int lbm_batch_create(lbm_batch** out, const lbm_instance_desc* desc, int n, int prec,
+                     const double* rho, const double* ux, const double* uy, void* pop_buf,
+                     size_t pop_bytes, void* hip_stream) {
+    if (!out) return set_error(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!desc || n < 1) return set_error(LBM_EINVAL, "need n >= 1 descriptors");
+    if (prec < LBM_F64 || prec > LBM_F16_SHIFTED) return set_error(LBM_EINVAL, "unknown precision %d", prec);
+    for (int j = 0; j < n; ++j) {
+        const lbm_instance_desc& d = desc[j];
+        if (d.nx < 2 || d.ny < 2 || (long long)d.nx * d.ny >= (1LL << 24))
+            return set_error(LBM_EINVAL, "instance %d: grid %d x %d out of range", j, d.nx, d.ny);
+        if (d.model < LBM_BGK || d.model > LBM_RR)
+            return set_error(LBM_EINVAL, "instance %d: model %d not a collision model", j, d.model);
+        if (d.eq_order < 2 || d.eq_order > 4)
+            return set_error(LBM_EINVAL, "instance %d: eq_order %d", j, d.eq_order);
+        int rc = validate_model(d.model, d.eq_order);
+        if (rc == LBM_OK) rc = validate_omega(d.omega);
+        if (rc != LBM_OK) return rc;
+        if (prec != LBM_F64 && !(d.rho0 > 0.0))
+            return set_error(LBM_EINVAL, "instance %d: rho0 must be > 0", j);
+    }
+    if (!rho || !ux || !uy || !pop_buf) return set_error(LBM_EINVAL, "NULL device pointer");
+    if (reinterpret_cast<uintptr_t>(pop_buf) % 256 != 0)
+        return set_error(LBM_EINVAL, "pop_buf must be 256-byte aligned");
+    const size_t need = lbm_batch_population_bytes(desc, n, prec);
+    if (need == 0 || pop_bytes < need)
+        return set_error(LBM_EINVAL, "pop_bytes %zu < required %zu", pop_bytes, need);
+
+    lbm_batch* b = new lbm_batch();
+    b->n = n;
+    b->prec = prec;
+    b->hdesc.assign(desc, desc + n);
+    b->buf = static_cast<char*>(pop_buf);
+    b->bytes = pop_bytes;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    long long o = 0, fo = 0;
+    for (int j = 0; j < n; ++j) {
+        const long long pl = plane_elems(desc[j].nx, desc[j].ny, prec);
+        b->off.push_back(o);
+        b->plane.push_back(pl);
+        b->foff.push_back(fo);
+        o += 9 * pl;
+        fo += (long long)desc[j].nx * desc[j].ny;
+    }
+    b->copy_elems = o;
+
+    int rc = LBM_OK;
+    int dev = 0, clock_khz = 0;
+    rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (rc == LBM_OK) rc = check_hip(hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+    if (rc == LBM_OK) rc = check_hip(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev), "wall clock rate");
+    b->timeout_ticks = 2LL * 1000LL * (long long)(clock_khz > 0 ? clock_khz : 100000);  // 2 s
+    const int npts[3] = {1, 2, 4};
+    for (int k = 0; k < 3 && rc == LBM_OK; ++k) {
+        rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[k], batch_kernel_p(prec, npts[k]),
+                                                                    kTileThreads, 0),
+                       "occupancy");
+        if (rc == LBM_OK && b->occ[k] < 1) rc = set_error(LBM_EHIP, "persistent kernel does not fit a CU");
+        // tile table and descriptors for this NPT
+        const int tile_nodes = kTileThreads * npts[k];
+        std::vector<int> tiles;
+        std::vector<char> dbytes;
+        const size_t dsz = prec == LBM_F64 ? sizeof(BDesc<double>) : sizeof(BDesc<float>);
+        dbytes.resize(dsz * (size_t)n);
+        for (int j = 0; j < n && rc == LBM_OK; ++j) {
+            const lbm_instance_desc& d = desc[j];
+            const int cells = d.nx * d.ny;
+            const int t0 = (int)tiles.size();
+            for (int t = 0; t < (cells + tile_nodes - 1) / tile_nodes; ++t) tiles.push_back(j);
+            if (prec == LBM_F64) {
+                BDesc<double> bd;
+                bd.nx = d.nx; bd.ny = d.ny; bd.model = d.model; bd.N = d.eq_order;
+                bd.cells = cells; bd.tile0 = t0; bd.off = b->off[j]; bd.plane = b->plane[j];
+                bd.foff = b->foff[j]; bd.rho_s = 0.0; bd.inv_nx = 1.0f / (float)d.nx;
+                bd.c = make_coef<double>(d.omega);
+                std::memcpy(dbytes.data() + dsz * j, &bd, dsz);
+            } else {
+                BDesc<float> bd;
+                bd.nx = d.nx; bd.ny = d.ny; bd.model = d.model; bd.N = d.eq_order;
+                bd.cells = cells; bd.tile0 = t0; bd.off = b->off[j]; bd.plane = b->plane[j];
+                bd.foff = b->foff[j]; bd.rho_s = d.rho0; bd.inv_nx = 1.0f / (float)d.nx;
+                bd.c = make_coef<float>(d.omega);
+                std::memcpy(dbytes.data() + dsz * j, &bd, dsz);
+            }
+        }
+        b->ntiles[k] = (int)tiles.size();
+        if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_desc[k], dbytes.size()), "hipMalloc(desc)");
+        if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_tiles[k], sizeof(int) * tiles.size()), "hipMalloc(tiles)");
+        if (rc == LBM_OK)
+            rc = check_hip(hipMemcpy(b->d_desc[k], dbytes.data(), dbytes.size(), hipMemcpyHostToDevice), "copy desc");
+        if (rc == LBM_OK)
+            rc = check_hip(hipMemcpy(b->d_tiles[k], tiles.data(), sizeof(int) * tiles.size(), hipMemcpyHostToDevice),
+                           "copy tiles");
+    }
+    if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_blowup, sizeof(int) * (size_t)n), "hipMalloc(blowup)");
+    if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_bar, sizeof(unsigned)), "hipMalloc(barrier)");
+    if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_err, sizeof(int)), "hipMalloc(err)");
+    if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_step, sizeof(long long)), "hipMalloc(step)");
+    if (rc == LBM_OK) rc = check_hip(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "capture stream");
+    if (rc == LBM_OK) {
+        const long long zero = 0;
+        rc = check_hip(hipMemcpy(b->d_step, &zero, sizeof(zero), hipMemcpyHostToDevice), "reset step");
+    }
+    if (rc == LBM_OK) {
+        hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, b->stream, b->d_blowup, n, INT_MAX);
+        hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, b->stream, b->d_bar);
+        hipLaunchKernelGGL(k_clear_i32, dim3(1), dim3(64), 0, b->stream, b->d_err);
+        switch (prec) {
+            case LBM_F64:
+                hipLaunchKernelGGL(k_batch_init<kF64>, dim3(b->ntiles[0]), dim3(kTileThreads), 0, b->stream,
+                                   reinterpret_cast<double*>(b->buf),
+                                   reinterpret_cast<const BDesc<double>*>(b->d_desc[0]), b->d_tiles[0], rho, ux, uy);
+                break;
+            case LBM_F32_SHIFTED:
+                hipLaunchKernelGGL(k_batch_init<kF32>, dim3(b->ntiles[0]), dim3(kTileThreads), 0, b->stream,
+                                   reinterpret_cast<float*>(b->buf),
+                                   reinterpret_cast<const BDesc<float>*>(b->d_desc[0]), b->d_tiles[0], rho, ux, uy);
+                break;
+            default:
+                hipLaunchKernelGGL(k_batch_init<kF16>, dim3(b->ntiles[0]), dim3(kTileThreads), 0, b->stream,
+                                   reinterpret_cast<_Float16*>(b->buf),
+                                   reinterpret_cast<const BDesc<float>*>(b->d_desc[0]), b->d_tiles[0], rho, ux, uy);
+                break;
+        }
+        rc = check_hip(hipGetLastError(), "batch init launch");
+    }
+    if (rc != LBM_OK) {
+        lbm_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+int lbm_batch_run(lbm_batch* b, int nsteps) {
+    if (!b) return set_error(LBM_ESTATE, "batch is NULL");
+    if (nsteps < 0) return set_error(LBM_EINVAL, "nsteps %d < 0", nsteps);
+    if (b->step + nsteps >= INT_MAX) return set_error(LBM_EINVAL, "step counter would overflow");
+    // keep the barrier counter G * nsteps below 2^32
+    const long long G = grid_size(b);
+    const int chunk = (int)std::min<long long>(nsteps, (1LL << 31) / G);
+    int left = nsteps;
+    while (left > 0) {
+        const int k = std::min(left, chunk);
+        const int rc = run_graph(b, k, 1);
+        if (rc != LBM_OK) return rc;
+        left -= k;
+        b->step += k;
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_status(lbm_batch* b, long long* step, long long* blowup_steps) {
+    if (!b) return set_error(LBM_ESTATE, "batch is NULL");
+    std::vector<int> flags((size_t)b->n);
+    int err = 0;
+    long long dstep = 0;
+    int rc = check_hip(hipStreamSynchronize(b->stream), "synchronise");
+    if (rc == LBM_OK) rc = check_hip(hipMemcpy(&err, b->d_err, sizeof(int), hipMemcpyDeviceToHost), "copy err");
+    if (rc == LBM_OK) rc = check_hip(hipMemcpy(&dstep, b->d_step, sizeof(dstep), hipMemcpyDeviceToHost), "copy step");
+    if (rc == LBM_OK)
+        rc = check_hip(hipMemcpy(flags.data(), b->d_blowup, sizeof(int) * flags.size(), hipMemcpyDeviceToHost),
+                       "copy blow-up steps");
+    if (rc != LBM_OK) return rc;
+    if (err) return set_error(LBM_EHIP, "persistent launch stopped: a grid barrier timed out");
+    if (dstep != b->step) return set_error(LBM_EHIP, "device step counter %lld != %lld", dstep, b->step);
+    if (step) *step = b->step;
+    if (blowup_steps)
+        for (int j = 0; j < b->n; ++j) blowup_steps[j] = flags[j] == INT_MAX ? -1 : (long long)flags[j];
+    return LBM_OK;
+}
+
+int lbm_batch_get_state(lbm_batch* b, int instance, double* f) {
+    if (!b) return set_error(LBM_ESTATE, "batch is NULL");
+    if (instance < 0 || instance >= b->n) return set_error(LBM_EINVAL, "instance %d out of range", instance);
+    if (!f) return set_error(LBM_EINVAL, "f is NULL");
+    const lbm_instance_desc& d = b->hdesc[instance];
+    const Launch l = launch_for(d.nx, d.ny);
+    const Geom g{d.nx, d.ny, b->plane[instance]};
+    const int sc = (int)(b->step & 1);
+    const size_t eoff = (size_t)(sc * b->copy_elems + b->off[instance]);
+    switch (b->prec) {
+        case LBM_F64:
+            hipLaunchKernelGGL(k_batch_get<kF64>, l.grid, l.block, 0, b->stream,
+                               reinterpret_cast<const double*>(b->buf) + eoff, g, 0.0, f);
+            break;
+        case LBM_F32_SHIFTED:
+            hipLaunchKernelGGL(k_batch_get<kF32>, l.grid, l.block, 0, b->stream,
+                               reinterpret_cast<const float*>(b->buf) + eoff, g, d.rho0, f);
+            break;
+        default:
+            hipLaunchKernelGGL(k_batch_get<kF16>, l.grid, l.block, 0, b->stream,
+                               reinterpret_cast<const _Float16*>(b->buf) + eoff, g, d.rho0, f);
+            break;
+    }
+    return check_hip(hipGetLastError(), "batch get_state launch");
+}
+
+int lbm_batch_set_launch(lbm_batch* b, int nodes_per_thread, int groups_per_cu) {
+    if (!b) return set_error(LBM_ESTATE, "batch is NULL");
+    if (nodes_per_thread != 1 && nodes_per_thread != 2 && nodes_per_thread != 4)
+        return set_error(LBM_EINVAL, "nodes_per_thread %d not in {1,2,4}", nodes_per_thread);
+    if (groups_per_cu < 0) return set_error(LBM_EINVAL, "groups_per_cu %d < 0", groups_per_cu);
+    b->npt = nodes_per_thread;
+    b->gpc = groups_per_cu;
+    return LBM_OK;
+}
+
+int lbm_batch_autotune(lbm_batch* b, int trials, int* nodes_per_thread, int* groups_per_cu,
+                       double* us_per_step) {
+    if (!b) return set_error(LBM_ESTATE, "batch is NULL");
+    if (trials < 1) return set_error(LBM_EINVAL, "trials %d < 1", trials);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = check_hip(hipEventCreate(&e0), "hipEventCreate");
+    if (rc == LBM_OK) rc = check_hip(hipEventCreate(&e1), "hipEventCreate");
+    const int npts[3] = {1, 2, 4};
+    const int keep_npt = b->npt, keep_gpc = b->gpc;
+    float best = 0.f;
+    int best_npt = keep_npt, best_gpc = keep_gpc;
+    for (int k = 0; k < 3 && rc == LBM_OK; ++k)
+        for (int half = 0; half < 2 && rc == LBM_OK; ++half) {
+            b->npt = npts[k];
+            const int lim = b->occ[k];
+            b->gpc = half ? std::max(1, lim / 2) : 0;
+            if (half && b->gpc == lim) continue;
+            rc = run_graph(b, 1, 0);  // warm-up (non-advancing)
+            if (rc == LBM_OK) rc = check_hip(hipEventRecord(e0, b->stream), "hipEventRecord");
+            if (rc == LBM_OK) rc = run_graph(b, trials, 0);
+            if (rc == LBM_OK) rc = check_hip(hipEventRecord(e1, b->stream), "hipEventRecord");
+            if (rc == LBM_OK) rc = check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0.f;
+            if (rc == LBM_OK) rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            int err = 0;
+            if (rc == LBM_OK) rc = check_hip(hipMemcpy(&err, b->d_err, sizeof(int), hipMemcpyDeviceToHost), "copy err");
+            if (rc == LBM_OK && err) rc = set_error(LBM_EHIP, "persistent launch stopped: a grid barrier timed out");
+            if (rc == LBM_OK && (best == 0.f || ms < best)) {
+                best = ms;
+                best_npt = b->npt;
+                best_gpc = b->gpc;
+            }
+        }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    b->npt = rc == LBM_OK ? best_npt : keep_npt;
+    b->gpc = rc == LBM_OK ? best_gpc : keep_gpc;
+    if (rc != LBM_OK) return rc;
+    if (nodes_per_thread) *nodes_per_thread = best_npt;
+    if (groups_per_cu) *groups_per_cu = best_gpc == 0 ? b->occ[npt_index(best_npt)] : best_gpc;
+    if (us_per_step) *us_per_step = 1e3 * (double)best / trials;
+    return LBM_OK;
+}
+
+void lbm_batch_destroy(lbm_batch* b) {
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (int k = 0; k < 3; ++k) {
+        if (b->d_desc[k]) (void)hipFree(b->d_desc[k]);
+        if (b->d_tiles[k]) (void)hipFree(b->d_tiles[k]);
+    }
+    if (b->d_blowup) (void)hipFree(b->d_blowup);
+    if (b->d_bar) (void)hipFree(b->d_bar);
+    if (b->d_err) (void)hipFree(b->d_err);
+    if (b->d_step) (void)hipFree(b->d_step);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+}
+
+}  // extern "C"

@@ -53,6 +53,18 @@ Launch launch_for(int nx, int ny) {
     return l;
 }
 
+StepShape step_shape(int nx, int ny, int rows, int xcd) {
+    const Launch l = launch_for(nx, ny);
+    StepShape sh;
+    sh.bw = (int)l.block.x;
+    sh.bh = (int)l.block.y;
+    sh.rows = rows;
+    sh.xcd = xcd;
+    sh.gx = l.grid.x;
+    sh.gy = (unsigned)((ny + sh.bh * rows - 1) / (sh.bh * rows));
+    return sh;
+}
+
 long long plane_elems(int nx, int ny, int prec) {
     const long long align = 256 / elem_size(prec);
     const long long n = (long long)nx * ny;
@@ -89,23 +101,32 @@ namespace {
 // ---------------------------------------------------------------------------------------------
 // kernels
 
-template <int MODEL, int PREC>
+template <int MODEL, int PREC, int ROWS>
 __global__ __launch_bounds__(256) void k_step(const typename Store<PREC>::S* __restrict__ src,
                                               typename Store<PREC>::S* __restrict__ dst, Geom g,
                                               Coef<typename Store<PREC>::R> c, double rho_s,
-                                              int N, int step, int* __restrict__ blowup) {
+                                              int N, int step, int* __restrict__ blowup,
+                                              unsigned gx, unsigned nb, int xcd) {
     using R = typename Store<PREC>::R;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    if (x >= g.nx || y >= g.ny) return;
-    const Nbr nb = neighbours(x, y, g.nx, g.ny);
-    R h[9];
-    pull_load(src, g.plane, nb, h);
-    double rho_d;
-    const Macro<R> m = macro_of(h, rho_s, rho_d);
-    flag_bad(!(rho_d > 0.0), blowup, step);
-    collide<MODEL>(h, m, c, N);
-    store_cell(dst, g.plane, nb.r0 + (unsigned)x, h);
+    unsigned bx, by;
+    tile_of_block(blockIdx.x, gx, nb, xcd, bx, by);
+    const int x = bx * blockDim.x + threadIdx.x;
+    const int y0 = by * blockDim.y * ROWS + threadIdx.y;
+    if (x >= g.nx) return;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int y = y0 + r * (int)blockDim.y;
+        if (y < g.ny) {
+            const Nbr nb4 = neighbours(x, y, g.nx, g.ny);
+            R h[9];
+            pull_load(src, g.plane, nb4, h);
+            double rho_d;
+            const Macro<R> m = macro_of(h, rho_s, rho_d);
+            flag_bad(!(rho_d > 0.0), blowup, step);
+            collide<MODEL>(h, m, c, N);
+            store_cell(dst, g.plane, nb4.r0 + (unsigned)x, h);
+        }
+    }
 }
 
 // Macroscopic fields of the state f(., n) (pulled from the post-collision copy) and per-block
@@ -204,29 +225,41 @@ __global__ __launch_bounds__(256) void k_init_eq(typename Store<PREC>::S* __rest
 // ---------------------------------------------------------------------------------------------
 // host side
 
-template <int MODEL, int PREC>
-void launch_step_t(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c) {
+template <int MODEL, int PREC, int ROWS>
+void launch_step_r(lbm_ctx* ctx, const StepShape& sh, const Coef<typename Store<PREC>::R>& c,
+                   int src_copy) {
     using S = typename Store<PREC>::S;
-    const Launch l = launch_for(ctx->nx, ctx->ny);
-    const S* src = reinterpret_cast<const S*>(ctx->copy(ctx->cur));
-    S* dst = reinterpret_cast<S*>(ctx->copy(ctx->cur ^ 1));
-    hipLaunchKernelGGL((k_step<MODEL, PREC>), l.grid, l.block, 0, ctx->stream, src, dst,
-                       ctx->geom(), c, ctx->rho_s, ctx->eq_order, (int)ctx->step, ctx->d_flag);
+    const S* src = reinterpret_cast<const S*>(ctx->copy(src_copy));
+    S* dst = reinterpret_cast<S*>(ctx->copy(src_copy ^ 1));
+    const unsigned nb = sh.gx * sh.gy;
+    hipLaunchKernelGGL((k_step<MODEL, PREC, ROWS>), dim3(nb), dim3(sh.bw, sh.bh), 0, ctx->stream,
+                       src, dst, ctx->geom(), c, ctx->rho_s, ctx->eq_order, (int)ctx->step,
+                       ctx->d_flag, sh.gx, nb, sh.xcd);
+}
+
+template <int MODEL, int PREC>
+void launch_step_t(lbm_ctx* ctx, const StepShape& sh, const Coef<typename Store<PREC>::R>& c,
+                   int src_copy) {
+    switch (sh.rows) {
+        case 4: launch_step_r<MODEL, PREC, 4>(ctx, sh, c, src_copy); break;
+        case 2: launch_step_r<MODEL, PREC, 2>(ctx, sh, c, src_copy); break;
+        default: launch_step_r<MODEL, PREC, 1>(ctx, sh, c, src_copy); break;
+    }
 }
 
 template <int PREC>
-void launch_step_p(lbm_ctx* ctx, int model, const double* w) {
+void launch_step_p(lbm_ctx* ctx, int model, const double* w, const StepShape& sh, int src_copy) {
     const Coef<typename Store<PREC>::R> c = make_coef<typename Store<PREC>::R>(w);
     switch (model) {
-        case LBM_BGK: launch_step_t<kBGK, PREC>(ctx, c); break;
-        case LBM_RM: launch_step_t<kRM, PREC>(ctx, c); break;
-        case LBM_HM: launch_step_t<kHM, PREC>(ctx, c); break;
-        case LBM_CM: launch_step_t<kCM, PREC>(ctx, c); break;
-        case LBM_CHM: launch_step_t<kCHM, PREC>(ctx, c); break;
-        case LBM_K: launch_step_t<kK, PREC>(ctx, c); break;
-        case LBM_PR: launch_step_t<kPR, PREC>(ctx, c); break;
-        case LBM_RR: launch_step_t<kRR, PREC>(ctx, c); break;
-        default: launch_step_t<kStreamOnly, PREC>(ctx, c); break;
+        case LBM_BGK: launch_step_t<kBGK, PREC>(ctx, sh, c, src_copy); break;
+        case LBM_RM: launch_step_t<kRM, PREC>(ctx, sh, c, src_copy); break;
+        case LBM_HM: launch_step_t<kHM, PREC>(ctx, sh, c, src_copy); break;
+        case LBM_CM: launch_step_t<kCM, PREC>(ctx, sh, c, src_copy); break;
+        case LBM_CHM: launch_step_t<kCHM, PREC>(ctx, sh, c, src_copy); break;
+        case LBM_K: launch_step_t<kK, PREC>(ctx, sh, c, src_copy); break;
+        case LBM_PR: launch_step_t<kPR, PREC>(ctx, sh, c, src_copy); break;
+        case LBM_RR: launch_step_t<kRR, PREC>(ctx, sh, c, src_copy); break;
+        default: launch_step_t<kStreamOnly, PREC>(ctx, sh, c, src_copy); break;
     }
 }
 
@@ -330,6 +363,9 @@ int lbm_init(lbm_ctx** out, int nx, int ny, int prec, int eq_order, double rho0,
     ctx->stream = static_cast<hipStream_t>(hip_stream);
     const Launch l = launch_for(nx, ny);
     ctx->nblocks = (int)(l.grid.x * l.grid.y);
+    // FP16 rows are 128 bytes per wave and plane: four nodes per thread keep enough bytes in
+    // flight (measured on MI355X; lbm_autotune can revise it)
+    for (int k = 0; k < 9; ++k) ctx->rows[k] = prec == LBM_F16_SHIFTED ? 4 : 1;
     int rc = check_hip(hipGetDevice(&ctx->device), "hipGetDevice");
     if (rc == LBM_OK) rc = check_hip(hipMalloc(&ctx->d_flag, sizeof(int)), "hipMalloc(flag)");
     if (rc == LBM_OK)
@@ -356,8 +392,9 @@ int lbm_step(lbm_ctx* ctx, int model, const double* omega, int nsteps) {
     rc = validate_omega(omega);
     if (rc != LBM_OK) return rc;
     if (ctx->step + nsteps >= INT_MAX) return set_error(LBM_EINVAL, "step counter would overflow");
+    const StepShape sh = ctx->shape_of(model);
     for (int s = 0; s < nsteps; ++s) {
-        LBM_DISPATCH_PREC(ctx->prec, launch_step_p, ctx, model, omega);
+        LBM_DISPATCH_PREC(ctx->prec, launch_step_p, ctx, model, omega, sh, ctx->cur);
         ctx->cur ^= 1;
         ctx->step += 1;
     }
@@ -412,6 +449,60 @@ int lbm_set_state(lbm_ctx* ctx, const double* f, long long step) {
     if (rc != LBM_OK) return rc;
     ctx->step = step;
     return reset_flag(ctx);
+}
+
+int lbm_set_launch(lbm_ctx* ctx, int model, int rows, int xcd) {
+    if (!ctx) return set_error(LBM_ESTATE, "context is NULL");
+    int rc = validate_model(model, 4);
+    if (rc != LBM_OK) return rc;
+    if (rows != 1 && rows != 2 && rows != 4) return set_error(LBM_EINVAL, "rows %d not in {1,2,4}", rows);
+    if (xcd != 0 && xcd != 1) return set_error(LBM_EINVAL, "xcd %d not in {0,1}", xcd);
+    ctx->rows[lbm_ctx::slot(model)] = rows;
+    ctx->xcd[lbm_ctx::slot(model)] = xcd;
+    return LBM_OK;
+}
+
+int lbm_autotune(lbm_ctx* ctx, int model, const double* omega, int trials, int* rows_out,
+                 int* xcd_out, double* us_per_step) {
+    if (!ctx) return set_error(LBM_ESTATE, "context is NULL");
+    if (trials < 1) return set_error(LBM_EINVAL, "trials %d < 1", trials);
+    int rc = validate_model(model, ctx->eq_order);
+    if (rc == LBM_OK) rc = validate_omega(omega);
+    if (rc != LBM_OK) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    rc = check_hip(hipEventCreate(&e0), "hipEventCreate");
+    if (rc == LBM_OK) rc = check_hip(hipEventCreate(&e1), "hipEventCreate");
+    const int rows_c[3] = {1, 2, 4};
+    float best = 0.f;
+    int best_rows = ctx->rows[lbm_ctx::slot(model)], best_xcd = ctx->xcd[lbm_ctx::slot(model)];
+    for (int ri = 0; ri < 3 && rc == LBM_OK; ++ri)
+        for (int xi = 0; xi < 2 && rc == LBM_OK; ++xi) {
+            const StepShape sh = step_shape(ctx->nx, ctx->ny, rows_c[ri], xi);
+            // one untimed launch, then `trials` timed ones, all from copy `cur`
+            LBM_DISPATCH_PREC(ctx->prec, launch_step_p, ctx, model, omega, sh, ctx->cur);
+            rc = check_hip(hipEventRecord(e0, ctx->stream), "hipEventRecord");
+            for (int t = 0; t < trials && rc == LBM_OK; ++t)
+                LBM_DISPATCH_PREC(ctx->prec, launch_step_p, ctx, model, omega, sh, ctx->cur);
+            if (rc == LBM_OK) rc = check_hip(hipGetLastError(), "autotune launch");
+            if (rc == LBM_OK) rc = check_hip(hipEventRecord(e1, ctx->stream), "hipEventRecord");
+            if (rc == LBM_OK) rc = check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0.f;
+            if (rc == LBM_OK) rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            if (rc == LBM_OK && (best == 0.f || ms < best)) {
+                best = ms;
+                best_rows = rows_c[ri];
+                best_xcd = xi;
+            }
+        }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (rc != LBM_OK) return rc;
+    ctx->rows[lbm_ctx::slot(model)] = best_rows;
+    ctx->xcd[lbm_ctx::slot(model)] = best_xcd;
+    if (rows_out) *rows_out = best_rows;
+    if (xcd_out) *xcd_out = best_xcd;
+    if (us_per_step) *us_per_step = 1e3 * (double)best / trials;
+    return LBM_OK;
 }
 
 void lbm_destroy(lbm_ctx* ctx) {

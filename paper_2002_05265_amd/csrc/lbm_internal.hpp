@@ -11,6 +11,13 @@
 #include "lbm.h"
 #include "lbm_cell.hpp"
 
+#ifndef LBM_DEFAULT_ROWS
+#define LBM_DEFAULT_ROWS 1
+#endif
+#ifndef LBM_DEFAULT_XCD
+#define LBM_DEFAULT_XCD 0
+#endif
+
 namespace lbm {
 
 // Storage type S and arithmetic type R of each precision.
@@ -28,6 +35,13 @@ struct Geom {
 
 struct Launch {
     dim3 grid, block;
+};
+
+// Launch shape of the step kernels: bw x bh threads, each thread `rows` nodes along y, gx x gy
+// tiles launched as a 1D grid (optionally renumbered per XCD).
+struct StepShape {
+    int bw, bh, rows, xcd;
+    unsigned gx, gy;
 };
 
 // Row offsets of rows y, y-1, y+1 and columns x, x-1, x+1 with periodic wrap.
@@ -49,26 +63,81 @@ __device__ __forceinline__ Nbr neighbours(int x, int y, int nx, int ny) {
     return n;
 }
 
+// Streaming loads / stores of population data.  Every population is read once and written
+// once per step, so the non-temporal variants keep it from displacing reusable lines.
+#ifndef LBM_NT_LOADS
+#define LBM_NT_LOADS 0
+#endif
+#ifndef LBM_NT_STORES
+#define LBM_NT_STORES 1
+#endif
+
+template <typename S>
+__device__ __forceinline__ S ld(const S* p) {
+#if LBM_NT_LOADS
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+
+template <typename S>
+__device__ __forceinline__ void st(S* p, S v) {
+#if LBM_NT_STORES
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
 // Gather f_i(x) = stored_i(x - xi_i).
 template <typename S, typename R>
 __device__ __forceinline__ void pull_load(const S* __restrict__ src, long long plane, const Nbr& n,
                                           R (&h)[9]) {
-    h[0] = R(src[0 * plane + n.r0 + n.x]);
-    h[1] = R(src[1 * plane + n.r0 + n.xm]);
-    h[2] = R(src[2 * plane + n.rm + n.x]);
-    h[3] = R(src[3 * plane + n.r0 + n.xp]);
-    h[4] = R(src[4 * plane + n.rp + n.x]);
-    h[5] = R(src[5 * plane + n.rm + n.xm]);
-    h[6] = R(src[6 * plane + n.rm + n.xp]);
-    h[7] = R(src[7 * plane + n.rp + n.xp]);
-    h[8] = R(src[8 * plane + n.rp + n.xm]);
+    h[0] = R(ld(src + 0 * plane + n.r0 + n.x));
+    h[1] = R(ld(src + 1 * plane + n.r0 + n.xm));
+    h[2] = R(ld(src + 2 * plane + n.rm + n.x));
+    h[3] = R(ld(src + 3 * plane + n.r0 + n.xp));
+    h[4] = R(ld(src + 4 * plane + n.rp + n.x));
+    h[5] = R(ld(src + 5 * plane + n.rm + n.xm));
+    h[6] = R(ld(src + 6 * plane + n.rm + n.xp));
+    h[7] = R(ld(src + 7 * plane + n.rp + n.xp));
+    h[8] = R(ld(src + 8 * plane + n.rp + n.xm));
+}
+
+// Conversion to the storage type.  For FP16 the value is first materialised as an FP32
+// register (an empty asm with a register constraint): otherwise the compiler may fuse the last
+// FMA with the rounding to half in one kernel and not in another, and the batched, plain and
+// adjoint kernels would round differently.
+template <typename S, typename R>
+__device__ __forceinline__ S to_store(R v) {
+    if constexpr (std::is_same<S, _Float16>::value) {
+        float f = (float)v;
+        asm volatile("" : "+v"(f));
+        return (S)f;
+    } else {
+        return (S)v;
+    }
 }
 
 template <typename S, typename R>
 __device__ __forceinline__ void store_cell(S* __restrict__ dst, long long plane, unsigned c,
                                            const R (&h)[9]) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) dst[i * plane + c] = S(h[i]);
+    for (int i = 0; i < 9; ++i) st(dst + i * plane + c, to_store<S>(h[i]));
+}
+
+// Tile of a 1D-launched block.  The hardware hands consecutive block ids to the eight XCDs in
+// turn; with `xcd` set, the ids are renumbered so that each XCD owns one contiguous band of
+// tiles (neighbouring tiles then share their edge cache lines in the same L2).
+__device__ __forceinline__ void tile_of_block(unsigned b, unsigned gx, unsigned nb, int xcd,
+                                              unsigned& bx, unsigned& by) {
+    if (xcd) {
+        const unsigned per = nb >> 3, rem = nb & 7u, k = b & 7u, j = b >> 3;
+        b = k * per + (k < rem ? k : rem) + j;
+    }
+    by = b / gx;
+    bx = b - by * gx;
 }
 
 // Store value i of node (x, y) where the next pull of node (x, y) reads it, i.e. at node
@@ -81,7 +150,7 @@ __device__ __forceinline__ void prestream_store(S* __restrict__ dst, const Geom&
         int xd = x - cx(i), yd = y - cy(i);
         xd = xd < 0 ? g.nx - 1 : (xd >= g.nx ? 0 : xd);
         yd = yd < 0 ? g.ny - 1 : (yd >= g.ny ? 0 : yd);
-        dst[i * g.plane + (long long)yd * g.nx + xd] = S(h[i]);
+        dst[i * g.plane + (long long)yd * g.nx + xd] = to_store<S>(h[i]);
     }
 }
 
@@ -144,6 +213,7 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* __restrict__ o
 int set_error(int code, const char* fmt, ...);
 int check_hip(hipError_t e, const char* what);
 Launch launch_for(int nx, int ny);
+StepShape step_shape(int nx, int ny, int rows, int xcd);
 long long plane_elems(int nx, int ny, int prec);
 int validate_omega(const double* w);
 int validate_model(int model, int eq_order);
@@ -166,6 +236,17 @@ struct lbm_ctx {
     double* d_part = nullptr;     // per-block partial sums, 5 per block
     double* d_tot = nullptr;      // 5 totals
 
+    int rows[9] = {LBM_DEFAULT_ROWS, LBM_DEFAULT_ROWS, LBM_DEFAULT_ROWS, LBM_DEFAULT_ROWS,
+                   LBM_DEFAULT_ROWS, LBM_DEFAULT_ROWS, LBM_DEFAULT_ROWS, LBM_DEFAULT_ROWS,
+                   LBM_DEFAULT_ROWS};   // nodes per thread along y, per model (index 8: stream)
+    int xcd[9] = {LBM_DEFAULT_XCD, LBM_DEFAULT_XCD, LBM_DEFAULT_XCD, LBM_DEFAULT_XCD,
+                  LBM_DEFAULT_XCD, LBM_DEFAULT_XCD, LBM_DEFAULT_XCD, LBM_DEFAULT_XCD,
+                  LBM_DEFAULT_XCD};     // XCD-banded tile order, per model
+
+    static int slot(int model) { return (model >= 0 && model < 8) ? model : 8; }
+    lbm::StepShape shape_of(int model) const {
+        return lbm::step_shape(nx, ny, rows[slot(model)], xcd[slot(model)]);
+    }
     char* copy(int c) const { return buf + (size_t)c * 9 * (size_t)plane * esize; }
     lbm::Geom geom() const { return lbm::Geom{nx, ny, plane}; }
 };

@@ -46,6 +46,14 @@ class Sim:
     def step(self, model, omega, nsteps: int = 1):
         B.lbm_step(self.ctx, _model_code(model), omega, nsteps)
 
+    def set_launch(self, model, rows: int, xcd: int):
+        B.lbm_set_launch(self.ctx, _model_code(model), rows, xcd)
+
+    def autotune(self, model, omega, trials: int = 10):
+        """Pick the fastest launch shape for `model` (state unchanged); returns
+        (rows, xcd, microseconds per step)."""
+        return B.lbm_autotune(self.ctx, _model_code(model), omega, trials)
+
     def moments(self):
         """(rho, ux, uy) FP64 device tensors [ny, nx] and the totals list
         [mass, px, py, kinetic energy, mean |u|^2, step]."""

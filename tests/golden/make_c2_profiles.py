@@ -3,7 +3,8 @@ vortex (Ma = 0.2, beta = 0.15, R = 0.1 L, nu = 1e-6, REG rates, extended equilib
 1000 for the eight collision models.
 
 Profiles: rho - 1 and uy along the row j = L/2, and ux along the column through the
-analytically advected centre x = round(L/2 + u0 n) mod L.  Calls only the oracle and the input
+analytically advected centre x = round(L/2 + u0 n) mod L.  Also stored per model: the first
+step whose state has a node with !(rho > 0) (-1 if none up to step 1000).  Calls only the oracle and the input
 generators.  Runs the eight models in parallel processes (about 10 minutes on 8 cores).
 
     python tests/golden/make_c2_profiles.py
@@ -29,23 +30,35 @@ def column(nsteps=STEPS):
     return int(round(L / 2 + MACH * inputs.CS * nsteps)) % L
 
 
+def bad(f):
+    rho = f.sum(axis=0)
+    return not bool(np.all(rho > 0.0))
+
+
 def run(name):
     t = time.time()
     rho, ux, uy = inputs.vortex_fields(L, L, MACH, beta=0.15, radius_frac=0.1)
     f = oracle.init_eq(4, rho, ux, uy)
-    f = oracle.step(f, oracle.MODELS[name], 4, inputs.rates(NU, "REG"), STEPS)
+    blowup = -1  # first step n in [0, STEPS] whose state has a node with !(rho > 0)
+    for n in range(STEPS):
+        if blowup < 0 and bad(f):
+            blowup = n
+        f = oracle.step(f, oracle.MODELS[name], 4, inputs.rates(NU, "REG"), 1)
+    if blowup < 0 and bad(f):
+        blowup = STEPS
     r, u, v, tot = oracle.moments(f)
     c = column()
-    print(f"{name}: {time.time() - t:.0f} s", flush=True)
-    return name, np.stack([r[L // 2, :] - 1.0, v[L // 2, :], u[:, c]]), tot
+    print(f"{name}: {time.time() - t:.0f} s, blow-up step {blowup}", flush=True)
+    return name, np.stack([r[L // 2, :] - 1.0, v[L // 2, :], u[:, c]]), tot, blowup
 
 
 if __name__ == "__main__":
     oracle.build()
     with mp.Pool(8) as pool:
         res = pool.map(run, list(oracle.MODELS))
-    data = {f"{n}_profiles": p for n, p, _ in res}
-    data.update({f"{n}_totals": t for n, _, t in res})
+    data = {f"{n}_profiles": p for n, p, _, _ in res}
+    data.update({f"{n}_totals": t for n, _, t, _ in res})
+    data.update({f"{n}_blowup": np.array(b) for n, _, _, b in res})
     data["column"] = np.array(column())
     np.savez_compressed(OUT, **data)
     print("wrote", OUT)

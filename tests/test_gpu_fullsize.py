@@ -1,0 +1,68 @@
+"""Parity at the benchmark's full size and launch configuration (4096 x 4096 double shear
+layer, the same Sim / lbm_step path bench.py times), on sampled nodes.
+
+After k steps a node depends only on nodes within distance k (one lattice link per step), so
+the oracle recomputes a sampled node exactly from a (2k + 3)^2 patch of the analytic initial
+fields: the patch is run periodically and its wrap-around errors cannot reach the centre in k
+steps.  Samples include the four corners and edge nodes so the periodic wrap of the full grid
+is covered.  Global invariants (mass and momentum) are checked over the whole grid.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2002_05265_amd import inputs
+from paper_2002_05265_amd.sim import Sim
+
+pytestmark = pytest.mark.gpu
+
+N = 4096
+STEPS = 3
+
+
+def sample_nodes(rng, n, count=48):
+    pts = [(0, 0), (0, n - 1), (n - 1, 0), (n - 1, n - 1), (0, n // 2), (n // 2, 0),
+           (n - 1, n // 3), (n // 3, n - 1), (n // 4, n // 4 + 1)]
+    pts += [(int(a), int(b)) for a, b in rng.integers(0, n, size=(count, 2))]
+    return pts
+
+
+def patch_reference(fields, y, x, model, omega, steps):
+    rho, ux, uy = fields
+    r = steps + 1
+    ys = (np.arange(y - r, y + r + 1)) % rho.shape[0]
+    xs = (np.arange(x - r, x + r + 1)) % rho.shape[1]
+    sub = [a[np.ix_(ys, xs)] for a in (rho, ux, uy)]
+    f = oracle.init_eq(4, *sub)
+    f = oracle.step(f, inputs.MODEL_CODES[model], 4, omega, steps)
+    return f[:, r, r]
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("f64", 1e-12)])
+def test_fullsize_sampled(gpu, prec, tol):
+    fields = inputs.dsl_fields(N, N, 0.1)
+    omega = inputs.rates(inputs.dsl_nu(N), "REG")
+    rng = np.random.default_rng(4096)
+    nodes = sample_nodes(rng, N)
+    iy = torch.tensor([p[0] for p in nodes], device=gpu)
+    ix = torch.tensor([p[1] for p in nodes], device=gpu)
+    for model in inputs.MODEL_NAMES:
+        print(f"full size {prec} {model}", flush=True)
+        sim = Sim(*fields, prec=prec, eq_order=4, device=gpu)
+        t0 = sim.totals()
+        sim.step(model, omega, STEPS)
+        state = sim.state()
+        got = state[:, iy, ix].cpu().numpy()
+        del state
+        t1 = sim.totals()
+        sim.close()
+        torch.cuda.empty_cache()
+        ref = np.stack([patch_reference(fields, y, x, model, omega, STEPS) for y, x in nodes], axis=1)
+        err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        assert err < tol, (model, prec, err)
+        # mass and momentum are conserved over the whole grid
+        mass_tol = 1e-13 if prec == "f64" else 1e-7
+        assert abs(t1[0] - t0[0]) < mass_tol * t0[0], (t0[0], t1[0])
+        assert abs(t1[1] - t0[1]) < mass_tol * t0[0] and abs(t1[2] - t0[2]) < mass_tol * t0[0]
+        assert t1[5] == STEPS
