@@ -51,7 +51,8 @@ enum {
 /* Storage precision of the populations. */
 enum {
     LBM_F64 = 0,         /* f_i stored in FP64, FP64 arithmetic                               */
-    LBM_F32_SHIFTED = 1, /* h_i = f_i - w_i rho0 stored in FP32, FP32 arithmetic, FP64 rho     */
+    LBM_F32_SHIFTED = 1, /* h_i = f_i - w_i rho0 stored in FP32 (or - f^eq(rho0, U), see
+                            lbm_init_shifted), FP32 arithmetic, FP64 rho                         */
     LBM_F16_SHIFTED = 2  /* h_i stored in FP16, FP32 arithmetic, FP64 rho                      */
 };
 
@@ -90,6 +91,16 @@ size_t lbm_population_bytes(int nx, int ny, int prec);
 int lbm_init(lbm_ctx** out, int nx, int ny, int prec, int eq_order, double rho0,
              const double* rho, const double* ux, const double* uy, void* pop_buf,
              size_t pop_bytes, void* hip_stream);
+
+/* As lbm_init, with the shifted precisions storing h_i = f_i - f^eq_N(rho0, U)_i for a
+ * reference velocity U = (ux0, uy0) (|U| < 1) instead of the rest state: for a flow with a
+ * mean velocity, U = that mean keeps the stored deviations, and so the FP32 / FP16 rounding,
+ * several times smaller.  rho0 and U are rounded to FP32 once; every kernel and the FP64
+ * state exchange use the rounded values.  LBM_F64 ignores rho0 and U (unshifted storage).
+ * lbm_init(...) is lbm_init_shifted(..., rho0, 0, 0, ...). */
+int lbm_init_shifted(lbm_ctx** out, int nx, int ny, int prec, int eq_order, double rho0,
+                     double ux0, double uy0, const double* rho, const double* ux,
+                     const double* uy, void* pop_buf, size_t pop_bytes, void* hip_stream);
 
 /* Advance nsteps >= 0 steps of stream-and-collide with the given model (eq. StreamCollide).
  *   omega  host, LBM_NOMEGA doubles in [0, 2]: (omega_nu, omega_b, omega_21, omega_12,

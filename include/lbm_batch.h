@@ -33,7 +33,9 @@ typedef struct {
     int model;                 /* LBM_BGK .. LBM_RR (not LBM_STREAM_ONLY) */
     int eq_order;              /* 2, 3 or 4 (4 for CM, CHM, K) */
     double omega[LBM_NOMEGA];  /* (omega_nu, omega_b, omega_21, omega_12, omega_22) in [0, 2] */
-    double rho0;               /* storage shift for shifted precisions (> 0), ignored in FP64 */
+    double rho0;               /* shifted precisions store f - f^eq_N(rho0, U) (rho0 > 0)    */
+    double ux0, uy0;           /* reference velocity U (|U| < 1; 0 = rest), see               */
+                               /* lbm_init_shifted; both ignored in FP64                      */
 } lbm_instance_desc;
 
 typedef struct lbm_batch lbm_batch; /* opaque, host-side, owned by the library */

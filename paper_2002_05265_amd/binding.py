@@ -22,7 +22,7 @@ STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_EUNSUPPORTED", -3: "LBM_EHIP",
 
 # every symbol declared in include/*.h
 EXPORTS = (
-    "lbm_population_bytes", "lbm_init", "lbm_step", "lbm_moments", "lbm_status",
+    "lbm_population_bytes", "lbm_init", "lbm_init_shifted", "lbm_step", "lbm_moments", "lbm_status",
     "lbm_get_state", "lbm_set_state", "lbm_set_launch", "lbm_autotune", "lbm_destroy",
     "lbm_last_error",
     "lbm_batch_population_bytes", "lbm_batch_create", "lbm_batch_run", "lbm_batch_status",
@@ -33,7 +33,8 @@ EXPORTS = (
 class InstanceDesc(ctypes.Structure):
     """lbm_instance_desc (include/lbm_batch.h)."""
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("model", ctypes.c_int),
-                ("eq_order", ctypes.c_int), ("omega", ctypes.c_double * 5), ("rho0", ctypes.c_double)]
+                ("eq_order", ctypes.c_int), ("omega", ctypes.c_double * 5), ("rho0", ctypes.c_double),
+                ("ux0", ctypes.c_double), ("uy0", ctypes.c_double)]
 
 
 class LbmError(RuntimeError):
@@ -51,6 +52,8 @@ def _declare(L: ctypes.CDLL):
     sig = {
         "lbm_population_bytes": (_sz, [_i, _i, _i]),
         "lbm_init": (_i, [ctypes.POINTER(_vp), _i, _i, _i, _i, _d, _vp, _vp, _vp, _vp, _sz, _vp]),
+        "lbm_init_shifted": (_i, [ctypes.POINTER(_vp), _i, _i, _i, _i, _d, _d, _d, _vp, _vp, _vp, _vp,
+                                  _sz, _vp]),
         "lbm_step": (_i, [_vp, _i, _dp, _i]),
         "lbm_moments": (_i, [_vp, _vp, _vp, _vp, _dp]),
         "lbm_status": (_i, [_vp, ctypes.POINTER(_ll), ctypes.POINTER(_ll)]),
@@ -121,6 +124,14 @@ def lbm_init(nx: int, ny: int, prec: int, eq_order: int, rho0: float, rho: int, 
     return ctx.value
 
 
+def lbm_init_shifted(nx: int, ny: int, prec: int, eq_order: int, rho0: float, ux0: float, uy0: float,
+                     rho: int, ux: int, uy: int, pop_buf: int, pop_bytes: int, stream: int) -> int:
+    ctx = _vp()
+    _check(lib().lbm_init_shifted(ctypes.byref(ctx), nx, ny, prec, eq_order, rho0, ux0, uy0, rho, ux,
+                                  uy, pop_buf, pop_bytes, stream or None), "lbm_init_shifted")
+    return ctx.value
+
+
 def lbm_step(ctx: int, model: int, omega, nsteps: int):
     _check(lib().lbm_step(ctx, model, _omega(omega), nsteps), "lbm_step")
 
@@ -168,6 +179,8 @@ def make_descs(descs) -> ctypes.Array:
         for k in range(5):
             a.omega[k] = float(d["omega"][k])
         a.rho0 = float(d.get("rho0", 1.0))
+        a.ux0 = float(d.get("ux0", 0.0))
+        a.uy0 = float(d.get("uy0", 0.0))
     return arr
 
 

@@ -36,8 +36,9 @@ struct BDesc {
     long long off;          // element offset of the instance inside each copy
     long long plane;        // elements per population plane of the instance
     long long foff;         // offset of the instance's initial fields
-    double rho_s;
     float inv_nx;
+    Ref<R> ref;             // storage reference (rho_s, U) in the arithmetic type
+    Ref<double> ref_d;      // the same values in FP64 (initialisation)
     Coef<R> c;
 };
 
@@ -48,23 +49,18 @@ __device__ __forceinline__ int row_of(int c, int nx, float inv_nx) {
     return y;
 }
 
-template <int MODEL, typename R>
-__device__ __forceinline__ void collide_as(R (&h)[9], const Macro<R>& m, const Coef<R>& c, int N) {
-    collide<MODEL>(h, m, c, N);
-}
-
 template <typename R>
 __device__ __forceinline__ void collide_model(int model, R (&h)[9], const Macro<R>& m,
-                                              const Coef<R>& c, int N) {
+                                              const Ref<R>& r, const Coef<R>& c, int N) {
     switch (model) {
-        case kBGK: collide_as<kBGK>(h, m, c, N); break;
-        case kRM: collide_as<kRM>(h, m, c, N); break;
-        case kHM: collide_as<kHM>(h, m, c, N); break;
-        case kCM: collide_as<kCM>(h, m, c, N); break;
-        case kCHM: collide_as<kCHM>(h, m, c, N); break;
-        case kK: collide_as<kK>(h, m, c, N); break;
-        case kPR: collide_as<kPR>(h, m, c, N); break;
-        default: collide_as<kRR>(h, m, c, N); break;
+        case kBGK: collide<kBGK>(h, m, r, c, N); break;
+        case kRM: collide<kRM>(h, m, r, c, N); break;
+        case kHM: collide<kHM>(h, m, r, c, N); break;
+        case kCM: collide<kCM>(h, m, r, c, N); break;
+        case kCHM: collide<kCHM>(h, m, r, c, N); break;
+        case kK: collide<kK>(h, m, r, c, N); break;
+        case kPR: collide<kPR>(h, m, r, c, N); break;
+        default: collide<kRR>(h, m, r, c, N); break;
     }
 }
 
@@ -129,9 +125,9 @@ __global__ __launch_bounds__(kTileThreads) void k_batch(
                     R h[9];
                     pull_load(src + d.off, d.plane, nb, h);
                     double rho_d;
-                    const Macro<R> m = macro_of(h, d.rho_s, rho_d);
+                    const Macro<R> m = macro_of(h, d.ref, rho_d);
                     flag_bad(!(rho_d > 0.0), blowup + j, (int)n);
-                    collide_model(d.model, h, m, d.c, d.N);
+                    collide_model(d.model, h, m, d.ref, d.c, d.N);
                     store_cell(dst + d.off, d.plane, (unsigned)c, h);
                 }
             }
@@ -154,22 +150,14 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_init(
     if (c >= d.cells) return;
     const int y = row_of(c, d.nx, d.inv_nx);
     const int x = c - y * d.nx;
-    Macro<double> m;
-    m.rho = rho[d.foff + c];
-    m.ux = ux[d.foff + c];
-    m.uy = uy[d.foff + c];
-    m.drho = m.rho - d.rho_s;
-    m.jx = m.rho * m.ux;
-    m.jy = m.rho * m.uy;
-    const Eq<double> e = hermite_eq(m, d.N);
     double h[9];
-    hermite_to_pop(m, e.e20, e.e02, e.e11, e.e21, e.e12, e.e22, h);
+    eq_deviation(rho[d.foff + c], ux[d.foff + c], uy[d.foff + c], d.ref_d, d.N, h);
     prestream_store(base + d.off, Geom{d.nx, d.ny, d.plane}, x, y, h);
 }
 
 template <int PREC>
 __global__ __launch_bounds__(256) void k_batch_get(const typename Store<PREC>::S* __restrict__ src,
-                                                   Geom g, double rho_s, double* __restrict__ f) {
+                                                   Geom g, Pop9 fref, double* __restrict__ f) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     if (x >= g.nx || y >= g.ny) return;
@@ -178,7 +166,7 @@ __global__ __launch_bounds__(256) void k_batch_get(const typename Store<PREC>::S
     pull_load(src, g.plane, nb, h);
     const size_t cells = (size_t)g.nx * g.ny, c = nb.r0 + (size_t)x;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) f[i * cells + c] = h[i] + rho_s * rest_weight(i);
+    for (int i = 0; i < 9; ++i) f[i * cells + c] = h[i] + fref.v[i];
 }
 
 // Reset the barrier counter before each replay.  The error flag is sticky (cleared only at
@@ -333,6 +321,8 @@ int lbm_batch_create(lbm_batch** out, const lbm_instance_desc* desc, int n, int 
         if (rc != LBM_OK) return rc;
         if (prec != LBM_F64 && !(d.rho0 > 0.0))
             return set_error(LBM_EINVAL, "instance %d: rho0 must be > 0", j);
+        if (prec != LBM_F64 && !(d.ux0 * d.ux0 + d.uy0 * d.uy0 < 1.0))
+            return set_error(LBM_EINVAL, "instance %d: reference velocity must have |U| < 1", j);
     }
     if (!rho || !ux || !uy || !pop_buf) return set_error(LBM_EINVAL, "NULL device pointer");
     if (reinterpret_cast<uintptr_t>(pop_buf) % 256 != 0)
@@ -382,18 +372,21 @@ int lbm_batch_create(lbm_batch** out, const lbm_instance_desc* desc, int n, int 
             const int cells = d.nx * d.ny;
             const int t0 = (int)tiles.size();
             for (int t = 0; t < (cells + tile_nodes - 1) / tile_nodes; ++t) tiles.push_back(j);
+            const Ref<double> rd = storage_reference(prec, d.rho0, d.ux0, d.uy0);
             if (prec == LBM_F64) {
                 BDesc<double> bd;
                 bd.nx = d.nx; bd.ny = d.ny; bd.model = d.model; bd.N = d.eq_order;
                 bd.cells = cells; bd.tile0 = t0; bd.off = b->off[j]; bd.plane = b->plane[j];
-                bd.foff = b->foff[j]; bd.rho_s = 0.0; bd.inv_nx = 1.0f / (float)d.nx;
+                bd.foff = b->foff[j]; bd.inv_nx = 1.0f / (float)d.nx;
+                bd.ref = ref_as<double>(rd); bd.ref_d = rd;
                 bd.c = make_coef<double>(d.omega);
                 std::memcpy(dbytes.data() + dsz * j, &bd, dsz);
             } else {
                 BDesc<float> bd;
                 bd.nx = d.nx; bd.ny = d.ny; bd.model = d.model; bd.N = d.eq_order;
                 bd.cells = cells; bd.tile0 = t0; bd.off = b->off[j]; bd.plane = b->plane[j];
-                bd.foff = b->foff[j]; bd.rho_s = d.rho0; bd.inv_nx = 1.0f / (float)d.nx;
+                bd.foff = b->foff[j]; bd.inv_nx = 1.0f / (float)d.nx;
+                bd.ref = ref_as<float>(rd); bd.ref_d = rd;
                 bd.c = make_coef<float>(d.omega);
                 std::memcpy(dbytes.data() + dsz * j, &bd, dsz);
             }
@@ -494,18 +487,19 @@ int lbm_batch_get_state(lbm_batch* b, int instance, double* f) {
     const Geom g{d.nx, d.ny, b->plane[instance]};
     const int sc = (int)(b->step & 1);
     const size_t eoff = (size_t)(sc * b->copy_elems + b->off[instance]);
+    const Pop9 fref = reference_populations(storage_reference(b->prec, d.rho0, d.ux0, d.uy0), d.eq_order);
     switch (b->prec) {
         case LBM_F64:
             hipLaunchKernelGGL(k_batch_get<kF64>, l.grid, l.block, 0, b->stream,
-                               reinterpret_cast<const double*>(b->buf) + eoff, g, 0.0, f);
+                               reinterpret_cast<const double*>(b->buf) + eoff, g, fref, f);
             break;
         case LBM_F32_SHIFTED:
             hipLaunchKernelGGL(k_batch_get<kF32>, l.grid, l.block, 0, b->stream,
-                               reinterpret_cast<const float*>(b->buf) + eoff, g, d.rho0, f);
+                               reinterpret_cast<const float*>(b->buf) + eoff, g, fref, f);
             break;
         default:
             hipLaunchKernelGGL(k_batch_get<kF16>, l.grid, l.block, 0, b->stream,
-                               reinterpret_cast<const _Float16*>(b->buf) + eoff, g, d.rho0, f);
+                               reinterpret_cast<const _Float16*>(b->buf) + eoff, g, fref, f);
             break;
     }
     return check_hip(hipGetLastError(), "batch get_state launch");

@@ -3,10 +3,12 @@
 // Every model of Appendix B (BGK, RM, HM, CM, CHM, K, PR, RR) is written here in one common
 // "deviation" form so that the same code runs in FP64 and in FP32 on shifted populations:
 //
-//   stored value   h_i   = f_i - w_i rho_s          (rho_s = 0 for plain FP64 storage)
-//   density        rho   = rho_s + drho,  drho = sum_i h_i
-//   Hermite moments are taken relative to the rest equilibrium of density rho, so every
-//   quantity carried through the transform is O(u) or O(f^neq), never O(rho).
+//   stored value   h_i   = f_i - f^ref_i,  f^ref = f^eq_N(rho_s, U)   (a fixed reference state;
+//                                           rho_s = 0, U = 0 for plain FP64 storage)
+//   density        rho   = rho_s + drho,   drho = sum_i h_i
+//   velocity       u     = U + du,         du = (sum_i xi_i h_i - drho U) / rho
+//   every equilibrium moment enters as its difference to the reference, built from drho and du,
+//   so each quantity carried through the transform is O(du), O(drho) or O(f^neq), never O(rho).
 //
 // Map used by every model (the pipeline of Appendix B):
 //   1. h -> raw moments (eq. RMcoll definition) -> Hermite non-equilibrium d_pq = A_pq - A^eq_pq
@@ -71,32 +73,59 @@ __host__ __device__ inline Coef<R> make_coef(const double w[5]) {
     return c;
 }
 
-// Conserved quantities of a cell.
-template <typename R> struct Macro {
-    R drho, rho, jx, jy, ux, uy;
+// Reference state of the stored deviations (density rho_s, velocity U).
+template <typename R> struct Ref {
+    R rho, ux, uy;
 };
 
-// Hermite equilibrium moments of order N (A^eq_pq = rho ux^p uy^q, zero above order N).
+// Conserved quantities of a cell: drho = rho - rho_s, (jx, jy) = rho u - rho_s U (the momentum
+// of the stored deviations), u and du = u - U.
+template <typename R> struct Macro {
+    R drho, rho, jx, jy, ux, uy, dux, duy;
+};
+
+// Hermite equilibrium moments of order N (A^eq_pq = rho ux^p uy^q, zero above order N), as
+// differences to those of the reference: E_pq = A^eq_pq(rho, u) - A^eq_pq(rho_s, U)
+//   = drho u^p v^q + rho_s (u^p v^q - U^p V^q),
+// the monomial differences telescoped through du so that nothing of order one cancels.
 template <typename R> struct Eq {
     R e20, e02, e11, e21, e12, e22;
 };
 
 template <typename R>
-__device__ __forceinline__ Eq<R> hermite_eq(const Macro<R>& m, int N) {
+__host__ __device__ __forceinline__ Eq<R> hermite_eq(const Macro<R>& m, const Ref<R>& r, int N) {
+    const R a = m.ux, b = m.uy, A = r.ux, da = m.dux, db = m.duy;
+    const R a2 = a * a, b2 = b * b;
+    const R D20 = da * (a + A);          // a^2 - A^2
+    const R D02 = db * (b + r.uy);       // b^2 - B^2
+    const R D11 = da * b + A * db;       // a b - A B
     Eq<R> e;
-    e.e20 = m.rho * m.ux * m.ux;
-    e.e02 = m.rho * m.uy * m.uy;
-    e.e11 = m.rho * m.ux * m.uy;
-    e.e21 = (N >= 3) ? e.e20 * m.uy : R(0);
-    e.e12 = (N >= 3) ? e.e02 * m.ux : R(0);
-    e.e22 = (N >= 4) ? e.e20 * m.uy * m.uy : R(0);
+    e.e20 = m.drho * a2 + r.rho * D20;
+    e.e02 = m.drho * b2 + r.rho * D02;
+    e.e11 = m.drho * (a * b) + r.rho * D11;
+    if (N >= 3) {
+        const R D21 = D20 * b + (A * A) * db;  // a^2 b - A^2 B
+        const R D12 = da * b2 + A * D02;       // a b^2 - A B^2
+        e.e21 = m.drho * (a2 * b) + r.rho * D21;
+        e.e12 = m.drho * (a * b2) + r.rho * D12;
+    } else {
+        e.e21 = R(0);
+        e.e12 = R(0);
+    }
+    if (N >= 4) {
+        const R D22 = D20 * b2 + (A * A) * D02;  // a^2 b^2 - A^2 B^2
+        e.e22 = m.drho * (a2 * b2) + r.rho * D22;
+    } else {
+        e.e22 = R(0);
+    }
     return e;
 }
 
-// Post-collision Hermite moments (equilibrium part + relaxed non-equilibrium part) ->
-// raw-moment deviations (eq. HM2RM_Q9) -> shifted populations (eq. Q9postCollVDF_RM).
+// Post-collision Hermite moments minus the reference's (equilibrium difference + relaxed
+// non-equilibrium part) -> raw-moment differences (eq. HM2RM_Q9, which is linear) -> stored
+// deviations (eq. Q9postCollVDF_RM; the density difference contributes drho w_i).
 template <typename R>
-__device__ __forceinline__ void hermite_to_pop(const Macro<R>& m, R a20, R a02, R a11, R a21,
+__host__ __device__ __forceinline__ void hermite_to_pop(const Macro<R>& m, R a20, R a02, R a11, R a21,
                                                R a12, R a22, R (&h)[9]) {
     using L = Lat<R>;
     const R M20 = a20, M02 = a02, M11 = a11;
@@ -148,12 +177,13 @@ __device__ __forceinline__ Neq<R> hermite_neq(const R (&h)[9], const Macro<R>& m
 
 // Collide one cell in place.  N is the equilibrium order (2, 3 or 4; CM, CHM and K use 4).
 template <int MODEL, typename R>
-__device__ __forceinline__ void collide(R (&h)[9], const Macro<R>& m, const Coef<R>& c, int N) {
+__device__ __forceinline__ void collide(R (&h)[9], const Macro<R>& m, const Ref<R>& ref,
+                                        const Coef<R>& c, int N) {
     using L = Lat<R>;
     if constexpr (MODEL == kStreamOnly) {
         return;
     } else {
-        const Eq<R> e = hermite_eq(m, N);
+        const Eq<R> e = hermite_eq(m, ref, N);
         if constexpr (MODEL == kBGK) {
             R heq[9];
             hermite_to_pop(m, e.e20, e.e02, e.e11, e.e21, e.e12, e.e22, heq);

@@ -104,9 +104,10 @@ namespace {
 template <int MODEL, int PREC, int ROWS>
 __global__ __launch_bounds__(256) void k_step(const typename Store<PREC>::S* __restrict__ src,
                                               typename Store<PREC>::S* __restrict__ dst, Geom g,
-                                              Coef<typename Store<PREC>::R> c, double rho_s,
-                                              int N, int step, int* __restrict__ blowup,
-                                              unsigned gx, unsigned nb, int xcd) {
+                                              Coef<typename Store<PREC>::R> c,
+                                              Ref<typename Store<PREC>::R> ref, int N, int step,
+                                              int* __restrict__ blowup, unsigned gx, unsigned nb,
+                                              int xcd) {
     using R = typename Store<PREC>::R;
     unsigned bx, by;
     tile_of_block(blockIdx.x, gx, nb, xcd, bx, by);
@@ -121,9 +122,9 @@ __global__ __launch_bounds__(256) void k_step(const typename Store<PREC>::S* __r
             R h[9];
             pull_load(src, g.plane, nb4, h);
             double rho_d;
-            const Macro<R> m = macro_of(h, rho_s, rho_d);
+            const Macro<R> m = macro_of(h, ref, rho_d);
             flag_bad(!(rho_d > 0.0), blowup, step);
-            collide<MODEL>(h, m, c, N);
+            collide<MODEL>(h, m, ref, c, N);
             store_cell(dst, g.plane, nb4.r0 + (unsigned)x, h);
         }
     }
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(256) void k_step(const typename Store<PREC>::S* __r
 // partial sums of {rho, rho ux, rho uy, rho |u|^2 / 2, |u|^2} in FP64.
 template <int PREC>
 __global__ __launch_bounds__(256) void k_moments(const typename Store<PREC>::S* __restrict__ src,
-                                                 Geom g, double rho_s, double* __restrict__ rho,
+                                                 Geom g, Ref<double> ref, double* __restrict__ rho,
                                                  double* __restrict__ ux, double* __restrict__ uy,
                                                  double* __restrict__ partials, int step,
                                                  int* __restrict__ blowup) {
@@ -144,9 +145,9 @@ __global__ __launch_bounds__(256) void k_moments(const typename Store<PREC>::S* 
         const Nbr nb = neighbours(x, y, g.nx, g.ny);
         double h[9];
         pull_load(src, g.plane, nb, h);
-        double r = rho_s + (((h[0] + (h[1] + h[3])) + (h[2] + h[4])) + ((h[5] + h[7]) + (h[6] + h[8])));
-        const double jx = (h[1] + h[5] + h[8]) - (h[3] + h[6] + h[7]);
-        const double jy = (h[2] + h[5] + h[6]) - (h[4] + h[7] + h[8]);
+        double r = ref.rho + (((h[0] + (h[1] + h[3])) + (h[2] + h[4])) + ((h[5] + h[7]) + (h[6] + h[8])));
+        const double jx = ((h[1] + h[5] + h[8]) - (h[3] + h[6] + h[7])) + ref.rho * ref.ux;
+        const double jy = ((h[2] + h[5] + h[6]) - (h[4] + h[7] + h[8])) + ref.rho * ref.uy;
         const double u = jx / r, w = jy / r;
         const unsigned c = nb.r0 + (unsigned)x;
         if (rho) rho[c] = r;
@@ -171,7 +172,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
 // Unshifted FP64 pre-collision populations, [q][y][x] dense.
 template <int PREC>
 __global__ __launch_bounds__(256) void k_get_state(const typename Store<PREC>::S* __restrict__ src,
-                                                   Geom g, double rho_s, double* __restrict__ f) {
+                                                   Geom g, Pop9 fref, double* __restrict__ f) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     if (x >= g.nx || y >= g.ny) return;
@@ -180,14 +181,14 @@ __global__ __launch_bounds__(256) void k_get_state(const typename Store<PREC>::S
     pull_load(src, g.plane, nb, h);
     const size_t cells = (size_t)g.nx * g.ny, c = nb.r0 + (size_t)x;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) f[i * cells + c] = h[i] + rho_s * rest_weight(i);
+    for (int i = 0; i < 9; ++i) f[i * cells + c] = h[i] + fref.v[i];
 }
 
 // Store pre-collision populations f (unshifted FP64, [q][y][x]) pre-streamed backwards so that
 // the next pull returns f(x): value i of node x goes to node x - xi_i.
 template <int PREC>
 __global__ __launch_bounds__(256) void k_set_state(typename Store<PREC>::S* __restrict__ dst,
-                                                   Geom g, double rho_s,
+                                                   Geom g, Pop9 fref,
                                                    const double* __restrict__ f) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -195,30 +196,22 @@ __global__ __launch_bounds__(256) void k_set_state(typename Store<PREC>::S* __re
     const size_t cells = (size_t)g.nx * g.ny, c = (size_t)y * g.nx + x;
     double h[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) h[i] = f[i * cells + c] - rho_s * rest_weight(i);
+    for (int i = 0; i < 9; ++i) h[i] = f[i * cells + c] - fref.v[i];
     prestream_store(dst, g, x, y, h);
 }
 
 // f(., 0) = f^eq_N(rho, u), stored pre-streamed like k_set_state.  FP64 arithmetic.
 template <int PREC>
 __global__ __launch_bounds__(256) void k_init_eq(typename Store<PREC>::S* __restrict__ dst, Geom g,
-                                                 double rho_s, int N, const double* __restrict__ rho,
+                                                 Ref<double> ref, int N, const double* __restrict__ rho,
                                                  const double* __restrict__ ux,
                                                  const double* __restrict__ uy) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     if (x >= g.nx || y >= g.ny) return;
     const size_t c = (size_t)y * g.nx + x;
-    Macro<double> m;
-    m.rho = rho[c];
-    m.ux = ux[c];
-    m.uy = uy[c];
-    m.drho = m.rho - rho_s;
-    m.jx = m.rho * m.ux;
-    m.jy = m.rho * m.uy;
-    const Eq<double> e = hermite_eq(m, N);
     double h[9];
-    hermite_to_pop(m, e.e20, e.e02, e.e11, e.e21, e.e12, e.e22, h);
+    eq_deviation(rho[c], ux[c], uy[c], ref, N, h);
     prestream_store(dst, g, x, y, h);
 }
 
@@ -233,8 +226,8 @@ void launch_step_r(lbm_ctx* ctx, const StepShape& sh, const Coef<typename Store<
     S* dst = reinterpret_cast<S*>(ctx->copy(src_copy ^ 1));
     const unsigned nb = sh.gx * sh.gy;
     hipLaunchKernelGGL((k_step<MODEL, PREC, ROWS>), dim3(nb), dim3(sh.bw, sh.bh), 0, ctx->stream,
-                       src, dst, ctx->geom(), c, ctx->rho_s, ctx->eq_order, (int)ctx->step,
-                       ctx->d_flag, sh.gx, nb, sh.xcd);
+                       src, dst, ctx->geom(), c, ref_as<typename Store<PREC>::R>(ctx->ref),
+                       ctx->eq_order, (int)ctx->step, ctx->d_flag, sh.gx, nb, sh.xcd);
 }
 
 template <int MODEL, int PREC>
@@ -268,7 +261,7 @@ void launch_moments_p(lbm_ctx* ctx, double* rho, double* ux, double* uy) {
     using S = typename Store<PREC>::S;
     const Launch l = launch_for(ctx->nx, ctx->ny);
     hipLaunchKernelGGL((k_moments<PREC>), l.grid, l.block, 0, ctx->stream,
-                       reinterpret_cast<const S*>(ctx->copy(ctx->cur)), ctx->geom(), ctx->rho_s, rho,
+                       reinterpret_cast<const S*>(ctx->copy(ctx->cur)), ctx->geom(), ctx->ref, rho,
                        ux, uy, ctx->d_part, (int)ctx->step, ctx->d_flag);
 }
 
@@ -277,7 +270,7 @@ void launch_get_p(lbm_ctx* ctx, double* f) {
     using S = typename Store<PREC>::S;
     const Launch l = launch_for(ctx->nx, ctx->ny);
     hipLaunchKernelGGL((k_get_state<PREC>), l.grid, l.block, 0, ctx->stream,
-                       reinterpret_cast<const S*>(ctx->copy(ctx->cur)), ctx->geom(), ctx->rho_s, f);
+                       reinterpret_cast<const S*>(ctx->copy(ctx->cur)), ctx->geom(), ctx->fref, f);
 }
 
 template <int PREC>
@@ -285,7 +278,7 @@ void launch_set_p(lbm_ctx* ctx, const double* f) {
     using S = typename Store<PREC>::S;
     const Launch l = launch_for(ctx->nx, ctx->ny);
     hipLaunchKernelGGL((k_set_state<PREC>), l.grid, l.block, 0, ctx->stream,
-                       reinterpret_cast<S*>(ctx->copy(ctx->cur)), ctx->geom(), ctx->rho_s, f);
+                       reinterpret_cast<S*>(ctx->copy(ctx->cur)), ctx->geom(), ctx->fref, f);
 }
 
 template <int PREC>
@@ -293,7 +286,7 @@ void launch_init_p(lbm_ctx* ctx, const double* rho, const double* ux, const doub
     using S = typename Store<PREC>::S;
     const Launch l = launch_for(ctx->nx, ctx->ny);
     hipLaunchKernelGGL((k_init_eq<PREC>), l.grid, l.block, 0, ctx->stream,
-                       reinterpret_cast<S*>(ctx->copy(ctx->cur)), ctx->geom(), ctx->rho_s,
+                       reinterpret_cast<S*>(ctx->copy(ctx->cur)), ctx->geom(), ctx->ref,
                        ctx->eq_order, rho, ux, uy);
 }
 
@@ -332,6 +325,13 @@ size_t lbm_population_bytes(int nx, int ny, int prec) {
 int lbm_init(lbm_ctx** out, int nx, int ny, int prec, int eq_order, double rho0, const double* rho,
              const double* ux, const double* uy, void* pop_buf, size_t pop_bytes,
              void* hip_stream) {
+    return lbm_init_shifted(out, nx, ny, prec, eq_order, rho0, 0.0, 0.0, rho, ux, uy, pop_buf,
+                            pop_bytes, hip_stream);
+}
+
+int lbm_init_shifted(lbm_ctx** out, int nx, int ny, int prec, int eq_order, double rho0,
+                     double ux0, double uy0, const double* rho, const double* ux,
+                     const double* uy, void* pop_buf, size_t pop_bytes, void* hip_stream) {
     if (!out) return set_error(LBM_EINVAL, "out is NULL");
     *out = nullptr;
     if (nx < 2 || ny < 2) return set_error(LBM_EINVAL, "grid %d x %d: each side must be >= 2", nx, ny);
@@ -340,6 +340,8 @@ int lbm_init(lbm_ctx** out, int nx, int ny, int prec, int eq_order, double rho0,
     if (prec < LBM_F64 || prec > LBM_F16_SHIFTED) return set_error(LBM_EINVAL, "unknown precision %d", prec);
     if (eq_order < 2 || eq_order > 4) return set_error(LBM_EINVAL, "eq_order %d not in {2,3,4}", eq_order);
     if (prec != LBM_F64 && !(rho0 > 0.0)) return set_error(LBM_EINVAL, "rho0 must be > 0 (got %g)", rho0);
+    if (prec != LBM_F64 && !(ux0 * ux0 + uy0 * uy0 < 1.0))
+        return set_error(LBM_EINVAL, "reference velocity (%g, %g) must have |U| < 1", ux0, uy0);
     if (!rho || !ux || !uy) return set_error(LBM_EINVAL, "rho/ux/uy must be device pointers");
     if (!pop_buf) return set_error(LBM_EINVAL, "pop_buf is NULL");
     if (reinterpret_cast<uintptr_t>(pop_buf) % 256 != 0)
@@ -353,7 +355,8 @@ int lbm_init(lbm_ctx** out, int nx, int ny, int prec, int eq_order, double rho0,
     ctx->ny = ny;
     ctx->prec = prec;
     ctx->eq_order = eq_order;
-    ctx->rho_s = prec == LBM_F64 ? 0.0 : rho0;
+    ctx->ref = storage_reference(prec, rho0, ux0, uy0);
+    ctx->fref = reference_populations(ctx->ref, eq_order);
     ctx->buf = static_cast<char*>(pop_buf);
     ctx->bytes = pop_bytes;
     ctx->plane = plane_elems(nx, ny, prec);

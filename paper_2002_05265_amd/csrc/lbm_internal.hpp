@@ -157,24 +157,75 @@ __device__ __forceinline__ void prestream_store(S* __restrict__ dst, const Geom&
 // Conserved quantities of a cell.  The density is always recovered in FP64:
 // rho = rho_s + sum_i h_i; rho_d returns it for the blow-up test.
 template <typename R>
-__device__ __forceinline__ Macro<R> macro_of(const R (&h)[9], double rho_s, double& rho_d) {
+__device__ __forceinline__ Macro<R> macro_of(const R (&h)[9], const Ref<R>& ref, double& rho_d) {
     Macro<R> m;
     if constexpr (std::is_same<R, double>::value) {
         m.drho = ((h[0] + (h[1] + h[3])) + (h[2] + h[4])) + ((h[5] + h[7]) + (h[6] + h[8]));
-        m.rho = rho_s + m.drho;
+        m.rho = ref.rho + m.drho;
         rho_d = m.rho;
     } else {
         const double d = (((double)h[0] + ((double)h[1] + (double)h[3])) + ((double)h[2] + (double)h[4])) +
                          (((double)h[5] + (double)h[7]) + ((double)h[6] + (double)h[8]));
-        rho_d = rho_s + d;
+        rho_d = (double)ref.rho + d;
         m.drho = (R)d;
         m.rho = (R)rho_d;
     }
     m.jx = ((h[1] + h[5]) + h[8]) - ((h[3] + h[6]) + h[7]);
     m.jy = ((h[2] + h[5]) + h[6]) - ((h[4] + h[7]) + h[8]);
-    m.ux = m.jx / m.rho;
-    m.uy = m.jy / m.rho;
+    m.dux = (m.jx - m.drho * ref.ux) / m.rho;
+    m.duy = (m.jy - m.drho * ref.uy) / m.rho;
+    m.ux = ref.ux + m.dux;
+    m.uy = ref.uy + m.duy;
     return m;
+}
+
+// Conserved quantities of a node given by its macroscopic fields (FP64, initialisation).
+__host__ __device__ inline Macro<double> macro_of_fields(double rho, double ux, double uy,
+                                                         const Ref<double>& r) {
+    Macro<double> m;
+    m.rho = rho;
+    m.ux = ux;
+    m.uy = uy;
+    m.drho = rho - r.rho;
+    m.dux = ux - r.ux;
+    m.duy = uy - r.uy;
+    m.jx = rho * ux - r.rho * r.ux;
+    m.jy = rho * uy - r.rho * r.uy;
+    return m;
+}
+
+// Stored deviations of f^eq_N(rho, u) with respect to the reference (FP64).
+__host__ __device__ inline void eq_deviation(double rho, double ux, double uy, const Ref<double>& r,
+                                             int N, double (&h)[9]) {
+    const Macro<double> m = macro_of_fields(rho, ux, uy, r);
+    const Eq<double> e = hermite_eq(m, r, N);
+    hermite_to_pop(m, e.e20, e.e02, e.e11, e.e21, e.e12, e.e22, h);
+}
+
+// The nine reference populations f^eq_N(rho_s, U) (FP64), added back by get_state.
+struct Pop9 {
+    double v[9];
+};
+
+inline Pop9 reference_populations(const Ref<double>& r, int N) {
+    const Ref<double> zero{0.0, 0.0, 0.0};
+    double h[9];
+    eq_deviation(r.rho, r.ux, r.uy, zero, N, h);
+    Pop9 p;
+    for (int i = 0; i < 9; ++i) p.v[i] = h[i];
+    return p;
+}
+
+// Reference of a precision: none for FP64; for shifted storage the values are rounded to FP32
+// once so that the FP32 kernels and the FP64 set-up use exactly the same reference.
+inline Ref<double> storage_reference(int prec, double rho0, double ux0, double uy0) {
+    if (prec == LBM_F64) return Ref<double>{0.0, 0.0, 0.0};
+    return Ref<double>{(double)(float)rho0, (double)(float)ux0, (double)(float)uy0};
+}
+
+template <typename R>
+inline Ref<R> ref_as(const Ref<double>& r) {
+    return Ref<R>{(R)r.rho, (R)r.ux, (R)r.uy};
 }
 
 // Record `step` in *flag (atomic min) if any lane of the wave saw a bad node.
@@ -222,7 +273,8 @@ int validate_model(int model, int eq_order);
 
 struct lbm_ctx {
     int nx = 0, ny = 0, prec = 0, eq_order = 4;
-    double rho_s = 0.0;           // storage shift: h_i = f_i - w_i rho_s
+    lbm::Ref<double> ref{0.0, 0.0, 0.0};  // storage reference: h_i = f_i - f^eq_N(rho_s, U)_i
+    lbm::Pop9 fref{};                      // the reference populations
     char* buf = nullptr;          // caller-owned population buffer (two copies)
     size_t bytes = 0;
     long long plane = 0;          // elements per population plane

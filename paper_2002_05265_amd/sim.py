@@ -23,10 +23,12 @@ class Sim:
     """One periodic nx x ny D2Q9 simulation on the current HIP device.
 
     rho, ux, uy: initial macroscopic fields [ny, nx] (numpy or torch, converted to FP64).
-    prec: 'f64' | 'f32' | 'f16' (shifted storage for the last two).  eq_order: 2, 3 or 4."""
+    prec: 'f64' | 'f32' | 'f16' (shifted storage for the last two).  eq_order: 2, 3 or 4.
+    ref_velocity: reference velocity U of the shifted storage (h = f - f^eq(rho0, U))."""
 
     def __init__(self, rho, ux, uy, prec: str = "f64", eq_order: int = 4, rho0: float = 1.0,
-                 device: str | torch.device = "cuda", stream: torch.cuda.Stream | None = None):
+                 device: str | torch.device = "cuda", stream: torch.cuda.Stream | None = None,
+                 ref_velocity=(0.0, 0.0)):
         self.device = torch.device(device)
         rho, ux, uy = (_dev_f64(a, self.device) for a in (rho, ux, uy))
         self.ny, self.nx = rho.shape
@@ -37,9 +39,10 @@ class Sim:
             raise ValueError(f"invalid grid {self.nx} x {self.ny}")
         self.pop = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream or torch.cuda.current_stream(self.device)
-        self.ctx = B.lbm_init(self.nx, self.ny, self.prec, eq_order, rho0, rho.data_ptr(),
-                              ux.data_ptr(), uy.data_ptr(), self.pop.data_ptr(), nbytes,
-                              self.stream.cuda_stream)
+        self.ctx = B.lbm_init_shifted(self.nx, self.ny, self.prec, eq_order, rho0,
+                                      float(ref_velocity[0]), float(ref_velocity[1]), rho.data_ptr(),
+                                      ux.data_ptr(), uy.data_ptr(), self.pop.data_ptr(), nbytes,
+                                      self.stream.cuda_stream)
         # the init kernel reads rho/ux/uy asynchronously: keep them alive until it has run
         self.stream.synchronize()
 

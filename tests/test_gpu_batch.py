@@ -31,8 +31,9 @@ def make_instances(rng, n=16, sizes=SIZES):
         model = inputs.MODEL_NAMES[k % 8]
         N = 4 if model in ("CM", "CHM", "K") else int(rng.choice([2, 3, 4]))
         omega = [1.96, *rng.uniform(0.5, 1.9, 4)] if k % 3 else list(inputs.rates(1e-4, "REG"))
+        mach = float(rng.uniform(0.05, 0.4))
         out.append({"nx": nx, "ny": ny, "model": model, "eq_order": N, "omega": omega, "rho0": 1.0,
-                    "mach": float(rng.uniform(0.05, 0.4))})
+                    "ux0": mach * inputs.CS if k % 2 else 0.0, "uy0": 0.01 * (k % 3), "mach": mach})
     return out
 
 
@@ -42,7 +43,8 @@ def fields_of(inst, k):
 
 
 def plain_state(inst, fields, prec, steps, gpu):
-    s = Sim(*fields, prec=prec, eq_order=inst["eq_order"], device=gpu)
+    s = Sim(*fields, prec=prec, eq_order=inst["eq_order"], device=gpu,
+            ref_velocity=(inst.get("ux0", 0.0), inst.get("uy0", 0.0)))
     s.step(inst["model"], inst["omega"], steps)
     out, st = s.state().cpu().numpy(), s.status()
     s.close()

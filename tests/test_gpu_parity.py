@@ -102,20 +102,22 @@ def test_models_fp64(gpu, name):
 
 
 @pytest.mark.parametrize("name", MODELS)
-def test_models_fp32_shifted(gpu, name):
+@pytest.mark.parametrize("reference", ["rest", "mean-flow"])
+def test_models_fp32_shifted(gpu, name, reference):
     nx, ny, steps = 70, 45, 40
     rho, ux, uy = inputs.vortex_fields(nx, ny, 0.3, beta=0.5, radius_frac=0.15)
     omega = omega_sets()["REG"]
     ref = oracle.step(oracle.init_eq(4, rho, ux, uy), inputs.MODEL_CODES[name], 4, omega, steps)
     rr, ru, rv, _ = oracle.moments(ref)
-    sim = Sim(rho, ux, uy, prec="f32", eq_order=4, device=gpu)
+    uref = (0.0, 0.0) if reference == "rest" else (0.3 * inputs.CS, 0.0)
+    sim = Sim(rho, ux, uy, prec="f32", eq_order=4, device=gpu, ref_velocity=uref)
     sim.step(name, omega, steps)
     r, u, v, _ = sim.moments()
     g = sim.state().cpu().numpy()
     r = r.cpu().numpy()
     e = [rel(g, ref), rel(r, rr), rel(u.cpu().numpy(), ru), rel(v.cpu().numpy(), rv)]
     drho = float(np.max(np.abs(r - rr)))
-    print(name, "fp32 errors f, rho, ux, uy", e, "max |d rho|", drho, flush=True)
+    print(name, reference, "fp32 errors f, rho, ux, uy", e, "max |d rho|", drho, flush=True)
     assert max(e) < 1e-5, e
     # each stored deviation carries a rounding of at most 2^-24 |h| (|h| <= 0.09 here); mass
     # errors are never damped, and the nine roundings per node and step random-walk over the
@@ -124,7 +126,8 @@ def test_models_fp32_shifted(gpu, name):
 
 
 @pytest.mark.parametrize("name", ["BGK", "CM", "K", "RR"])
-def test_models_fp16(gpu, name):
+@pytest.mark.parametrize("reference", ["rest", "mean-flow"])
+def test_models_fp16(gpu, name, reference):
     # FP16 storage rounds every stored deviation h_i with relative error <= 2^-11; over 40
     # steps the accumulated error stays within 40 * 2^-11 * max|h| / max|u| ~ 2e-2 of the
     # velocity scale, the bound asserted here.
@@ -133,11 +136,12 @@ def test_models_fp16(gpu, name):
     omega = omega_sets()["REG"]
     ref = oracle.step(oracle.init_eq(4, rho, ux, uy), inputs.MODEL_CODES[name], 4, omega, steps)
     _, ru, rv, _ = oracle.moments(ref)
-    sim = Sim(rho, ux, uy, prec="f16", eq_order=4, device=gpu)
+    uref = (0.0, 0.0) if reference == "rest" else (0.3 * inputs.CS, 0.0)
+    sim = Sim(rho, ux, uy, prec="f16", eq_order=4, device=gpu, ref_velocity=uref)
     sim.step(name, omega, steps)
     _, u, v, _ = sim.moments()
     e = [rel(u.cpu().numpy(), ru), rel(v.cpu().numpy(), rv)]
-    print(name, "fp16 errors", e, flush=True)
+    print(name, reference, "fp16 errors", e, flush=True)
     assert max(e) < 2e-2, e
 
 
