@@ -1,0 +1,80 @@
+/*
+ * lbm_adjoint.h - discrete adjoint of the stream-and-collide scheme, and raw state
+ * checkpoints for reverse sweeps.
+ *
+ * Forward map of one step (eq. StreamCollide): f_{n+1} = S C(f_n; omega), C the per-cell
+ * collision of Appendix B, S the streaming permutation.  Its adjoint, for a loss L of the
+ * final state, is
+ *     lambda_n(x) = J_C(f_n(x))^T mu(x),   mu_i(x) = lambda_{n+1, i}(x + xi_i)      (S^T)
+ *     dL/domega  += sum_x (dC/domega (f_n(x)))^T mu(x)
+ * with J_C = dC/df, the Jacobian whose role in the linear analysis of the paper is set out
+ * in Appendix A (eq. Perturbed_Collision).  Here it is applied in transposed form by a
+ * hand-written reverse pass of each model's moment transform -> relax -> back-transform,
+ * with no matrix formed.  The initial state f_0 = f^eq_N(rho0, u0) pulls lambda_0 back to
+ * dL/du0 (lbm_eq_vjp).
+ *
+ * Arrays
+ *   raw state   the context's own storage of one state (9 planes, storage precision,
+ *               pre-streamed), lbm_state_bytes bytes; only meaningful to the same context
+ *   lambda      adjoint populations, 9 planes [q][y][x] with the context's plane stride
+ *               (lbm_adjoint_bytes bytes): FP64 for LBM_F64 contexts, FP32 otherwise
+ * All pointers below are device pointers unless stated; work is enqueued on the context's
+ * stream.  Conventions otherwise as in lbm.h.
+ */
+#ifndef LBM_ADJOINT_H
+#define LBM_ADJOINT_H
+
+#include <stddef.h>
+
+#include "lbm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Bytes of one raw state of this context (0 if ctx is NULL). */
+size_t lbm_state_bytes(lbm_ctx* ctx);
+
+/* Bytes of one adjoint population array of this context (0 if ctx is NULL). */
+size_t lbm_adjoint_bytes(lbm_ctx* ctx);
+
+/* Copy the current state, in the context's storage format, to dst (lbm_state_bytes bytes).
+ * Asynchronous (device-to-device). */
+int lbm_save_state(lbm_ctx* ctx, void* dst);
+
+/* Make a raw state saved by lbm_save_state of this context the current state, with step
+ * counter `step` (>= 0); the blow-up record is cleared.  Asynchronous. */
+int lbm_load_state(lbm_ctx* ctx, const void* src, long long step);
+
+/* Seed of the velocity loss L = || u(f) - u_target ||_2 (sum over nodes and both
+ * components) for the current state f:
+ *   ux_t, uy_t  device, nx*ny FP64 [y][x]: the target velocity
+ *   lam         device, lbm_adjoint_bytes: receives dL/df (u = sum xi f / sum f)
+ *   loss        host, 1 double: receives L (computed in FP64)
+ * Synchronises the stream (L is needed to scale the seed).  L = 0 gives LBM_EINVAL. */
+int lbm_adjoint_seed_velocity_l2(lbm_ctx* ctx, const double* ux_t, const double* uy_t, void* lam,
+                                 double* loss);
+
+/* One reverse step through the collision of state f_n and the streaming that follows it:
+ *   model, omega  as in lbm_step (must be those of the forward step)
+ *   state         raw state f_n (lbm_save_state of this context), or NULL = current state
+ *   lam_next      lambda_{n+1} (read); lam: receives lambda_n (must not alias lam_next)
+ *   domega        device, LBM_NOMEGA doubles: dL/domega of this step is ADDED (FP64,
+ *                 deterministic order)
+ * Asynchronous. */
+int lbm_adjoint_step(lbm_ctx* ctx, int model, const double* omega, const void* state,
+                     const void* lam_next, void* lam, double* domega);
+
+/* Pull-back through the initial equilibrium f_0 = f^eq_N(rho0, u0) of the context's order:
+ *   rho0, ux0, uy0   device FP64 [y][x]: the initial fields given to lbm_init
+ *   lam0             lambda_0 (lbm_adjoint_bytes)
+ *   dux, duy         device FP64 [y][x]: receive dL/du0 (overwritten)
+ * Asynchronous. */
+int lbm_eq_vjp(lbm_ctx* ctx, const double* rho0, const double* ux0, const double* uy0,
+               const void* lam0, double* dux, double* duy);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_ADJOINT_H */

@@ -27,6 +27,8 @@ EXPORTS = (
     "lbm_last_error",
     "lbm_batch_population_bytes", "lbm_batch_create", "lbm_batch_run", "lbm_batch_status",
     "lbm_batch_get_state", "lbm_batch_set_launch", "lbm_batch_autotune", "lbm_batch_destroy",
+    "lbm_state_bytes", "lbm_adjoint_bytes", "lbm_save_state", "lbm_load_state",
+    "lbm_adjoint_seed_velocity_l2", "lbm_adjoint_step", "lbm_eq_vjp",
 )
 
 
@@ -72,6 +74,13 @@ def _declare(L: ctypes.CDLL):
         "lbm_batch_set_launch": (_i, [_vp, _i, _i]),
         "lbm_batch_autotune": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), _dp]),
         "lbm_batch_destroy": (None, [_vp]),
+        "lbm_state_bytes": (_sz, [_vp]),
+        "lbm_adjoint_bytes": (_sz, [_vp]),
+        "lbm_save_state": (_i, [_vp, _vp]),
+        "lbm_load_state": (_i, [_vp, _vp, _ll]),
+        "lbm_adjoint_seed_velocity_l2": (_i, [_vp, _vp, _vp, _vp, _dp]),
+        "lbm_adjoint_step": (_i, [_vp, _i, _dp, _vp, _vp, _vp, _vp]),
+        "lbm_eq_vjp": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -224,6 +233,38 @@ def lbm_batch_autotune(b: int, trials: int):
 
 def lbm_batch_destroy(b: int):
     lib().lbm_batch_destroy(b)
+
+
+def lbm_state_bytes(ctx: int) -> int:
+    return int(lib().lbm_state_bytes(ctx))
+
+
+def lbm_adjoint_bytes(ctx: int) -> int:
+    return int(lib().lbm_adjoint_bytes(ctx))
+
+
+def lbm_save_state(ctx: int, dst: int):
+    _check(lib().lbm_save_state(ctx, dst), "lbm_save_state")
+
+
+def lbm_load_state(ctx: int, src: int, step: int):
+    _check(lib().lbm_load_state(ctx, src, step), "lbm_load_state")
+
+
+def lbm_adjoint_seed_velocity_l2(ctx: int, ux_t: int, uy_t: int, lam: int) -> float:
+    loss = _d()
+    _check(lib().lbm_adjoint_seed_velocity_l2(ctx, ux_t, uy_t, lam, ctypes.byref(loss)),
+           "lbm_adjoint_seed_velocity_l2")
+    return loss.value
+
+
+def lbm_adjoint_step(ctx: int, model: int, omega, state: int | None, lam_next: int, lam: int, domega: int):
+    _check(lib().lbm_adjoint_step(ctx, model, _omega(omega), state, lam_next, lam, domega),
+           "lbm_adjoint_step")
+
+
+def lbm_eq_vjp(ctx: int, rho0: int, ux0: int, uy0: int, lam0: int, dux: int, duy: int):
+    _check(lib().lbm_eq_vjp(ctx, rho0, ux0, uy0, lam0, dux, duy), "lbm_eq_vjp")
 
 
 def lbm_last_error() -> str:

@@ -311,6 +311,17 @@ int reset_flag(lbm_ctx* ctx) {
 
 }  // namespace
 
+namespace lbm {
+
+int reset_blowup(lbm_ctx* ctx) { return reset_flag(ctx); }
+
+int reduce_partials(lbm_ctx* ctx) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, ctx->stream, ctx->d_part, ctx->nblocks, ctx->d_tot);
+    return check_hip(hipGetLastError(), "finalize kernel launch");
+}
+
+}  // namespace lbm
+
 // -------------------------------------------------------------------------------------------------
 // C ABI
 

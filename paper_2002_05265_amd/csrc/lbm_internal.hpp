@@ -271,6 +271,12 @@ int validate_model(int model, int eq_order);
 
 }  // namespace lbm
 
+struct lbm_ctx;
+namespace lbm {
+int reset_blowup(lbm_ctx* ctx);     // blow-up record := none (kernel on the context's stream)
+int reduce_partials(lbm_ctx* ctx);  // d_tot[0..4] := sum over blocks of d_part (fixed order)
+}  // namespace lbm
+
 struct lbm_ctx {
     int nx = 0, ny = 0, prec = 0, eq_order = 4;
     lbm::Ref<double> ref{0.0, 0.0, 0.0};  // storage reference: h_i = f_i - f^eq_N(rho_s, U)_i
