@@ -136,6 +136,63 @@ def batched_sweep(steps: int, plain_f64_mlups: float, n_inst: int = 512):
             "precision": "f64"}
 
 
+def adjoint_run(n: int = 512, steps: int = 2000, prec: str = "f32"):
+    """Vortex-transport gradient: n x n CM convected vortex (Ma 0.2, nu 1e-5, REG rates),
+    L = ||u_T - u_target||_2 after `steps`, gradients w.r.t. the initial velocity field and the
+    rates by the discrete adjoint with sqrt(n) checkpoints.  Compared with the plain forward
+    run of the same grid, precision and step count."""
+    import torch
+
+    from paper_2002_05265_amd import inputs
+    from paper_2002_05265_amd.adjoint import _Run
+    from paper_2002_05265_amd.sim import Sim
+
+    mach = 0.2
+    rho, ux, uy = inputs.vortex_fields(n, n, mach, beta=0.15, radius_frac=0.1)
+    tx, ty = inputs.translated_vortex_velocity(n, n, mach, steps, beta=0.15, radius_frac=0.1)
+    omega = inputs.rates(1e-5, "REG")
+    uref = (mach * inputs.CS, 0.0)
+    dev = torch.device("cuda:0")
+    u0 = torch.tensor(np.stack([ux, uy]), device=dev)
+    tgt = torch.tensor(np.stack([tx, ty]), device=dev)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    # plain forward
+    sim = Sim(rho, ux, uy, prec=prec, eq_order=4, device=dev, ref_velocity=uref)
+    sim.step("CM", omega, 20)
+    torch.cuda.synchronize()
+    e[0].record()
+    sim.step("CM", omega, steps)
+    e[1].record()
+    torch.cuda.synchronize()
+    plain_s = e[0].elapsed_time(e[1]) * 1e-3
+    sim.close()
+    run = _Run(u0, omega, torch.tensor(rho, device=dev), tgt, "CM", steps, prec, 4, "sqrt", 0, uref)
+    torch.cuda.synchronize()
+    e[0].record()
+    loss = run.forward()
+    e[1].record()
+    e[2].record()
+    du, dw = run.backward()
+    e[3].record()
+    torch.cuda.synchronize()
+    fwd_s = e[0].elapsed_time(e[1]) * 1e-3
+    bwd_s = e[2].elapsed_time(e[3]) * 1e-3
+    stats = {"recomputed_steps": run.steps_run - steps, "peak_states": run.peak_states}
+    run.close()
+    total = fwd_s + bwd_s
+    cells = n * n
+    return {"workload": f"{n}x{n} CM convected vortex, Ma 0.2, nu 1e-5, REG, {prec} (mean-flow "
+                        f"reference), {steps} steps, sqrt(n) checkpoints",
+            "loss": loss, "grad_omega": [float(v) for v in dw.cpu()],
+            "forward_s": round(fwd_s, 4), "backward_s": round(bwd_s, 4),
+            "plain_forward_s": round(plain_s, 4),
+            "mlups_forward_plus_backward": round(cells * steps / total / 1e6, 1),
+            "plain_mlups": round(cells * steps / plain_s / 1e6, 1),
+            "vs_plain": round(plain_s / total, 3),
+            "expected_vs_plain_from_bytes": round(18 / (18 + 18 + 27), 3),
+            "cache_resident": True, **stats}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,7 +264,7 @@ def main():
     dom_us = per_model[dominant]["us_per_step"]
     achieved = cells * bytes_per_cell(args.prec) / (dom_us * 1e-6) / 1e9
     line = {
-        "metric": "MLUPS per collision model at 4096^2 FP32 + % HBM roofline",
+        "metric": "MLUPS per collision model at 4096^2 FP32 + % HBM roofline; adjoint/batched vs plain",
         "value": round(value, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -239,6 +296,7 @@ def main():
         line["precisions"] = {p: time_models(p, n, models, extra_steps, 5, omega, fields) for p in ("f64", "f16")}
         f64_mlups = min(v["mlups"] for v in line["precisions"]["f64"].values())
         line["batched"] = batched_sweep(args.batch_steps, f64_mlups)
+        line["adjoint"] = adjoint_run()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(models)
     print(json.dumps(line), flush=True)

@@ -46,6 +46,21 @@ int lbm_save_state(lbm_ctx* ctx, void* dst);
  * counter `step` (>= 0); the blow-up record is cleared.  Asynchronous. */
 int lbm_load_state(lbm_ctx* ctx, const void* src, long long step);
 
+/* One forward step from raw state src (f_n, saved by lbm_save_state or written by this
+ * function) to raw state dst (receives f_{n+1}), without touching the context's current state
+ * or step counter: reverse sweeps rebuild the states of a segment straight into their
+ * checkpoint slots.  src and dst must differ; `step` = n is the index recorded if src has a
+ * node with !(rho > 0) (lbm_status).  Asynchronous. */
+int lbm_step_raw(lbm_ctx* ctx, int model, const double* omega, const void* src, void* dst,
+                 long long step);
+
+/* count (>= 0) independent raw steps in one call, in order: step k reads src[k] and writes
+ * dst[k] (src[k] != dst[k]) with step index step0 + k.  src and dst are host arrays of
+ * device pointers; a later step may read what an earlier one wrote (stream order).  Same
+ * arithmetic as lbm_step_raw, without one host call per step. */
+int lbm_step_raw_many(lbm_ctx* ctx, int model, const double* omega, const void* const* src,
+                      void* const* dst, int count, long long step0);
+
 /* Seed of the velocity loss L = || u(f) - u_target ||_2 (sum over nodes and both
  * components) for the current state f:
  *   ux_t, uy_t  device, nx*ny FP64 [y][x]: the target velocity
@@ -59,11 +74,26 @@ int lbm_adjoint_seed_velocity_l2(lbm_ctx* ctx, const double* ux_t, const double*
  *   model, omega  as in lbm_step (must be those of the forward step)
  *   state         raw state f_n (lbm_save_state of this context), or NULL = current state
  *   lam_next      lambda_{n+1} (read); lam: receives lambda_n (must not alias lam_next)
- *   domega        device, LBM_NOMEGA doubles: dL/domega of this step is ADDED (FP64,
- *                 deterministic order)
+ *   domega        device, LBM_NOMEGA doubles: dL/domega of this step (and of any steps
+ *                 left pending by lbm_adjoint_many) is ADDED (FP64, deterministic order)
  * Asynchronous. */
 int lbm_adjoint_step(lbm_ctx* ctx, int model, const double* omega, const void* state,
                      const void* lam_next, void* lam, double* domega);
+
+/* count (>= 0) reverse steps in one call: step k applies the adjoint at raw state states[k]
+ * to lam[k] and writes lam[k + 1] (host arrays of device pointers; lam has count + 1 entries,
+ * lam[k] != lam[k + 1]).  Same arithmetic as lbm_adjoint_step, without one host call per step.
+ * Rate gradients: each block of the grid keeps a running FP64 sum of its contributions, in
+ * step order, across calls.  With domega != NULL the pending sums are added to domega (device,
+ * 5 doubles) at the end of the call and cleared; with domega == NULL they stay pending, so
+ * that a whole reverse sweep issued in any grouping of calls sums in the same order
+ * (bit-identical gradients).  lbm_adjoint_step is this function with count = 1. */
+int lbm_adjoint_many(lbm_ctx* ctx, int model, const double* omega, const void* const* states,
+                     int count, void* const* lam, double* domega);
+
+/* Add the pending rate-gradient sums (see lbm_adjoint_many) to domega (device, 5 doubles) and
+ * clear them; nothing to add leaves domega unchanged.  Asynchronous. */
+int lbm_adjoint_flush(lbm_ctx* ctx, double* domega);
 
 /* Pull-back through the initial equilibrium f_0 = f^eq_N(rho0, u0) of the context's order:
  *   rho0, ux0, uy0   device FP64 [y][x]: the initial fields given to lbm_init

@@ -6,7 +6,8 @@ L = || u(f_T) - u_target ||_2; its backward pass runs the hand-written discrete 
 and dL/domega (all five rates; the four higher-order ones are omega[1:]).
 
 The forward states needed in reverse order are rebuilt from checkpoints of the raw device
-state (``lbm_save_state``):
+state; steps between checkpoints run out-of-place (``lbm_step_raw``) straight into the buffer
+that keeps their result, so no state is ever copied:
   "sqrt"       ceil(sqrt(n)) evenly spaced checkpoints, each segment recomputed once into a
                ring of at most ceil(sqrt(n)) states (about n extra steps, 2 sqrt(n) states)
   "revolve"    binomial checkpointing with `slots` state buffers (Griewank's schedule: the
@@ -113,6 +114,11 @@ def _revolve(a: int, b: int, key, free: int):
 
 
 class _Run:
+    """Executes the schedule on raw state buffers without copying them: "save" pins the buffer
+    that holds the current state, "load" makes a pinned buffer current, "advance" steps
+    out-of-place (lbm_step_raw) into a free buffer of a pool, "adjoint" reads a pinned or the
+    current buffer."""
+
     def __init__(self, u0, omega, rho0, target, model, nsteps, prec, eq_order, schedule, slots,
                  ref_velocity):
         self.model = MODEL_CODES[model] if isinstance(model, str) else int(model)
@@ -132,40 +138,181 @@ class _Run:
         self.sbytes = B.lbm_state_bytes(self.ctx)
         self.abytes = B.lbm_adjoint_bytes(self.ctx)
         self.dev = dev
-        self.saved = {}
+        self.saved = {}          # key -> buffer
+        self.refs = {}           # id(buffer) -> number of keys pinning it
+        # every state buffer the schedule needs, carved out of one allocation up front so that
+        # no device allocation happens inside either sweep
+        n = self.nsteps
+        if schedule == "store_all":
+            need = n + 1
+        elif schedule == "sqrt":
+            K = sqrt_interval(n)
+            need = -(-n // K) + (K - 1) + 4
+        else:
+            need = self.slots + 3
+        self.arena = torch.empty((need, self.sbytes), dtype=torch.uint8, device=dev)
+        self.pool = [self.arena[i] for i in range(need - 1, -1, -1)]  # free buffers
+        self.nbuf = 0
+        self.cur = None          # buffer holding the current state
+        self.cur_step = 0
+        self.q_src, self.q_dst, self.q_step0 = [], [], 0   # queued raw steps
+        self.a_states, self.a_keep = [], []                # queued reverse steps
         self.steps_run = 0       # forward steps, including recomputation
-        self.peak_states = 0     # most raw states held at once
+        self.peak_states = 0     # most state buffers allocated at once
+
+    def _free_buffer(self):
+        self.nbuf += 1
+        self.peak_states = max(self.peak_states, self.nbuf)
+        if self.pool:
+            return self.pool.pop()
+        return torch.empty(self.sbytes, dtype=torch.uint8, device=self.dev)
+
+    def _release_if_unused(self, b):
+        if b is not None and self.refs.get(id(b), 0) == 0 and b is not self.cur:
+            self.pool.append(b)
+            self.nbuf -= 1
+
+    def _pin(self, key, b):
+        old = self.saved.get(key)
+        if old is b:
+            return
+        self.saved[key] = b
+        self.refs[id(b)] = self.refs.get(id(b), 0) + 1
+        if old is not None:
+            self.refs[id(old)] -= 1
+            self._release_if_unused(old)
+
+    def _unpin(self, key):
+        b = self.saved.pop(key)
+        self.refs[id(b)] -= 1
+        self._release_if_unused(b)
 
     def _do(self, act):
         kind = act[0]
         if kind == "save":
-            b = self.saved.get(act[1])
-            if b is None:
-                b = torch.empty(self.sbytes, dtype=torch.uint8, device=self.dev)
-                self.saved[act[1]] = b
-                self.peak_states = max(self.peak_states, len(self.saved))
-            B.lbm_save_state(self.ctx, b.data_ptr())
+            self._pin(act[1], self.cur)
         elif kind == "advance":
-            if act[1] > 0:
-                B.lbm_step(self.ctx, self.model, self.omega, act[1])
-                self.steps_run += act[1]
+            self._flush_adjoints()
+            for _ in range(act[1]):
+                dst = self._free_buffer()
+                if not self.q_src:
+                    self.q_step0 = self.cur_step
+                self.q_src.append(self.cur.data_ptr())
+                self.q_dst.append(dst.data_ptr())
+                prev, self.cur = self.cur, dst
+                self._release_if_unused(prev)
+                self.cur_step += 1
+                self.steps_run += 1
         elif kind == "load":
-            B.lbm_load_state(self.ctx, self.saved[act[1]].data_ptr(), act[2])
+            prev, self.cur = self.cur, self.saved[act[1]]
+            self.cur_step = act[2]
+            self._release_if_unused(prev)
         elif kind == "free":
-            del self.saved[act[1]]
+            self._unpin(act[1])
         elif kind == "adjoint":
-            st = None if act[1] is None else self.saved[act[1]].data_ptr()
-            B.lbm_adjoint_step(self.ctx, self.model, self.omega, st, self.lam[0].data_ptr(),
-                               self.lam[1].data_ptr(), self.domega.data_ptr())
-            self.lam.reverse()
+            self._flush_steps()
+            st = self.cur if act[1] is None else self.saved[act[1]]
+            self.a_states.append(st.data_ptr())
+            self.a_keep.append(st)
         else:
             raise ValueError(kind)
 
+    # Steps and reverse steps are queued and issued in batches (one host call each); buffers
+    # released meanwhile may be reused by later queued work because everything runs in stream
+    # order on one stream.
+    def _flush_steps(self):
+        if self.q_src:
+            B.lbm_step_raw_many(self.ctx, self.model, self.omega, self.q_src, self.q_dst, self.q_step0)
+            self.q_src, self.q_dst = [], []
+
+    def _flush_adjoints(self):
+        if self.a_states:
+            lam = [self.lam[k % 2].data_ptr() for k in range(len(self.a_states) + 1)]
+            # gradients stay pending in the per-block sums until the end of the sweep, so every
+            # schedule sums them in the same (step) order
+            B.lbm_adjoint_many(self.ctx, self.model, self.omega, self.a_states, lam, None)
+            if len(self.a_states) % 2:
+                self.lam.reverse()
+            self.a_states, self.a_keep = [], []
+
+    def _flush(self):
+        self._flush_steps()
+        self._flush_adjoints()
+
+    # Fast paths: the sqrt(n) and store-all sweeps issue whole segments with two host calls
+    # (lbm_step_raw_many / lbm_adjoint_many); they run exactly the kernels, in exactly the order,
+    # that the generic action executor (used for "revolve") would.
+    def _forward_fast(self):
+        n = self.nsteps
+        K = n if self.schedule == "store_all" else sqrt_interval(n)
+        keep = {}
+        bufs = [self.cur]
+        for t in range(1, n + 1):
+            bufs.append(self._free_buffer() if (self.schedule == "store_all" or t % K == 0 or t == n)
+                        else None)
+        # scratch ping-pong for states that are not kept
+        scratch = [self._free_buffer(), self._free_buffer()] if self.schedule == "sqrt" else []
+        src, dst = [], []
+        prev = bufs[0]
+        for t in range(1, n + 1):
+            b = bufs[t] if bufs[t] is not None else scratch[t % 2]
+            src.append(prev.data_ptr())
+            dst.append(b.data_ptr())
+            prev = b
+        B.lbm_step_raw_many(self.ctx, self.model, self.omega, src, dst, 0)
+        self.steps_run += n
+        if self.schedule == "store_all":
+            for t in range(n):
+                keep[("s", t)] = bufs[t]
+        else:
+            for t in range(0, n, K):
+                keep[("c", t)] = bufs[t]
+            self.pool.extend(scratch)
+            self.nbuf -= len(scratch)
+        for k, b in keep.items():
+            self._pin(k, b)
+        self.cur = bufs[n]
+
+    def _backward_fast(self):
+        n = self.nsteps
+        lam = self.lam
+        if self.schedule == "store_all":
+            states = [self.saved[("s", t)].data_ptr() for t in range(n - 1, -1, -1)]
+            ptrs = [lam[k % 2].data_ptr() for k in range(n + 1)]
+            B.lbm_adjoint_many(self.ctx, self.model, self.omega, states, ptrs, None)
+            if n % 2:
+                lam.reverse()
+            return
+        K = sqrt_interval(n)
+        ring = [self._free_buffer() for _ in range(K - 1)]
+        for s0 in reversed(range(0, n, K)):
+            m = min(s0 + K, n) - s0
+            seg = [self.saved[("c", s0)]] + ring[:m - 1]
+            if m > 1:
+                B.lbm_step_raw_many(self.ctx, self.model, self.omega, [b.data_ptr() for b in seg[:-1]],
+                                    [b.data_ptr() for b in seg[1:]], s0)
+                self.steps_run += m - 1
+            states = [b.data_ptr() for b in reversed(seg)]
+            ptrs = [lam[k % 2].data_ptr() for k in range(m + 1)]
+            B.lbm_adjoint_many(self.ctx, self.model, self.omega, states, ptrs, None)
+            if m % 2:
+                lam.reverse()
+        self.pool.extend(ring)
+        self.nbuf -= len(ring)
+
     def forward(self):
-        for act in forward_actions(self.nsteps, self.schedule):
-            self._do(act)
-        self.final = torch.empty(self.sbytes, dtype=torch.uint8, device=self.dev)
-        B.lbm_save_state(self.ctx, self.final.data_ptr())
+        self.cur = self._free_buffer()
+        B.lbm_save_state(self.ctx, self.cur.data_ptr())  # the initial state f^eq(rho0, u0)
+        self.cur_step = 0
+        if self.schedule in ("sqrt", "store_all"):
+            self._forward_fast()
+        else:
+            for act in forward_actions(self.nsteps, self.schedule):
+                self._do(act)
+            self._flush()
+        self.final = self.cur
+        self.refs[id(self.final)] = self.refs.get(id(self.final), 0) + 1  # keep it
+        B.lbm_load_state(self.ctx, self.final.data_ptr(), self.nsteps)
         self.lam = [torch.empty(self.abytes, dtype=torch.uint8, device=self.dev) for _ in range(2)]
         self.loss = B.lbm_adjoint_seed_velocity_l2(self.ctx, self.tx.data_ptr(), self.ty.data_ptr(),
                                                    self.lam[0].data_ptr())
@@ -173,19 +320,24 @@ class _Run:
 
     def backward(self):
         self.domega = torch.zeros(5, dtype=torch.float64, device=self.dev)
-        for act in backward_actions(self.nsteps, self.schedule, self.slots):
-            self._do(act)
+        if self.schedule in ("sqrt", "store_all"):
+            self._backward_fast()
+        else:
+            for act in backward_actions(self.nsteps, self.schedule, self.slots):
+                self._do(act)
+            self._flush()
+        B.lbm_adjoint_flush(self.ctx, self.domega.data_ptr())
         dux = torch.empty_like(self.ux0)
         duy = torch.empty_like(self.uy0)
         B.lbm_eq_vjp(self.ctx, self.rho0.data_ptr(), self.ux0.data_ptr(), self.uy0.data_ptr(),
                      self.lam[0].data_ptr(), dux.data_ptr(), duy.data_ptr())
-        # leave the context at the final state
-        B.lbm_load_state(self.ctx, self.final.data_ptr(), self.nsteps)
         torch.cuda.current_stream(self.dev).synchronize()
         return torch.stack([dux, duy]), self.domega.clone()
 
     def close(self):
         self.saved.clear()
+        self.pool.clear()
+        self.cur = self.final = self.arena = None
         self.sim.close()
 
 

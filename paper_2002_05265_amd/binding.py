@@ -27,7 +27,8 @@ EXPORTS = (
     "lbm_last_error",
     "lbm_batch_population_bytes", "lbm_batch_create", "lbm_batch_run", "lbm_batch_status",
     "lbm_batch_get_state", "lbm_batch_set_launch", "lbm_batch_autotune", "lbm_batch_destroy",
-    "lbm_state_bytes", "lbm_adjoint_bytes", "lbm_save_state", "lbm_load_state",
+    "lbm_state_bytes", "lbm_adjoint_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_raw",
+    "lbm_step_raw_many", "lbm_adjoint_many", "lbm_adjoint_flush",
     "lbm_adjoint_seed_velocity_l2", "lbm_adjoint_step", "lbm_eq_vjp",
 )
 
@@ -78,6 +79,10 @@ def _declare(L: ctypes.CDLL):
         "lbm_adjoint_bytes": (_sz, [_vp]),
         "lbm_save_state": (_i, [_vp, _vp]),
         "lbm_load_state": (_i, [_vp, _vp, _ll]),
+        "lbm_step_raw": (_i, [_vp, _i, _dp, _vp, _vp, _ll]),
+        "lbm_step_raw_many": (_i, [_vp, _i, _dp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i, _ll]),
+        "lbm_adjoint_many": (_i, [_vp, _i, _dp, ctypes.POINTER(_vp), _i, ctypes.POINTER(_vp), _vp]),
+        "lbm_adjoint_flush": (_i, [_vp, _vp]),
         "lbm_adjoint_seed_velocity_l2": (_i, [_vp, _vp, _vp, _vp, _dp]),
         "lbm_adjoint_step": (_i, [_vp, _i, _dp, _vp, _vp, _vp, _vp]),
         "lbm_eq_vjp": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -249,6 +254,28 @@ def lbm_save_state(ctx: int, dst: int):
 
 def lbm_load_state(ctx: int, src: int, step: int):
     _check(lib().lbm_load_state(ctx, src, step), "lbm_load_state")
+
+
+def lbm_step_raw(ctx: int, model: int, omega, src: int, dst: int, step: int):
+    _check(lib().lbm_step_raw(ctx, model, _omega(omega), src, dst, step), "lbm_step_raw")
+
+
+def _ptrs(seq):
+    return (_vp * max(1, len(seq)))(*[int(p) for p in seq])
+
+
+def lbm_step_raw_many(ctx: int, model: int, omega, src, dst, step0: int):
+    _check(lib().lbm_step_raw_many(ctx, model, _omega(omega), _ptrs(src), _ptrs(dst), len(src), step0),
+           "lbm_step_raw_many")
+
+
+def lbm_adjoint_many(ctx: int, model: int, omega, states, lam, domega: int | None):
+    _check(lib().lbm_adjoint_many(ctx, model, _omega(omega), _ptrs(states), len(states), _ptrs(lam),
+                                  domega or None), "lbm_adjoint_many")
+
+
+def lbm_adjoint_flush(ctx: int, domega: int):
+    _check(lib().lbm_adjoint_flush(ctx, domega), "lbm_adjoint_flush")
 
 
 def lbm_adjoint_seed_velocity_l2(ctx: int, ux_t: int, uy_t: int, lam: int) -> float:

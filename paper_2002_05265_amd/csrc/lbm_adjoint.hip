@@ -2,8 +2,9 @@
 //
 // One reverse step reads f_n (pull from the raw state, exactly as the forward step does),
 // lambda_{n+1} at x + xi_i (transpose of the streaming permutation) and writes lambda_n at x:
-// 27 stored values per node, no atomics.  The rate gradients are reduced per block in FP64 and
-// summed into the caller's accumulator in a fixed order.
+// 27 stored values per node, no atomics.  The rate gradients are reduced per block in FP64,
+// accumulated per block over the steps of one call, and summed into the caller's accumulator
+// in a fixed order at the end of the call.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -39,13 +40,39 @@ __device__ __forceinline__ void push_gather(const T* __restrict__ lam, long long
     mu[8] = R(lam[8 * plane + n.rm + n.xp]);
 }
 
+// Per-block rate-gradient slots: block b adds (accumulate = 1) or writes (0) its FP64 block sum
+// to slot b.  A slot is touched by one block per launch and launches are stream-ordered, so no
+// atomics or fences are needed; one k_finalize_add per host call folds the slots into domega.
+__device__ __forceinline__ void block_accumulate(double (&v)[5], double* __restrict__ slots, int accumulate) {
+    __shared__ double tot[5];
+    block_sum<5>(v, tot);
+    __syncthreads();
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        double* p = slots + 5 * (size_t)(blockIdx.y * gridDim.x + blockIdx.x);
+        for (int k = 0; k < 5; ++k) p[k] = (accumulate ? p[k] : 0.0) + tot[k];
+    }
+}
+
+// out[k] += sum over blocks of slots[5 b + k] (one block, fixed order).
+__global__ __launch_bounds__(256) void k_finalize_add(const double* __restrict__ slots, int nblocks,
+                                                      double* __restrict__ out) {
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+        for (int k = 0; k < 5; ++k) v[k] += slots[5 * (size_t)b + k];
+    __shared__ double tot[5];
+    block_sum<5>(v, tot);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 5; ++k) out[k] += tot[k];
+}
+
 template <int MODEL, int PREC>
 __global__ __launch_bounds__(256) void k_adjoint_step(const typename Store<PREC>::S* __restrict__ state,
                                                       const typename AdjT<PREC>::T* __restrict__ lam_next,
                                                       typename AdjT<PREC>::T* __restrict__ lam, Geom g,
                                                       Coef<typename Store<PREC>::R> c,
                                                       Ref<typename Store<PREC>::R> ref, int N,
-                                                      double* __restrict__ partials) {
+                                                      double* __restrict__ slots, int accumulate) {
     using R = typename Store<PREC>::R;
     using T = typename AdjT<PREC>::T;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -65,21 +92,9 @@ __global__ __launch_bounds__(256) void k_adjoint_step(const typename Store<PREC>
         for (int i = 0; i < 9; ++i) lam[i * g.plane + o] = T(hb[i]);
         omega_adjoint(cb, wb);
     }
-    block_sum<5>(wb, partials + 5 * (size_t)(blockIdx.y * gridDim.x + blockIdx.x));
+    block_accumulate(wb, slots, accumulate);
 }
 
-// out[k] += sum over blocks of partials[5 b + k] (one block, fixed order).
-__global__ __launch_bounds__(256) void k_finalize_add(const double* __restrict__ partials, int nblocks,
-                                                      double* __restrict__ out) {
-    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
-        for (int k = 0; k < 5; ++k) v[k] += partials[5 * (size_t)b + k];
-    __shared__ double tot[5];
-    block_sum<5>(v, tot);
-    __syncthreads();
-    if (threadIdx.x == 0 && threadIdx.y == 0)
-        for (int k = 0; k < 5; ++k) out[k] += tot[k];
-}
 
 // Velocity of the current state in FP64 (pull).
 template <int PREC>
@@ -159,7 +174,8 @@ __global__ __launch_bounds__(256) void k_eq_vjp(Geom g, Ref<double> ref, int N, 
 }
 
 template <int MODEL, int PREC>
-void launch_adj_t(lbm_ctx* ctx, const double* w, const void* state, const void* lam_next, void* lam) {
+void launch_adj_t(lbm_ctx* ctx, const double* w, const void* state, const void* lam_next, void* lam,
+                  int accumulate) {
     using S = typename Store<PREC>::S;
     using R = typename Store<PREC>::R;
     using T = typename AdjT<PREC>::T;
@@ -167,22 +183,22 @@ void launch_adj_t(lbm_ctx* ctx, const double* w, const void* state, const void* 
     hipLaunchKernelGGL((k_adjoint_step<MODEL, PREC>), l.grid, l.block, 0, ctx->stream,
                        reinterpret_cast<const S*>(state), reinterpret_cast<const T*>(lam_next),
                        reinterpret_cast<T*>(lam), ctx->geom(), make_coef<R>(w), ref_as<R>(ctx->ref),
-                       ctx->eq_order, ctx->d_part);
+                       ctx->eq_order, ctx->d_wslots, accumulate);
 }
 
 template <int PREC>
 void launch_adj_p(lbm_ctx* ctx, int model, const double* w, const void* state, const void* lam_next,
-                  void* lam) {
+                  void* lam, int accumulate) {
     switch (model) {
-        case LBM_BGK: launch_adj_t<kBGK, PREC>(ctx, w, state, lam_next, lam); break;
-        case LBM_RM: launch_adj_t<kRM, PREC>(ctx, w, state, lam_next, lam); break;
-        case LBM_HM: launch_adj_t<kHM, PREC>(ctx, w, state, lam_next, lam); break;
-        case LBM_CM: launch_adj_t<kCM, PREC>(ctx, w, state, lam_next, lam); break;
-        case LBM_CHM: launch_adj_t<kCHM, PREC>(ctx, w, state, lam_next, lam); break;
-        case LBM_K: launch_adj_t<kK, PREC>(ctx, w, state, lam_next, lam); break;
-        case LBM_PR: launch_adj_t<kPR, PREC>(ctx, w, state, lam_next, lam); break;
-        case LBM_RR: launch_adj_t<kRR, PREC>(ctx, w, state, lam_next, lam); break;
-        default: launch_adj_t<kStreamOnly, PREC>(ctx, w, state, lam_next, lam); break;
+        case LBM_BGK: launch_adj_t<kBGK, PREC>(ctx, w, state, lam_next, lam, accumulate); break;
+        case LBM_RM: launch_adj_t<kRM, PREC>(ctx, w, state, lam_next, lam, accumulate); break;
+        case LBM_HM: launch_adj_t<kHM, PREC>(ctx, w, state, lam_next, lam, accumulate); break;
+        case LBM_CM: launch_adj_t<kCM, PREC>(ctx, w, state, lam_next, lam, accumulate); break;
+        case LBM_CHM: launch_adj_t<kCHM, PREC>(ctx, w, state, lam_next, lam, accumulate); break;
+        case LBM_K: launch_adj_t<kK, PREC>(ctx, w, state, lam_next, lam, accumulate); break;
+        case LBM_PR: launch_adj_t<kPR, PREC>(ctx, w, state, lam_next, lam, accumulate); break;
+        case LBM_RR: launch_adj_t<kRR, PREC>(ctx, w, state, lam_next, lam, accumulate); break;
+        default: launch_adj_t<kStreamOnly, PREC>(ctx, w, state, lam_next, lam, accumulate); break;
     }
 }
 
@@ -271,19 +287,46 @@ int lbm_adjoint_step(lbm_ctx* ctx, int model, const double* omega, const void* s
                      const void* lam_next, void* lam, double* domega) {
     if (!ctx) return set_error(LBM_ESTATE, "context is NULL");
     if (!lam_next || !lam || !domega) return set_error(LBM_EINVAL, "NULL pointer");
-    if (lam_next == lam) return set_error(LBM_EINVAL, "lam must not alias lam_next");
+    const void* st = state ? state : ctx->copy(ctx->cur);
+    void* lams[2] = {const_cast<void*>(lam_next), lam};
+    return lbm_adjoint_many(ctx, model, omega, &st, 1, lams, domega);
+}
+
+int lbm_adjoint_many(lbm_ctx* ctx, int model, const double* omega, const void* const* states,
+                     int count, void* const* lam, double* domega) {
+    if (!ctx) return set_error(LBM_ESTATE, "context is NULL");
+    if (count < 0) return set_error(LBM_EINVAL, "count %d < 0", count);
+    if (count > 0 && (!states || !lam)) return set_error(LBM_EINVAL, "NULL pointer array");
+    for (int k = 0; k < count; ++k)
+        if (!states[k] || !lam[k] || !lam[k + 1] || lam[k] == lam[k + 1])
+            return set_error(LBM_EINVAL, "bad pointer at reverse step %d", k);
     int rc = validate_model(model, ctx->eq_order);
     if (rc == LBM_OK) rc = validate_omega(omega);
     if (rc != LBM_OK) return rc;
-    const void* st = state ? state : ctx->copy(ctx->cur);
-    switch (ctx->prec) {
-        case LBM_F64: launch_adj_p<kF64>(ctx, model, omega, st, lam_next, lam); break;
-        case LBM_F32_SHIFTED: launch_adj_p<kF32>(ctx, model, omega, st, lam_next, lam); break;
-        default: launch_adj_p<kF16>(ctx, model, omega, st, lam_next, lam); break;
+    if (!ctx->d_wslots) {
+        rc = check_hip(hipMalloc(&ctx->d_wslots, sizeof(double) * 5 * (size_t)ctx->nblocks), "hipMalloc(slots)");
+        if (rc != LBM_OK) return rc;
+    }
+    for (int k = 0; k < count; ++k) {
+        const int acc = ctx->wslots_live ? 1 : 0;
+        switch (ctx->prec) {
+            case LBM_F64: launch_adj_p<kF64>(ctx, model, omega, states[k], lam[k], lam[k + 1], acc); break;
+            case LBM_F32_SHIFTED: launch_adj_p<kF32>(ctx, model, omega, states[k], lam[k], lam[k + 1], acc); break;
+            default: launch_adj_p<kF16>(ctx, model, omega, states[k], lam[k], lam[k + 1], acc); break;
+        }
+        ctx->wslots_live = true;
     }
     rc = check_hip(hipGetLastError(), "adjoint kernel launch");
-    if (rc != LBM_OK) return rc;
-    hipLaunchKernelGGL(k_finalize_add, dim3(1), dim3(256), 0, ctx->stream, ctx->d_part, ctx->nblocks, domega);
+    if (rc != LBM_OK || !domega) return rc;
+    return lbm_adjoint_flush(ctx, domega);
+}
+
+int lbm_adjoint_flush(lbm_ctx* ctx, double* domega) {
+    if (!ctx) return set_error(LBM_ESTATE, "context is NULL");
+    if (!domega) return set_error(LBM_EINVAL, "domega is NULL");
+    if (!ctx->wslots_live) return LBM_OK;
+    hipLaunchKernelGGL(k_finalize_add, dim3(1), dim3(256), 0, ctx->stream, ctx->d_wslots, ctx->nblocks, domega);
+    ctx->wslots_live = false;
     return check_hip(hipGetLastError(), "adjoint reduction launch");
 }
 

@@ -230,6 +230,44 @@ void launch_step_r(lbm_ctx* ctx, const StepShape& sh, const Coef<typename Store<
                        ctx->eq_order, (int)ctx->step, ctx->d_flag, sh.gx, nb, sh.xcd);
 }
 
+template <int MODEL, int PREC, int ROWS>
+void launch_step_raw_r(lbm_ctx* ctx, const StepShape& sh, const Coef<typename Store<PREC>::R>& c,
+                       const void* src, void* dst, int step) {
+    using S = typename Store<PREC>::S;
+    const unsigned nb = sh.gx * sh.gy;
+    hipLaunchKernelGGL((k_step<MODEL, PREC, ROWS>), dim3(nb), dim3(sh.bw, sh.bh), 0, ctx->stream,
+                       reinterpret_cast<const S*>(src), reinterpret_cast<S*>(dst), ctx->geom(), c,
+                       ref_as<typename Store<PREC>::R>(ctx->ref), ctx->eq_order, step,
+                       ctx->d_flag, sh.gx, nb, sh.xcd);
+}
+
+template <int MODEL, int PREC>
+void launch_step_raw_t(lbm_ctx* ctx, const StepShape& sh, const Coef<typename Store<PREC>::R>& c,
+                       const void* src, void* dst, int step) {
+    switch (sh.rows) {
+        case 4: launch_step_raw_r<MODEL, PREC, 4>(ctx, sh, c, src, dst, step); break;
+        case 2: launch_step_raw_r<MODEL, PREC, 2>(ctx, sh, c, src, dst, step); break;
+        default: launch_step_raw_r<MODEL, PREC, 1>(ctx, sh, c, src, dst, step); break;
+    }
+}
+
+template <int PREC>
+void launch_step_raw_p(lbm_ctx* ctx, int model, const double* w, const StepShape& sh, const void* src,
+                       void* dst, int step) {
+    const Coef<typename Store<PREC>::R> c = make_coef<typename Store<PREC>::R>(w);
+    switch (model) {
+        case LBM_BGK: launch_step_raw_t<kBGK, PREC>(ctx, sh, c, src, dst, step); break;
+        case LBM_RM: launch_step_raw_t<kRM, PREC>(ctx, sh, c, src, dst, step); break;
+        case LBM_HM: launch_step_raw_t<kHM, PREC>(ctx, sh, c, src, dst, step); break;
+        case LBM_CM: launch_step_raw_t<kCM, PREC>(ctx, sh, c, src, dst, step); break;
+        case LBM_CHM: launch_step_raw_t<kCHM, PREC>(ctx, sh, c, src, dst, step); break;
+        case LBM_K: launch_step_raw_t<kK, PREC>(ctx, sh, c, src, dst, step); break;
+        case LBM_PR: launch_step_raw_t<kPR, PREC>(ctx, sh, c, src, dst, step); break;
+        case LBM_RR: launch_step_raw_t<kRR, PREC>(ctx, sh, c, src, dst, step); break;
+        default: launch_step_raw_t<kStreamOnly, PREC>(ctx, sh, c, src, dst, step); break;
+    }
+}
+
 template <int MODEL, int PREC>
 void launch_step_t(lbm_ctx* ctx, const StepShape& sh, const Coef<typename Store<PREC>::R>& c,
                    int src_copy) {
@@ -415,6 +453,39 @@ int lbm_step(lbm_ctx* ctx, int model, const double* omega, int nsteps) {
     return check_hip(hipGetLastError(), "step kernel launch");
 }
 
+int lbm_step_raw(lbm_ctx* ctx, int model, const double* omega, const void* src, void* dst,
+                 long long step) {
+    if (!ctx) return set_error(LBM_ESTATE, "context is NULL");
+    if (!src || !dst) return set_error(LBM_EINVAL, "NULL state pointer");
+    if (src == dst) return set_error(LBM_EINVAL, "src and dst must differ");
+    if (step < 0 || step >= INT_MAX) return set_error(LBM_EINVAL, "step %lld out of range", step);
+    int rc = validate_model(model, ctx->eq_order);
+    if (rc == LBM_OK) rc = validate_omega(omega);
+    if (rc != LBM_OK) return rc;
+    LBM_DISPATCH_PREC(ctx->prec, launch_step_raw_p, ctx, model, omega, ctx->shape_of(model), src, dst,
+                      (int)step);
+    return check_hip(hipGetLastError(), "raw step kernel launch");
+}
+
+int lbm_step_raw_many(lbm_ctx* ctx, int model, const double* omega, const void* const* src,
+                      void* const* dst, int count, long long step0) {
+    if (!ctx) return set_error(LBM_ESTATE, "context is NULL");
+    if (count < 0) return set_error(LBM_EINVAL, "count %d < 0", count);
+    if (count == 0) return LBM_OK;
+    if (!src || !dst) return set_error(LBM_EINVAL, "NULL pointer array");
+    if (step0 < 0 || step0 + count >= INT_MAX) return set_error(LBM_EINVAL, "step %lld out of range", step0);
+    for (int k = 0; k < count; ++k)
+        if (!src[k] || !dst[k] || src[k] == dst[k])
+            return set_error(LBM_EINVAL, "bad state pointer at step %d", k);
+    int rc = validate_model(model, ctx->eq_order);
+    if (rc == LBM_OK) rc = validate_omega(omega);
+    if (rc != LBM_OK) return rc;
+    const StepShape sh = ctx->shape_of(model);
+    for (int k = 0; k < count; ++k)
+        LBM_DISPATCH_PREC(ctx->prec, launch_step_raw_p, ctx, model, omega, sh, src[k], dst[k], (int)(step0 + k));
+    return check_hip(hipGetLastError(), "raw step kernel launch");
+}
+
 int lbm_moments(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* totals) {
     if (!ctx) return set_error(LBM_ESTATE, "context is NULL");
     LBM_DISPATCH_PREC(ctx->prec, launch_moments_p, ctx, rho, ux, uy);
@@ -525,6 +596,7 @@ void lbm_destroy(lbm_ctx* ctx) {
     if (ctx->d_flag) (void)hipFree(ctx->d_flag);
     if (ctx->d_part) (void)hipFree(ctx->d_part);
     if (ctx->d_tot) (void)hipFree(ctx->d_tot);
+    if (ctx->d_wslots) (void)hipFree(ctx->d_wslots);
     delete ctx;
 }
 

@@ -291,8 +291,10 @@ struct lbm_ctx {
     int device = 0;
     int nblocks = 0;              // blocks of the per-cell launch
     int* d_flag = nullptr;        // first bad step (INT_MAX = none)
-    double* d_part = nullptr;     // per-block partial sums, 5 per block
+    double* d_part = nullptr;     // per-block partial sums, 5 per block (reduction scratch)
     double* d_tot = nullptr;      // 5 totals
+    double* d_wslots = nullptr;   // adjoint: per-block pending rate-gradient sums, 5 per block
+    bool wslots_live = false;     // d_wslots holds pending sums
 
     int rows[9] = {LBM_DEFAULT_ROWS, LBM_DEFAULT_ROWS, LBM_DEFAULT_ROWS, LBM_DEFAULT_ROWS,
                    LBM_DEFAULT_ROWS, LBM_DEFAULT_ROWS, LBM_DEFAULT_ROWS, LBM_DEFAULT_ROWS,
