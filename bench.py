@@ -19,10 +19,49 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E spec
+ROOT = os.path.dirname(os.path.abspath(__file__))
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+# the sources the plain step kernel is compiled from: a measured traffic figure is reported only
+# while these are unchanged since the counters were taken
+STEP_SOURCES = ("paper_2002_05265_amd/csrc/lbm_core.hip", "paper_2002_05265_amd/csrc/lbm_cell.hpp",
+                "paper_2002_05265_amd/csrc/lbm_internal.hpp", "paper_2002_05265_amd/build.py")
+MODEL_ORDER = ("BGK", "RM", "HM", "CM", "CHM", "K", "PR", "RR")
+PREC_CODE = {"f64": 0, "f32": 1, "f16": 2}
 
 
 def bytes_per_cell(prec: str) -> int:
     return 18 * {"f64": 8, "f32": 4, "f16": 2}[prec]
+
+
+def step_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in STEP_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(rel.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def step_kernel_key(model: str, prec: str) -> str:
+    """Template arguments of the plain step kernel as they appear in a kernel trace."""
+    return f"k_step<{MODEL_ORDER.index(model)}, {PREC_CODE[prec]}, "
+
+
+def measured_traffic(model: str, prec: str):
+    """HBM bytes per launch of the step kernel from the committed counter summary, or None when
+    there is none for this kernel or its sources changed since it was taken."""
+    path = os.path.join(PROFILE_DIR, f"k_step_{prec}_dsl4096_counters.md")
+    try:
+        with open(path) as fh:
+            text = fh.read()
+        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if blob.get("step_source_hash") != step_source_hash():
+        return None
+    rec = blob.get("per_launch", {}).get(model)
+    return None if rec is None else rec["hbm_bytes"]
 
 
 def cpu_baseline(models, budget_s: float = 16.0):
@@ -136,6 +175,35 @@ def batched_sweep(steps: int, plain_f64_mlups: float, n_inst: int = 512):
             "precision": "f64"}
 
 
+def precision_errors(n: int = 4096, steps: int = 5000, models=("CM", "K")):
+    """Shifted FP32 and FP16 storage against FP64 on the double shear layer: relative L2 error
+    of the velocity field after `steps` steps (same initial fields, rates and model)."""
+    import torch
+
+    from paper_2002_05265_amd import inputs
+    from paper_2002_05265_amd.sim import Sim
+
+    mach = 0.1
+    omega = inputs.rates(inputs.dsl_nu(n, mach), "REG")
+    rho, ux, uy = inputs.dsl_fields(n, n, mach)
+    out = {}
+    for m in models:
+        u = {}
+        for p in ("f64", "f32", "f16"):
+            s = Sim(rho, ux, uy, prec=p, eq_order=4, device="cuda:0")
+            s.step(m, omega, steps)
+            _, vx, vy, _ = s.moments()
+            u[p] = torch.stack([vx, vy])
+            s.close()
+            del s
+        norm = float(torch.linalg.vector_norm(u["f64"]))
+        out[m] = {p: float(torch.linalg.vector_norm(u[p] - u["f64"])) / norm for p in ("f32", "f16")}
+        del u
+        torch.cuda.empty_cache()
+    return {"workload": f"double shear layer {n}x{n}, Ma 0.1, Re 3e4, REG, {steps} steps",
+            "l2_velocity_error_vs_f64": out}
+
+
 def adjoint_run(n: int = 512, steps: int = 2000, prec: str = "f32"):
     """Vortex-transport gradient: n x n CM convected vortex (Ma 0.2, nu 1e-5, REG rates),
     L = ||u_T - u_target||_2 after `steps`, gradients w.r.t. the initial velocity field and the
@@ -166,7 +234,14 @@ def adjoint_run(n: int = 512, steps: int = 2000, prec: str = "f32"):
     torch.cuda.synchronize()
     plain_s = e[0].elapsed_time(e[1]) * 1e-3
     sim.close()
-    run = _Run(u0, omega, torch.tensor(rho, device=dev), tgt, "CM", steps, prec, 4, "sqrt", 0, uref)
+    rho_d = torch.tensor(rho, device=dev)
+    # untimed warm-up sweep: first use of every kernel (and of torch's fill kernels) loads code
+    # objects, a one-time host cost
+    warm = _Run(u0, omega, rho_d, tgt, "CM", 16, prec, 4, "sqrt", 0, uref)
+    warm.forward()
+    warm.backward()
+    warm.close()
+    run = _Run(u0, omega, rho_d, tgt, "CM", steps, prec, 4, "sqrt", 0, uref)
     torch.cuda.synchronize()
     e[0].record()
     loss = run.forward()
@@ -193,6 +268,109 @@ def adjoint_run(n: int = 512, steps: int = 2000, prec: str = "f32"):
             "cache_resident": True, **stats}
 
 
+def _csv_rows(path):
+    import csv
+
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _find_csv(d, suffix):
+    for f in sorted(os.listdir(d)):
+        if f.endswith(suffix):
+            return os.path.join(d, f)
+    raise FileNotFoundError(f"no *{suffix} under {d}")
+
+
+def _per_dispatch(rows, key):
+    """Mean counter value (KiB) per dispatch of every kernel whose name contains key."""
+    vals = [float(r["Counter_Value"]) for r in rows if key in r["Kernel_Name"]]
+    return (sum(vals) / len(vals), len(vals)) if vals else (None, 0)
+
+
+def profile_summary(out_root: str, prec: str, n: int, commands: dict):
+    """Write the kernel-trace and HBM-counter summaries of the bench workload under profiles/.
+
+    out_root holds the rocprofv3 output directories rp_trace, rp_fetch, rp_write,
+    rp_copy_fetch and rp_copy_write (csv format) written by the commands in `commands`."""
+    os.makedirs(PROFILE_DIR, exist_ok=True)
+    stats = _csv_rows(_find_csv(os.path.join(out_root, "rp_trace"), "kernel_stats.csv"))
+    cells = n * n
+    alg = cells * bytes_per_cell(prec)
+    lines = [f"# k_step ({prec}, {n}x{n} double shear layer): kernel trace", "",
+             "Command (from the repository root, with `cd /tmp && export TMPDIR=/tmp` semantics for",
+             "the profiler's scratch files):", "", "```", commands["trace"], "```", "",
+             f"Algorithmic bytes per launch: {n}*{n} nodes * 18 * {bytes_per_cell(prec) // 18} B = {alg} B.",
+             "", "| kernel | calls | average us | min us | max us | GB/s at algorithmic bytes |",
+             "|---|---|---|---|---|---|"]
+    for r in stats:
+        name = r["Name"]
+        short = name.replace("(anonymous namespace)::", "").replace("void ", "", 1).split("(")[0][:70]
+        avg = float(r["AverageNs"]) * 1e-3
+        gbs = ""
+        for m in MODEL_ORDER:
+            if step_kernel_key(m, prec) in name:
+                gbs = f"{alg / (avg * 1e-6) / 1e9:.1f}"
+                short = f"k_step<{m}, {prec}>"
+        lines.append(f"| {short} | {r['Calls']} | {avg:.2f} | {float(r['MinNs']) * 1e-3:.2f} | "
+                     f"{float(r['MaxNs']) * 1e-3:.2f} | {gbs} |")
+    with open(os.path.join(PROFILE_DIR, f"k_step_{prec}_dsl4096_trace.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+    fetch = _csv_rows(_find_csv(os.path.join(out_root, "rp_fetch"), "counter_collection.csv"))
+    write = _csv_rows(_find_csv(os.path.join(out_root, "rp_write"), "counter_collection.csv"))
+    cfetch = _csv_rows(_find_csv(os.path.join(out_root, "rp_copy_fetch"), "counter_collection.csv"))
+    cwrite = _csv_rows(_find_csv(os.path.join(out_root, "rp_copy_write"), "counter_collection.csv"))
+    copy_key = "copyBuffer"  # the runtime's device-to-device copy kernel behind the 1 GiB copy
+    cf, _ = _per_dispatch(cfetch, copy_key)
+    cw, _ = _per_dispatch(cwrite, copy_key)
+    gib_kib = (1 << 30) / 1024
+    fscale, wscale = gib_kib / cf, gib_kib / cw
+    per_launch = {}
+    rows = ["| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) | / algorithmic |",
+            "|---|---|---|---|---|---|"]
+    for m in MODEL_ORDER:
+        key = step_kernel_key(m, prec)
+        f_kib, nf = _per_dispatch(fetch, key)
+        w_kib, _ = _per_dispatch(write, key)
+        if f_kib is None or w_kib is None:
+            continue
+        hbm = f_kib * 1024 * fscale + w_kib * 1024 * wscale
+        per_launch[m] = {"fetch_kib": round(f_kib, 1), "write_kib": round(w_kib, 1),
+                         "hbm_bytes": int(round(hbm)), "vs_algorithmic": round(hbm / alg, 4)}
+        rows.append(f"| k_step<{m}, {prec}> | {nf} | {f_kib:.1f} | {w_kib:.1f} | {hbm:.4g} | {hbm / alg:.4f} |")
+    blob = {"step_source_hash": step_source_hash(), "prec": prec, "n": n, "algorithmic_bytes": alg,
+            "copy_probe_kib": {"fetch": round(cf, 1), "write": round(cw, 1), "true": gib_kib},
+            "scale": {"fetch": round(fscale, 4), "write": round(wscale, 4)}, "per_launch": per_launch}
+    text = [f"# k_step ({prec}, {n}x{n} double shear layer): HBM counters", "",
+            "Commands (each counter in a run of its own):", "", "```", commands["fetch"], commands["write"],
+            commands["copy_fetch"], commands["copy_write"], "```", "",
+            "Calibration: a plain device copy of 1 GiB (torch, same box) reads "
+            f"{cf:.1f} KiB of FETCH_SIZE and {cw:.1f} KiB of WRITE_SIZE per dispatch against "
+            f"{gib_kib:.0f} KiB moved each way, so FETCH_SIZE is scaled by {fscale:.4f} and "
+            f"WRITE_SIZE by {wscale:.4f}.", "", *rows, "",
+            "Machine-readable (bench.py reports `roofline.traffic` from this block while the step "
+            "kernel's sources hash to `step_source_hash`):", "", "```json", json.dumps(blob, indent=1), "```", ""]
+    with open(os.path.join(PROFILE_DIR, f"k_step_{prec}_dsl4096_counters.md"), "w") as fh:
+        fh.write("\n".join(text))
+    print(json.dumps(blob), flush=True)
+
+
+PROFILE_ARGS = "--steps 20 --warmup 2 --no-cpu --no-extras"
+PROFILE_COMMANDS = {
+    "trace": f"rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/rp_trace -o bench -- "
+             f"python bench.py {PROFILE_ARGS}",
+    "fetch": f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/rp_fetch -o bench -- "
+             f"python bench.py {PROFILE_ARGS}",
+    "write": f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/rp_write -o bench -- "
+             f"python bench.py {PROFILE_ARGS}",
+    "copy_fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/rp_copy_fetch -o copy -- "
+                  "python bench.py --copy-probe",
+    "copy_write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/rp_copy_write -o copy -- "
+                  "python bench.py --copy-probe",
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,7 +385,13 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FP64/FP16, batched and adjoint measurements")
     ap.add_argument("--batch-steps", type=int, default=20000)
+    ap.add_argument("--profile-summary", metavar="DIR",
+                    help="summarise the rocprofv3 csv output of PROFILE_COMMANDS found under DIR "
+                         "into profiles/ (no GPU use)")
     args = ap.parse_args()
+    if args.profile_summary:
+        profile_summary(args.profile_summary, args.prec, args.n, PROFILE_COMMANDS)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the grid would shard as y-slabs with a one-row halo; see DESIGN.md)", file=sys.stderr)
@@ -263,6 +447,7 @@ def main():
     dominant = max(models, key=lambda m: per_model[m]["us_per_step"])
     dom_us = per_model[dominant]["us_per_step"]
     achieved = cells * bytes_per_cell(args.prec) / (dom_us * 1e-6) / 1e9
+    traffic = measured_traffic(dominant, args.prec) if n == 4096 else None
     line = {
         "metric": "MLUPS per collision model at 4096^2 FP32 + % HBM roofline; adjoint/batched vs plain",
         "value": round(value, 1),
@@ -282,7 +467,10 @@ def main():
                    "nx": n, "ny": n, "models": models, "omega": [round(w, 6) for w in omega]},
         "roofline": {"bound": "hbm", "kernel": f"k_step<{dominant}>", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+                     "traffic": traffic, "traffic_unit": "bytes per launch",
+                     "algorithmic_bytes": cells * bytes_per_cell(args.prec),
+                     "measured_frac": (None if traffic is None else
+                                       round(traffic / (dom_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4))},
         "per_model": per_model,
         "blowup": {m: st[1] for m, st in status.items()},
     }
@@ -297,6 +485,7 @@ def main():
         f64_mlups = min(v["mlups"] for v in line["precisions"]["f64"].values())
         line["batched"] = batched_sweep(args.batch_steps, f64_mlups)
         line["adjoint"] = adjoint_run()
+        line["precision_error"] = precision_errors(n)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(models)
     print(json.dumps(line), flush=True)
