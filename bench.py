@@ -175,6 +175,25 @@ def batched_sweep(steps: int, plain_f64_mlups: float, n_inst: int = 512):
             "precision": "f64"}
 
 
+def stability_map(L: int = 32, M: float = 50.0):
+    """Numerical stability domains of the convected vortex (beta 0.5, R = L/20), every model under
+    SRT and REG, nu in {1e-6 .. 1e-2}, Ma in {0.05 .. 0.8}, M convective times each, all runs in
+    one batch (FP64).  Reports the largest stable Ma per model, preset and nu."""
+    from paper_2002_05265_amd import inputs
+    from paper_2002_05265_amd import stability as S
+
+    nus = [1e-6, 1e-5, 1e-4, 1e-3, 1e-2]
+    machs = [round(0.05 * k, 2) for k in range(1, 17)]
+    insts = S.vortex_instances(list(inputs.MODEL_NAMES), ["SRT", "REG"], nus, machs, L=L, M=M)
+    fb, sec, upd = S.run_stability(insts)
+    best = S.max_stable_mach(insts, fb)
+    table = {f"{m}-{p}": [best[(m, p, nu)] for nu in nus] for m in inputs.MODEL_NAMES for p in ("SRT", "REG")}
+    return {"workload": f"convected vortex L={L}, M={M:g} t_c, {len(insts)} runs (8 models x SRT/REG x "
+                        f"{len(nus)} nu x {len(machs)} Ma), FP64, |u|^2 criterion checked every 64 steps",
+            "seconds": round(sec, 3), "node_updates": upd, "mlups": round(upd / sec / 1e6, 1),
+            "nu": nus, "max_stable_mach": table}
+
+
 def precision_errors(n: int = 4096, steps: int = 5000, models=("CM", "K")):
     """Shifted FP32 and FP16 storage against FP64 on the double shear layer: relative L2 error
     of the velocity field after `steps` steps (same initial fields, rates and model)."""
@@ -486,6 +505,7 @@ def main():
         line["batched"] = batched_sweep(args.batch_steps, f64_mlups)
         line["adjoint"] = adjoint_run()
         line["precision_error"] = precision_errors(n)
+        line["stability_map"] = stability_map()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(models)
     print(json.dumps(line), flush=True)

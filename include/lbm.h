@@ -53,7 +53,7 @@ enum {
     LBM_F64 = 0,         /* f_i stored in FP64, FP64 arithmetic                               */
     LBM_F32_SHIFTED = 1, /* h_i = f_i - w_i rho0 stored in FP32 (or - f^eq(rho0, U), see
                             lbm_init_shifted), FP32 arithmetic, FP64 rho                         */
-    LBM_F16_SHIFTED = 2  /* h_i stored in FP16, FP32 arithmetic, FP64 rho                      */
+    LBM_F16_SHIFTED = 2  /* h_i stored in FP16, FP32 arithmetic (FP32 mass sum)              */
 };
 
 /* Status codes. */
@@ -68,7 +68,8 @@ enum {
 typedef struct lbm_ctx lbm_ctx; /* opaque, host-side, owned by the library */
 
 /* Bytes of device memory the caller must provide for the populations of an nx x ny grid at
- * precision prec (two copies of the nine population planes, each plane padded to 256 bytes).
+ * precision prec (two copies of the nine population planes, each plane rounded up to 256 bytes
+ * plus a 1 KiB skew).
  * Returns 0 for invalid arguments. */
 size_t lbm_population_bytes(int nx, int ny, int prec);
 

@@ -6,8 +6,8 @@
  * numerical stability study (Section 5b-c: one simulation per (model, Ma, nu) point, with a
  * blow-up test).  Instances share nothing; their nodes are cut into tiles of 256 consecutive
  * nodes, and one persistent grid of co-resident workgroups sweeps all tiles of all instances
- * every step, with a grid-wide barrier between steps.  The launch is captured once in a
- * hipGraph and replayed.
+ * every step, with a grid-wide barrier between steps.  The grid is launched cooperatively, so
+ * the runtime guarantees that all its workgroups are resident together (or refuses the launch).
  *
  * Per-instance arithmetic is exactly that of lbm_step (same device code, same rounding): an
  * instance of the batch is bit-identical to the same run through lbm_init / lbm_step.
@@ -41,7 +41,8 @@ typedef struct {
 typedef struct lbm_batch lbm_batch; /* opaque, host-side, owned by the library */
 
 /* Bytes of device memory for the populations of all n instances at precision prec (two
- * copies, every instance's planes padded to 256 bytes).  0 for invalid arguments. */
+ * copies, every instance's planes rounded up to 256 bytes plus a 1 KiB skew).  0 for invalid
+ * arguments. */
 size_t lbm_batch_population_bytes(const lbm_instance_desc* desc, int n, int prec);
 
 /* Create a batch and set every instance to f^eq(rho, u) of its own equilibrium order.
@@ -51,16 +52,20 @@ size_t lbm_batch_population_bytes(const lbm_instance_desc* desc, int n, int prec
  *               order, each instance's block [y][x] (sum of nx*ny values each); read only
  *   pop_buf     device, caller-owned, >= lbm_batch_population_bytes bytes, 256-byte aligned
  *   hip_stream  stream for all work of this batch (NULL = default)
- * Allocates descriptor and tile tables, the barrier counter and the blow-up record
- * (O(number of tiles) bytes). */
+ * Allocates descriptor and tile tables, the barrier counter, the blow-up record and the
+ * per-instance flags (O(number of tiles) bytes).  LBM_EUNSUPPORTED if the device has no
+ * cooperative launches. */
 int lbm_batch_create(lbm_batch** out, const lbm_instance_desc* desc, int n, int prec,
                      const double* rho, const double* ux, const double* uy, void* pop_buf,
                      size_t pop_bytes, void* hip_stream);
 
-/* Advance every live instance by nsteps >= 0 steps in one persistent launch (replayed from a
- * hipGraph captured for this nsteps).  Asynchronous.  A grid barrier that does not complete
- * within two seconds (co-residency lost) stops the launch; lbm_batch_status then reports
- * LBM_EHIP. */
+/* Advance every live instance by nsteps >= 0 steps in one cooperative persistent launch.
+ * Asynchronous, except that the first run of each launch shape first probes how many workgroups
+ * per CU really stay co-resident (the runtime's occupancy figure can be one too high): two
+ * non-advancing steps with a 250 ms barrier bound per candidate, from the occupancy figure
+ * down; this synchronises the stream and leaves states and records unchanged.  A refused launch
+ * returns LBM_EHIP.  A grid barrier that does not complete within two seconds stops the launch
+ * (every wave exits); lbm_batch_status then reports LBM_EHIP. */
 int lbm_batch_run(lbm_batch* b, int nsteps);
 
 /* Step counter and, per instance, the first step whose state had a node with !(rho > 0)
@@ -68,18 +73,35 @@ int lbm_batch_run(lbm_batch* b, int nsteps);
 int lbm_batch_status(lbm_batch* b, long long* step, long long* blowup_steps);
 
 /* Current state of one instance as unshifted FP64 populations (device, 9*nx*ny, [q][y][x]).
- * Asynchronous. */
+ * An instance that blew up at step b stops at state b + 1 (the collided state of step b); one
+ * retired at step r (lbm_batch_set_active) stops at state r.  Synchronises the stream (to read
+ * those records), then enqueues the copy. */
 int lbm_batch_get_state(lbm_batch* b, int instance, double* f);
 
+/* Domain mean of |u|^2 of every instance's current state, the quantity of the stability
+ * criterion of Section 5b (unweighted mean over the nx*ny nodes, u = j / rho in FP64):
+ *   mean_u2   device, n doubles (overwritten), in instance order
+ * Deterministic (fixed summation order).  Values of blown-up or retired instances are
+ * unspecified (NaN for blown-up states).  Asynchronous. */
+int lbm_batch_mean_u2(lbm_batch* b, double* mean_u2);
+
+/* Retire instances: active is a device array of n ints; every instance whose flag is 0 is
+ * retired for good from the following lbm_batch_run calls (its state and blow-up record stay as
+ * they are, and the current step is recorded as its last).  Nonzero flags change nothing: a
+ * retired instance cannot be re-admitted.  All instances start active.  The flags are read in
+ * stream order (the array may be overwritten once the stream has passed this call).
+ * Asynchronous. */
+int lbm_batch_set_active(lbm_batch* b, const int* active);
+
 /* Launch shape of the persistent kernel: nodes per thread per tile (1, 2 or 4) and resident
- * workgroups per CU (1 .. the occupancy limit; 0 = the limit).  Takes effect at the next
+ * workgroups per CU (1 .. the probed residency limit; 0 = that limit).  Takes effect at the next
  * lbm_batch_run. */
 int lbm_batch_set_launch(lbm_batch* b, int nodes_per_thread, int groups_per_cu);
 
 /* Autotune the persistent launch: each candidate (nodes per thread in {1, 2, 4} x groups per
- * CU in {limit, limit/2}) runs `trials` (>= 1) steps that all recompute the current step from
- * the same input copy, so states, counters and blow-up records are unchanged.  Keeps and
- * returns the fastest shape.  Synchronises. */
+ * CU in {limit, limit/2}, limit = the probed residency limit of that shape) runs `trials` (>= 1)
+ * steps that all recompute the current step from the same input copy, so states, counters and
+ * blow-up records are unchanged.  Keeps and returns the fastest shape.  Synchronises. */
 int lbm_batch_autotune(lbm_batch* b, int trials, int* nodes_per_thread, int* groups_per_cu,
                        double* us_per_step);
 

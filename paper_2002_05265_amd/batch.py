@@ -50,6 +50,20 @@ class Batch:
         self.stream.synchronize()
         return f
 
+    def mean_u2(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Domain mean of |u|^2 per instance (FP64 device tensor, asynchronous)."""
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        B.lbm_batch_mean_u2(self.handle, out.data_ptr())
+        return out
+
+    def set_active(self, active: torch.Tensor):
+        """Retire (for good) the instances whose flag is 0; active: int32 device tensor of n
+        flags.  Asynchronous."""
+        if active.dtype != torch.int32 or active.numel() != self.n or active.device != self.device:
+            raise ValueError("active must be an int32 device tensor with one flag per instance")
+        B.lbm_batch_set_active(self.handle, active.contiguous().data_ptr())
+
     def set_launch(self, nodes_per_thread: int, groups_per_cu: int = 0):
         B.lbm_batch_set_launch(self.handle, nodes_per_thread, groups_per_cu)
 

@@ -26,7 +26,8 @@ EXPORTS = (
     "lbm_get_state", "lbm_set_state", "lbm_set_launch", "lbm_autotune", "lbm_destroy",
     "lbm_last_error",
     "lbm_batch_population_bytes", "lbm_batch_create", "lbm_batch_run", "lbm_batch_status",
-    "lbm_batch_get_state", "lbm_batch_set_launch", "lbm_batch_autotune", "lbm_batch_destroy",
+    "lbm_batch_get_state", "lbm_batch_mean_u2", "lbm_batch_set_active", "lbm_batch_set_launch",
+    "lbm_batch_autotune", "lbm_batch_destroy",
     "lbm_state_bytes", "lbm_adjoint_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_raw",
     "lbm_step_raw_many", "lbm_adjoint_many", "lbm_adjoint_flush",
     "lbm_adjoint_seed_velocity_l2", "lbm_adjoint_step", "lbm_eq_vjp",
@@ -72,6 +73,8 @@ def _declare(L: ctypes.CDLL):
         "lbm_batch_run": (_i, [_vp, _i]),
         "lbm_batch_status": (_i, [_vp, ctypes.POINTER(_ll), ctypes.POINTER(_ll)]),
         "lbm_batch_get_state": (_i, [_vp, _i, _vp]),
+        "lbm_batch_mean_u2": (_i, [_vp, _vp]),
+        "lbm_batch_set_active": (_i, [_vp, _vp]),
         "lbm_batch_set_launch": (_i, [_vp, _i, _i]),
         "lbm_batch_autotune": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), _dp]),
         "lbm_batch_destroy": (None, [_vp]),
@@ -223,6 +226,14 @@ def lbm_batch_status(b: int, n: int):
 
 def lbm_batch_get_state(b: int, instance: int, f: int):
     _check(lib().lbm_batch_get_state(b, instance, f), "lbm_batch_get_state")
+
+
+def lbm_batch_mean_u2(b: int, mean_u2: int):
+    _check(lib().lbm_batch_mean_u2(b, mean_u2), "lbm_batch_mean_u2")
+
+
+def lbm_batch_set_active(b: int, active: int):
+    _check(lib().lbm_batch_set_active(b, active), "lbm_batch_set_active")
 
 
 def lbm_batch_set_launch(b: int, nodes_per_thread: int, groups_per_cu: int):

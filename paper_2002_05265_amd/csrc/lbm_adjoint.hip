@@ -29,15 +29,18 @@ template <> struct AdjT<kF16> { using T = float; };
 template <typename T, typename R>
 __device__ __forceinline__ void push_gather(const T* __restrict__ lam, long long plane, const Nbr& n,
                                             R (&mu)[9]) {
-    mu[0] = R(lam[0 * plane + n.r0 + n.x]);
-    mu[1] = R(lam[1 * plane + n.r0 + n.xp]);
-    mu[2] = R(lam[2 * plane + n.rp + n.x]);
-    mu[3] = R(lam[3 * plane + n.r0 + n.xm]);
-    mu[4] = R(lam[4 * plane + n.rm + n.x]);
-    mu[5] = R(lam[5 * plane + n.rp + n.xp]);
-    mu[6] = R(lam[6 * plane + n.rp + n.xm]);
-    mu[7] = R(lam[7 * plane + n.rm + n.xm]);
-    mu[8] = R(lam[8 * plane + n.rm + n.xp]);
+    constexpr unsigned E = sizeof(T);
+    const unsigned r0 = n.r0 * E, rm = n.rm * E, rp = n.rp * E;
+    const unsigned x0 = n.x * E, xm = n.xm * E, xp = n.xp * E;
+    mu[0] = R(*plane_at(lam, plane, 0, r0 + x0));
+    mu[1] = R(*plane_at(lam, plane, 1, r0 + xp));
+    mu[2] = R(*plane_at(lam, plane, 2, rp + x0));
+    mu[3] = R(*plane_at(lam, plane, 3, r0 + xm));
+    mu[4] = R(*plane_at(lam, plane, 4, rm + x0));
+    mu[5] = R(*plane_at(lam, plane, 5, rp + xp));
+    mu[6] = R(*plane_at(lam, plane, 6, rp + xm));
+    mu[7] = R(*plane_at(lam, plane, 7, rm + xm));
+    mu[8] = R(*plane_at(lam, plane, 8, rm + xp));
 }
 
 // Per-block rate-gradient slots: block b adds (accumulate = 1) or writes (0) its FP64 block sum
@@ -84,12 +87,12 @@ __global__ __launch_bounds__(256) void k_adjoint_step(const typename Store<PREC>
         pull_load(state, g.plane, nb, h);
         push_gather(lam_next, g.plane, nb, mu);
         double rho_d;
-        const Macro<R> m = macro_of(h, ref, rho_d);
+        const Macro<R> m = macro_of<typename Store<PREC>::S>(h, ref, rho_d);
         R cb[7] = {R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
         collide_adjoint<MODEL>(h, m, ref, c, N, mu, hb, cb);
         const unsigned o = nb.r0 + (unsigned)x;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) lam[i * g.plane + o] = T(hb[i]);
+        for (int i = 0; i < 9; ++i) *plane_at(lam, g.plane, i, o * (unsigned)sizeof(T)) = T(hb[i]);
         omega_adjoint(cb, wb);
     }
     block_accumulate(wb, slots, accumulate);

@@ -127,7 +127,7 @@ __device__ __forceinline__ void macro_adjoint(const Macro<R>& m, const Ref<R>& r
                                               R (&hb)[9]) {
     mb.dux += mb.ux;  // u = U + du
     mb.duy += mb.uy;
-    const R inv = R(1) / m.rho;
+    const R inv = m.inv_rho;
     // du = (j - drho U) / rho
     mb.jx += mb.dux * inv;
     mb.jy += mb.duy * inv;
@@ -252,7 +252,7 @@ __device__ __forceinline__ void collide_adjoint(const R (&h)[9], const Macro<R>&
                     n20b -= L::cs2 * s22b;
                     n02b -= L::cs2 * s22b;
                 } else {  // kK
-                    const R inv = R(1) / m.rho;
+                    const R inv = m.inv_rho;
                     const R P = d.d20 * d.d02 + R(2) * d.d11 * d.d11;
                     const R Q = n20 * n02 + R(2) * n11 * n11;
                     cb[5] += (t22 - P * inv) * s22b;

@@ -2,12 +2,12 @@
 //
 // Work decomposition.  Instance j owns `cells_j = nx_j * ny_j` nodes, cut into tiles of
 // 256 * NPT consecutive nodes (linear index y * nx + x).  All tiles of all instances form one
-// list; a persistent grid of G co-resident workgroups takes tiles t = blockIdx.x + k G every
-// step, then all workgroups meet at a grid barrier before the next step reads what this one
-// wrote.  The barrier is a monotonic counter: workgroup arrivals after step s bring it to
-// G (s + 1).  Agent-scope release / acquire fences around it make the populations written on
-// one XCD visible to the others.  Its spin is bounded in wall-clock time, so every wave exits
-// even if co-residency were lost.
+// list; a persistent grid of G workgroups, launched cooperatively so that all of them are
+// resident at once, takes tiles t = blockIdx.x + k G every step, then all workgroups meet at a
+// grid barrier before the next step reads what this one wrote.  The barrier is a monotonic
+// counter: workgroup arrivals after step s bring it to G (s + 1).  Agent-scope release / acquire
+// fences around it make the populations written on one XCD visible to the others.  Its spin is
+// also bounded in wall-clock time, so every wave exits whatever happens to the others.
 //
 // Each node runs exactly the code of the plain kernel (pull_load / macro_of / collide /
 // store_cell with the same coefficients), so an instance is bit-identical to its plain run.
@@ -97,8 +97,9 @@ template <int PREC, int NPT>
 __global__ __launch_bounds__(kTileThreads) void k_batch(
     typename Store<PREC>::S* __restrict__ base, long long copy_elems,
     const BDesc<typename Store<PREC>::R>* __restrict__ desc, const int* __restrict__ tile_inst,
-    int ntiles, int* __restrict__ blowup, unsigned* __restrict__ bar, int* __restrict__ err,
-    long long* __restrict__ step_ctr, int nsteps, int advance, long long timeout_ticks) {
+    int ntiles, int* __restrict__ blowup, const int* __restrict__ active, unsigned* __restrict__ bar,
+    int* __restrict__ err, long long* __restrict__ step_ctr, int nsteps, int advance,
+    long long timeout_ticks) {
     using S = typename Store<PREC>::S;
     using R = typename Store<PREC>::R;
     const long long n0 = *step_ctr;
@@ -113,7 +114,7 @@ __global__ __launch_bounds__(kTileThreads) void k_batch(
             const int j = tile_inst[t];
             const BDesc<R>& d = desc[j];
             const int frozen = __hip_atomic_load(blowup + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if ((long long)frozen < n) continue;  // blew up at an earlier step
+            if ((long long)frozen < n || !active[j]) continue;  // blew up earlier, or retired
             const int first = (t - d.tile0) * NPT * kTileThreads + tid;
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
@@ -125,7 +126,7 @@ __global__ __launch_bounds__(kTileThreads) void k_batch(
                     R h[9];
                     pull_load(src + d.off, d.plane, nb, h);
                     double rho_d;
-                    const Macro<R> m = macro_of(h, d.ref, rho_d);
+                    const Macro<R> m = macro_of<typename Store<PREC>::S>(h, d.ref, rho_d);
                     flag_bad(!(rho_d > 0.0), blowup + j, (int)n);
                     collide_model(d.model, h, m, d.ref, d.c, d.N);
                     store_cell(dst + d.off, d.plane, (unsigned)c, h);
@@ -169,6 +170,59 @@ __global__ __launch_bounds__(256) void k_batch_get(const typename Store<PREC>::S
     for (int i = 0; i < 9; ++i) f[i * cells + c] = h[i] + fref.v[i];
 }
 
+// Mean of |u|^2 over the nodes of every instance (FP64, pulled from the copy of the current
+// step): one block per 256-node tile writes its partial sum, then one thread per instance adds
+// its tiles in order (deterministic).
+template <int PREC>
+__global__ __launch_bounds__(kTileThreads) void k_batch_u2_tiles(
+    const typename Store<PREC>::S* __restrict__ cur, const BDesc<typename Store<PREC>::R>* __restrict__ desc,
+    const int* __restrict__ tile_inst, double* __restrict__ partial) {
+    __shared__ double red[kTileThreads / 64];
+    const int j = tile_inst[blockIdx.x];
+    const BDesc<typename Store<PREC>::R>& d = desc[j];
+    const int c = (blockIdx.x - d.tile0) * kTileThreads + threadIdx.x;
+    double v = 0.0;
+    if (c < d.cells) {
+        const int y = row_of(c, d.nx, d.inv_nx);
+        const int x = c - y * d.nx;
+        const Nbr nb = neighbours(x, y, d.nx, d.ny);
+        double h[9];
+        pull_load(cur + d.off, d.plane, nb, h);
+        const Ref<double>& r = d.ref_d;
+        const double rho = r.rho + (((h[0] + (h[1] + h[3])) + (h[2] + h[4])) + ((h[5] + h[7]) + (h[6] + h[8])));
+        const double jx = ((h[1] + h[5] + h[8]) - (h[3] + h[6] + h[7])) + r.rho * r.ux;
+        const double jy = ((h[2] + h[5] + h[6]) - (h[4] + h[7] + h[8])) + r.rho * r.uy;
+        const double ux = jx / rho, uy = jy / rho;
+        v = ux * ux + uy * uy;
+    }
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+template <typename R>
+__global__ void k_batch_u2_sum(const BDesc<R>* __restrict__ desc, int n, const double* __restrict__ partial,
+                               double* __restrict__ out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const BDesc<R>& d = desc[j];
+    const int nt = (d.cells + kTileThreads - 1) / kTileThreads;
+    double s = 0.0;
+    for (int t = 0; t < nt; ++t) s += partial[d.tile0 + t];
+    out[j] = s / (double)d.cells;
+}
+
+// Retire the instances whose flag is 0 (for good) and record the step at which they left.
+__global__ void k_retire(const int* __restrict__ flags, int* __restrict__ active, int* __restrict__ retired,
+                         int n, int step) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && active[i] && !flags[i]) {
+        active[i] = 0;
+        retired[i] = step;
+    }
+}
+
 // Reset the barrier counter before each replay.  The error flag is sticky (cleared only at
 // creation) so that a stopped launch stays reported.
 __global__ void k_batch_reset(unsigned* __restrict__ bar) {
@@ -194,21 +248,22 @@ struct lbm_batch {
     char* buf = nullptr;
     size_t bytes = 0;
     hipStream_t stream = nullptr;      // caller's stream
-    hipStream_t cap = nullptr;         // private stream used only for graph capture
-    int cus = 0, occ[3] = {0, 0, 0};   // CUs, occupancy limit per NPT index
+    int cus = 0, occ[3] = {0, 0, 0};   // CUs, occupancy limit per NPT index (runtime query)
+    int resident[3] = {0, 0, 0};       // groups per CU confirmed co-resident (0 = not probed)
     int npt = 1, gpc = 0;              // launch shape (gpc 0 = occupancy limit)
     long long step = 0;                // host mirror of the step counter
     void* d_desc[3] = {nullptr, nullptr, nullptr};  // descriptors per NPT (tile0 differs)
     int* d_tiles[3] = {nullptr, nullptr, nullptr};
     int ntiles[3] = {0, 0, 0};
     int* d_blowup = nullptr;
+    int* d_active = nullptr;           // per instance: nonzero = advanced by lbm_batch_run
+    int* d_retired = nullptr;          // per instance: step at which it was retired (INT_MAX)
+    double* d_u2part = nullptr;        // per 256-node tile: partial sums of |u|^2
     unsigned* d_bar = nullptr;
     int* d_err = nullptr;
     long long* d_step = nullptr;
     long long timeout_ticks = 0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    int g_nsteps = -1, g_npt = -1, g_G = -1, g_adv = -1;
+    long long probe_ticks = 0;
 };
 
 namespace {
@@ -232,58 +287,97 @@ const void* batch_kernel_p(int prec, int npt) {
     }
 }
 
+// The persistent kernel is launched cooperatively: the runtime then either makes all G
+// workgroups resident at once or refuses the launch (hipErrorCooperativeLaunchTooLarge), so the
+// grid barrier never waits on a workgroup that cannot start.
 template <int PREC, int NPT>
-void launch_batch_t(lbm_batch* b, hipStream_t s, int G, int nsteps, int advance) {
+hipError_t launch_batch_t(lbm_batch* b, hipStream_t s, int G, int nsteps, int advance) {
     using S = typename Store<PREC>::S;
     using R = typename Store<PREC>::R;
     const int k = npt_index(NPT);
-    hipLaunchKernelGGL((k_batch<PREC, NPT>), dim3(G), dim3(kTileThreads), 0, s,
-                       reinterpret_cast<S*>(b->buf), b->copy_elems,
-                       reinterpret_cast<const BDesc<R>*>(b->d_desc[k]), b->d_tiles[k], b->ntiles[k],
-                       b->d_blowup, b->d_bar, b->d_err, b->d_step, nsteps, advance, b->timeout_ticks);
+    S* base = reinterpret_cast<S*>(b->buf);
+    long long copy_elems = b->copy_elems;
+    const BDesc<R>* desc = reinterpret_cast<const BDesc<R>*>(b->d_desc[k]);
+    const int* tiles = b->d_tiles[k];
+    int ntiles = b->ntiles[k];
+    int* blowup = b->d_blowup;
+    const int* active = b->d_active;
+    unsigned* bar = b->d_bar;
+    int* err = b->d_err;
+    long long* step = b->d_step;
+    long long timeout = b->timeout_ticks;
+    void* args[] = {&base, &copy_elems, &desc, &tiles, &ntiles, &blowup, &active, &bar, &err, &step,
+                    &nsteps, &advance, &timeout};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_batch<PREC, NPT>), dim3(G),
+                                      dim3(kTileThreads), args, 0, s);
 }
 
 template <int PREC>
-void launch_batch_p(lbm_batch* b, hipStream_t s, int G, int nsteps, int advance) {
+hipError_t launch_batch_p(lbm_batch* b, hipStream_t s, int G, int nsteps, int advance) {
     switch (b->npt) {
-        case 4: launch_batch_t<PREC, 4>(b, s, G, nsteps, advance); break;
-        case 2: launch_batch_t<PREC, 2>(b, s, G, nsteps, advance); break;
-        default: launch_batch_t<PREC, 1>(b, s, G, nsteps, advance); break;
+        case 4: return launch_batch_t<PREC, 4>(b, s, G, nsteps, advance);
+        case 2: return launch_batch_t<PREC, 2>(b, s, G, nsteps, advance);
+        default: return launch_batch_t<PREC, 1>(b, s, G, nsteps, advance);
     }
 }
 
+int groups_limit(lbm_batch* b) {
+    const int k = npt_index(b->npt);
+    return b->resident[k] > 0 ? b->resident[k] : b->occ[k];
+}
+
 int grid_size(lbm_batch* b) {
-    const int lim = b->occ[npt_index(b->npt)];
+    const int lim = groups_limit(b);
     const int per = (b->gpc <= 0 || b->gpc > lim) ? lim : b->gpc;
     return b->cus * per;
 }
 
-// Capture (reset kernel + persistent kernel) for this shape once, then replay.
-int run_graph(lbm_batch* b, int nsteps, int advance) {
-    const int G = grid_size(b);
-    if (!(b->exec && b->g_nsteps == nsteps && b->g_npt == b->npt && b->g_G == G && b->g_adv == advance)) {
-        if (b->exec) (void)hipGraphExecDestroy(b->exec);
-        if (b->graph) (void)hipGraphDestroy(b->graph);
-        b->exec = nullptr;
-        b->graph = nullptr;
-        int rc = check_hip(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture");
-        if (rc != LBM_OK) return rc;
-        hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, b->cap, b->d_bar);
-        switch (b->prec) {
-            case LBM_F64: launch_batch_p<kF64>(b, b->cap, G, nsteps, advance); break;
-            case LBM_F32_SHIFTED: launch_batch_p<kF32>(b, b->cap, G, nsteps, advance); break;
-            default: launch_batch_p<kF16>(b, b->cap, G, nsteps, advance); break;
-        }
-        rc = check_hip(hipStreamEndCapture(b->cap, &b->graph), "end capture");
-        if (rc != LBM_OK) return rc;
-        rc = check_hip(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "instantiate graph");
-        if (rc != LBM_OK) return rc;
-        b->g_nsteps = nsteps;
-        b->g_npt = b->npt;
-        b->g_G = G;
-        b->g_adv = advance;
+// Reset the barrier counter, then one cooperative launch of the persistent kernel on G groups.
+int run_persistent_on(lbm_batch* b, int G, int nsteps, int advance, long long ticks) {
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, b->stream, b->d_bar);
+    int rc = check_hip(hipGetLastError(), "barrier reset launch");
+    if (rc != LBM_OK) return rc;
+    const long long keep = b->timeout_ticks;
+    b->timeout_ticks = ticks;
+    hipError_t e;
+    switch (b->prec) {
+        case LBM_F64: e = launch_batch_p<kF64>(b, b->stream, G, nsteps, advance); break;
+        case LBM_F32_SHIFTED: e = launch_batch_p<kF32>(b, b->stream, G, nsteps, advance); break;
+        default: e = launch_batch_p<kF16>(b, b->stream, G, nsteps, advance); break;
     }
-    return check_hip(hipGraphLaunch(b->exec, b->stream), "graph launch");
+    b->timeout_ticks = keep;
+    return check_hip(e, "cooperative launch of the persistent kernel");
+}
+
+int run_persistent(lbm_batch* b, int nsteps, int advance) {
+    return run_persistent_on(b, grid_size(b), nsteps, advance, b->timeout_ticks);
+}
+
+// The occupancy query can promise more resident workgroups per CU than the hardware actually
+// co-schedules for a kernel (measured on MI355X: 8 reported, 7 resident for the FP32 and FP16
+// kernels), and a persistent grid larger than what is resident cannot pass its first barrier.
+// Before the first run of each nodes-per-thread shape, a probe runs two non-advancing steps
+// (they recompute the current step from the same copy: state, counters and records unchanged)
+// with a short barrier bound, at `per` groups per CU from the query's value down, and keeps the
+// first `per` whose grid passed every barrier.  A failed probe ends by its bound: every wave exits.
+int ensure_resident(lbm_batch* b) {
+    const int k = npt_index(b->npt);
+    if (b->resident[k] > 0) return LBM_OK;
+    for (int per = b->occ[k]; per >= 1; --per) {
+        int rc = run_persistent_on(b, b->cus * per, 2, 0, b->probe_ticks);
+        if (rc == LBM_OK) rc = check_hip(hipStreamSynchronize(b->stream), "synchronise (residency probe)");
+        int err = 0;
+        if (rc == LBM_OK) rc = check_hip(hipMemcpy(&err, b->d_err, sizeof(int), hipMemcpyDeviceToHost), "copy err");
+        if (rc != LBM_OK) return rc;
+        if (!err) {
+            b->resident[k] = per;
+            return LBM_OK;
+        }
+        hipLaunchKernelGGL(k_clear_i32, dim3(1), dim3(64), 0, b->stream, b->d_err);
+        rc = check_hip(hipGetLastError(), "clear err");
+        if (rc != LBM_OK) return rc;
+    }
+    return set_error(LBM_EHIP, "no persistent grid of this shape stays co-resident");
 }
 
 }  // namespace
@@ -355,6 +449,10 @@ int lbm_batch_create(lbm_batch** out, const lbm_instance_desc* desc, int n, int 
     if (rc == LBM_OK) rc = check_hip(hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
     if (rc == LBM_OK) rc = check_hip(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev), "wall clock rate");
     b->timeout_ticks = 2LL * 1000LL * (long long)(clock_khz > 0 ? clock_khz : 100000);  // 2 s
+    b->probe_ticks = b->timeout_ticks / 8;                                                // 250 ms
+    int coop = 0;
+    if (rc == LBM_OK) rc = check_hip(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev), "cooperative launch attribute");
+    if (rc == LBM_OK && !coop) rc = set_error(LBM_EUNSUPPORTED, "device does not support cooperative launches");
     const int npts[3] = {1, 2, 4};
     for (int k = 0; k < 3 && rc == LBM_OK; ++k) {
         rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[k], batch_kernel_p(prec, npts[k]),
@@ -401,16 +499,21 @@ int lbm_batch_create(lbm_batch** out, const lbm_instance_desc* desc, int n, int 
                            "copy tiles");
     }
     if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_blowup, sizeof(int) * (size_t)n), "hipMalloc(blowup)");
+    if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_active, sizeof(int) * (size_t)n), "hipMalloc(active)");
+    if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_retired, sizeof(int) * (size_t)n), "hipMalloc(retired)");
+    if (rc == LBM_OK)
+        rc = check_hip(hipMalloc(&b->d_u2part, sizeof(double) * (size_t)b->ntiles[0]), "hipMalloc(u2 partials)");
     if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_bar, sizeof(unsigned)), "hipMalloc(barrier)");
     if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_err, sizeof(int)), "hipMalloc(err)");
     if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_step, sizeof(long long)), "hipMalloc(step)");
-    if (rc == LBM_OK) rc = check_hip(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "capture stream");
     if (rc == LBM_OK) {
         const long long zero = 0;
         rc = check_hip(hipMemcpy(b->d_step, &zero, sizeof(zero), hipMemcpyHostToDevice), "reset step");
     }
     if (rc == LBM_OK) {
         hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, b->stream, b->d_blowup, n, INT_MAX);
+        hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, b->stream, b->d_active, n, 1);
+        hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, b->stream, b->d_retired, n, INT_MAX);
         hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, b->stream, b->d_bar);
         hipLaunchKernelGGL(k_clear_i32, dim3(1), dim3(64), 0, b->stream, b->d_err);
         switch (prec) {
@@ -444,13 +547,16 @@ int lbm_batch_run(lbm_batch* b, int nsteps) {
     if (!b) return set_error(LBM_ESTATE, "batch is NULL");
     if (nsteps < 0) return set_error(LBM_EINVAL, "nsteps %d < 0", nsteps);
     if (b->step + nsteps >= INT_MAX) return set_error(LBM_EINVAL, "step counter would overflow");
+    if (nsteps == 0) return LBM_OK;
+    const int rc0 = ensure_resident(b);
+    if (rc0 != LBM_OK) return rc0;
     // keep the barrier counter G * nsteps below 2^32
     const long long G = grid_size(b);
     const int chunk = (int)std::min<long long>(nsteps, (1LL << 31) / G);
     int left = nsteps;
     while (left > 0) {
         const int k = std::min(left, chunk);
-        const int rc = run_graph(b, k, 1);
+        const int rc = run_persistent(b, k, 1);
         if (rc != LBM_OK) return rc;
         left -= k;
         b->step += k;
@@ -485,7 +591,18 @@ int lbm_batch_get_state(lbm_batch* b, int instance, double* f) {
     const lbm_instance_desc& d = b->hdesc[instance];
     const Launch l = launch_for(d.nx, d.ny);
     const Geom g{d.nx, d.ny, b->plane[instance]};
-    const int sc = (int)(b->step & 1);
+    // the instance's own last step: it stops advancing after blowing up or being retired
+    int blow = INT_MAX, ret = INT_MAX;
+    int rc = check_hip(hipStreamSynchronize(b->stream), "synchronise");
+    if (rc == LBM_OK)
+        rc = check_hip(hipMemcpy(&blow, b->d_blowup + instance, sizeof(int), hipMemcpyDeviceToHost), "copy blow-up");
+    if (rc == LBM_OK)
+        rc = check_hip(hipMemcpy(&ret, b->d_retired + instance, sizeof(int), hipMemcpyDeviceToHost), "copy retired");
+    if (rc != LBM_OK) return rc;
+    long long own = b->step;
+    if (blow != INT_MAX) own = std::min(own, (long long)blow + 1);
+    if (ret != INT_MAX) own = std::min(own, (long long)ret);
+    const int sc = (int)(own & 1);
     const size_t eoff = (size_t)(sc * b->copy_elems + b->off[instance]);
     const Pop9 fref = reference_populations(storage_reference(b->prec, d.rho0, d.ux0, d.uy0), d.eq_order);
     switch (b->prec) {
@@ -503,6 +620,45 @@ int lbm_batch_get_state(lbm_batch* b, int instance, double* f) {
             break;
     }
     return check_hip(hipGetLastError(), "batch get_state launch");
+}
+
+int lbm_batch_mean_u2(lbm_batch* b, double* mean_u2) {
+    if (!b) return set_error(LBM_ESTATE, "batch is NULL");
+    if (!mean_u2) return set_error(LBM_EINVAL, "mean_u2 is NULL");
+    const long long eoff = (b->step & 1) * b->copy_elems;
+    const dim3 tiles(b->ntiles[0]), tb(kTileThreads), ib((b->n + 255) / 256), ibt(256);
+    switch (b->prec) {
+        case LBM_F64:
+            hipLaunchKernelGGL(k_batch_u2_tiles<kF64>, tiles, tb, 0, b->stream,
+                               reinterpret_cast<const double*>(b->buf) + eoff,
+                               reinterpret_cast<const BDesc<double>*>(b->d_desc[0]), b->d_tiles[0], b->d_u2part);
+            hipLaunchKernelGGL(k_batch_u2_sum<double>, ib, ibt, 0, b->stream,
+                               reinterpret_cast<const BDesc<double>*>(b->d_desc[0]), b->n, b->d_u2part, mean_u2);
+            break;
+        case LBM_F32_SHIFTED:
+            hipLaunchKernelGGL(k_batch_u2_tiles<kF32>, tiles, tb, 0, b->stream,
+                               reinterpret_cast<const float*>(b->buf) + eoff,
+                               reinterpret_cast<const BDesc<float>*>(b->d_desc[0]), b->d_tiles[0], b->d_u2part);
+            hipLaunchKernelGGL(k_batch_u2_sum<float>, ib, ibt, 0, b->stream,
+                               reinterpret_cast<const BDesc<float>*>(b->d_desc[0]), b->n, b->d_u2part, mean_u2);
+            break;
+        default:
+            hipLaunchKernelGGL(k_batch_u2_tiles<kF16>, tiles, tb, 0, b->stream,
+                               reinterpret_cast<const _Float16*>(b->buf) + eoff,
+                               reinterpret_cast<const BDesc<float>*>(b->d_desc[0]), b->d_tiles[0], b->d_u2part);
+            hipLaunchKernelGGL(k_batch_u2_sum<float>, ib, ibt, 0, b->stream,
+                               reinterpret_cast<const BDesc<float>*>(b->d_desc[0]), b->n, b->d_u2part, mean_u2);
+            break;
+    }
+    return check_hip(hipGetLastError(), "batch mean |u|^2 launch");
+}
+
+int lbm_batch_set_active(lbm_batch* b, const int* active) {
+    if (!b) return set_error(LBM_ESTATE, "batch is NULL");
+    if (!active) return set_error(LBM_EINVAL, "active is NULL");
+    hipLaunchKernelGGL(k_retire, dim3((b->n + 255) / 256), dim3(256), 0, b->stream, active, b->d_active,
+                       b->d_retired, b->n, (int)b->step);
+    return check_hip(hipGetLastError(), "batch set_active launch");
 }
 
 int lbm_batch_set_launch(lbm_batch* b, int nodes_per_thread, int groups_per_cu) {
@@ -529,12 +685,14 @@ int lbm_batch_autotune(lbm_batch* b, int trials, int* nodes_per_thread, int* gro
     for (int k = 0; k < 3 && rc == LBM_OK; ++k)
         for (int half = 0; half < 2 && rc == LBM_OK; ++half) {
             b->npt = npts[k];
-            const int lim = b->occ[k];
+            rc = ensure_resident(b);
+            if (rc != LBM_OK) break;
+            const int lim = groups_limit(b);
             b->gpc = half ? std::max(1, lim / 2) : 0;
             if (half && b->gpc == lim) continue;
-            rc = run_graph(b, 1, 0);  // warm-up (non-advancing)
+            rc = run_persistent(b, 1, 0);  // warm-up (non-advancing)
             if (rc == LBM_OK) rc = check_hip(hipEventRecord(e0, b->stream), "hipEventRecord");
-            if (rc == LBM_OK) rc = run_graph(b, trials, 0);
+            if (rc == LBM_OK) rc = run_persistent(b, trials, 0);
             if (rc == LBM_OK) rc = check_hip(hipEventRecord(e1, b->stream), "hipEventRecord");
             if (rc == LBM_OK) rc = check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
             float ms = 0.f;
@@ -554,7 +712,7 @@ int lbm_batch_autotune(lbm_batch* b, int trials, int* nodes_per_thread, int* gro
     b->gpc = rc == LBM_OK ? best_gpc : keep_gpc;
     if (rc != LBM_OK) return rc;
     if (nodes_per_thread) *nodes_per_thread = best_npt;
-    if (groups_per_cu) *groups_per_cu = best_gpc == 0 ? b->occ[npt_index(best_npt)] : best_gpc;
+    if (groups_per_cu) *groups_per_cu = best_gpc == 0 ? b->resident[npt_index(best_npt)] : best_gpc;
     if (us_per_step) *us_per_step = 1e3 * (double)best / trials;
     return LBM_OK;
 }
@@ -562,17 +720,17 @@ int lbm_batch_autotune(lbm_batch* b, int trials, int* nodes_per_thread, int* gro
 void lbm_batch_destroy(lbm_batch* b) {
     if (!b) return;
     (void)hipStreamSynchronize(b->stream);
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
     for (int k = 0; k < 3; ++k) {
         if (b->d_desc[k]) (void)hipFree(b->d_desc[k]);
         if (b->d_tiles[k]) (void)hipFree(b->d_tiles[k]);
     }
     if (b->d_blowup) (void)hipFree(b->d_blowup);
+    if (b->d_active) (void)hipFree(b->d_active);
+    if (b->d_retired) (void)hipFree(b->d_retired);
+    if (b->d_u2part) (void)hipFree(b->d_u2part);
     if (b->d_bar) (void)hipFree(b->d_bar);
     if (b->d_err) (void)hipFree(b->d_err);
     if (b->d_step) (void)hipFree(b->d_step);
-    if (b->cap) (void)hipStreamDestroy(b->cap);
     delete b;
 }
 

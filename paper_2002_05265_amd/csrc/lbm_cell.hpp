@@ -82,6 +82,7 @@ template <typename R> struct Ref {
 // of the stored deviations), u and du = u - U.
 template <typename R> struct Macro {
     R drho, rho, jx, jy, ux, uy, dux, duy;
+    R inv_rho;  // 1 / rho
 };
 
 // Hermite equilibrium moments of order N (A^eq_pq = rho ux^p uy^q, zero above order N), as
@@ -230,7 +231,7 @@ __device__ __forceinline__ void collide(R (&h)[9], const Macro<R>& m, const Ref<
                     s22 = c.c22 * (t22 + L::cs2 * (d.d20 + d.d02)) - L::cs2 * (n20 + n02);
                 } else {
                     // fourth-order cumulant times rho: t22 - (t20 t02 + 2 t11^2) / rho
-                    const R inv = R(1) / m.rho;
+                    const R inv = m.inv_rho;
                     s22 = c.c22 * (t22 - (d.d20 * d.d02 + R(2) * d.d11 * d.d11) * inv) +
                           (n20 * n02 + R(2) * n11 * n11) * inv;
                 }

@@ -52,11 +52,10 @@ struct Nbr {
 
 __device__ __forceinline__ Nbr neighbours(int x, int y, int nx, int ny) {
     Nbr n;
-    const int ym = y == 0 ? ny - 1 : y - 1;
-    const int yp = y == ny - 1 ? 0 : y + 1;
+    // one per-lane multiply; the wrapped rows come from the wave-uniform (ny - 1) nx
     n.r0 = (unsigned)y * (unsigned)nx;
-    n.rm = (unsigned)ym * (unsigned)nx;
-    n.rp = (unsigned)yp * (unsigned)nx;
+    n.rm = y == 0 ? (unsigned)(ny - 1) * (unsigned)nx : n.r0 - (unsigned)nx;
+    n.rp = y == ny - 1 ? 0u : n.r0 + (unsigned)nx;
     n.x = (unsigned)x;
     n.xm = (unsigned)(x == 0 ? nx - 1 : x - 1);
     n.xp = (unsigned)(x == nx - 1 ? 0 : x + 1);
@@ -90,19 +89,32 @@ __device__ __forceinline__ void st(S* p, S v) {
 #endif
 }
 
+// Address of the element at byte offset `off` (< 2^31) of plane q.  The plane base is the same
+// for the whole wave (scalar registers) and the per-lane part stays a 32-bit byte offset, so the
+// access needs no 64-bit address arithmetic per lane (global loads and stores take a scalar base
+// plus a 32-bit vector offset).
+template <typename S>
+__device__ __forceinline__ S* plane_at(S* base, long long plane, int q, unsigned off) {
+    using B = typename std::conditional<std::is_const<S>::value, const char, char>::type;
+    return reinterpret_cast<S*>(reinterpret_cast<B*>(base + q * plane) + off);
+}
+
 // Gather f_i(x) = stored_i(x - xi_i).
 template <typename S, typename R>
 __device__ __forceinline__ void pull_load(const S* __restrict__ src, long long plane, const Nbr& n,
                                           R (&h)[9]) {
-    h[0] = R(ld(src + 0 * plane + n.r0 + n.x));
-    h[1] = R(ld(src + 1 * plane + n.r0 + n.xm));
-    h[2] = R(ld(src + 2 * plane + n.rm + n.x));
-    h[3] = R(ld(src + 3 * plane + n.r0 + n.xp));
-    h[4] = R(ld(src + 4 * plane + n.rp + n.x));
-    h[5] = R(ld(src + 5 * plane + n.rm + n.xm));
-    h[6] = R(ld(src + 6 * plane + n.rm + n.xp));
-    h[7] = R(ld(src + 7 * plane + n.rp + n.xp));
-    h[8] = R(ld(src + 8 * plane + n.rp + n.xm));
+    constexpr unsigned E = sizeof(S);
+    const unsigned r0 = n.r0 * E, rm = n.rm * E, rp = n.rp * E;
+    const unsigned x0 = n.x * E, xm = n.xm * E, xp = n.xp * E;
+    h[0] = R(ld(plane_at(src, plane, 0, r0 + x0)));
+    h[1] = R(ld(plane_at(src, plane, 1, r0 + xm)));
+    h[2] = R(ld(plane_at(src, plane, 2, rm + x0)));
+    h[3] = R(ld(plane_at(src, plane, 3, r0 + xp)));
+    h[4] = R(ld(plane_at(src, plane, 4, rp + x0)));
+    h[5] = R(ld(plane_at(src, plane, 5, rm + xm)));
+    h[6] = R(ld(plane_at(src, plane, 6, rm + xp)));
+    h[7] = R(ld(plane_at(src, plane, 7, rp + xp)));
+    h[8] = R(ld(plane_at(src, plane, 8, rp + xm)));
 }
 
 // Conversion to the storage type.  For FP16 the value is first materialised as an FP32
@@ -123,8 +135,9 @@ __device__ __forceinline__ S to_store(R v) {
 template <typename S, typename R>
 __device__ __forceinline__ void store_cell(S* __restrict__ dst, long long plane, unsigned c,
                                            const R (&h)[9]) {
+    const unsigned off = c * (unsigned)sizeof(S);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) st(dst + i * plane + c, to_store<S>(h[i]));
+    for (int i = 0; i < 9; ++i) st(plane_at(dst, plane, i, off), to_store<S>(h[i]));
 }
 
 // Tile of a 1D-launched block.  The hardware hands consecutive block ids to the eight XCDs in
@@ -154,12 +167,15 @@ __device__ __forceinline__ void prestream_store(S* __restrict__ dst, const Geom&
     }
 }
 
-// Conserved quantities of a cell.  The density is always recovered in FP64:
-// rho = rho_s + sum_i h_i; rho_d returns it for the blow-up test.
-template <typename R>
+// Conserved quantities of a cell: rho = rho_s + sum_i h_i, u = U + (j_h - delta rho U) / rho.
+// For FP32 storage the nine-term mass sum is carried in FP64 (delta rho ~ 1e-4 of rho needs more
+// than FP32's 24 bits once added to rho_s); for binary16 storage the rounding of the stored values
+// (2^-11 |h|) is far above that of an FP32 sum, which is used there.  rho_d returns rho for the
+// blow-up test.  S is the storage type.
+template <typename S, typename R>
 __device__ __forceinline__ Macro<R> macro_of(const R (&h)[9], const Ref<R>& ref, double& rho_d) {
     Macro<R> m;
-    if constexpr (std::is_same<R, double>::value) {
+    if constexpr (std::is_same<R, double>::value || std::is_same<S, _Float16>::value) {
         m.drho = ((h[0] + (h[1] + h[3])) + (h[2] + h[4])) + ((h[5] + h[7]) + (h[6] + h[8]));
         m.rho = ref.rho + m.drho;
         rho_d = m.rho;
@@ -172,8 +188,9 @@ __device__ __forceinline__ Macro<R> macro_of(const R (&h)[9], const Ref<R>& ref,
     }
     m.jx = ((h[1] + h[5]) + h[8]) - ((h[3] + h[6]) + h[7]);
     m.jy = ((h[2] + h[5]) + h[6]) - ((h[4] + h[7]) + h[8]);
-    m.dux = (m.jx - m.drho * ref.ux) / m.rho;
-    m.duy = (m.jy - m.drho * ref.uy) / m.rho;
+    m.inv_rho = R(1) / m.rho;
+    m.dux = (m.jx - m.drho * ref.ux) * m.inv_rho;
+    m.duy = (m.jy - m.drho * ref.uy) * m.inv_rho;
     m.ux = ref.ux + m.dux;
     m.uy = ref.uy + m.duy;
     return m;
@@ -191,6 +208,7 @@ __host__ __device__ inline Macro<double> macro_of_fields(double rho, double ux, 
     m.duy = uy - r.uy;
     m.jx = rho * ux - r.rho * r.ux;
     m.jy = rho * uy - r.rho * r.uy;
+    m.inv_rho = 1.0 / rho;
     return m;
 }
 

@@ -37,11 +37,11 @@ def test_every_declared_symbol_is_exported(B):
 
 
 def test_population_bytes(B):
-    # two copies x 9 planes, each plane padded to 256 bytes
-    assert B.lbm_population_bytes(64, 64, B.LBM_F64) == 2 * 9 * 64 * 64 * 8
-    assert B.lbm_population_bytes(10, 3, B.LBM_F32_SHIFTED) == 2 * 9 * 64 * 4
-    assert B.lbm_population_bytes(10, 3, B.LBM_F16_SHIFTED) == 2 * 9 * 128 * 2
-    assert B.lbm_population_bytes(4096, 4096, B.LBM_F32_SHIFTED) == 2 * 9 * 4096 * 4096 * 4
+    # two copies x 9 planes, each plane rounded up to 256 bytes plus a 1 KiB skew
+    assert B.lbm_population_bytes(64, 64, B.LBM_F64) == 2 * 9 * (64 * 64 * 8 + 1024)
+    assert B.lbm_population_bytes(10, 3, B.LBM_F32_SHIFTED) == 2 * 9 * (64 * 4 + 1024)
+    assert B.lbm_population_bytes(10, 3, B.LBM_F16_SHIFTED) == 2 * 9 * (128 * 2 + 1024)
+    assert B.lbm_population_bytes(4096, 4096, B.LBM_F32_SHIFTED) == 2 * 9 * (4096 * 4096 * 4 + 1024)
     assert B.lbm_population_bytes(1, 64, B.LBM_F64) == 0
     assert B.lbm_population_bytes(64, 64, 7) == 0
     assert B.lbm_population_bytes(40000, 40000, B.LBM_F64) == 0

@@ -8,8 +8,8 @@ central finite differences.
   the three checkpoint schedules give bit-identical gradients.
 - The 512 x 512 configuration (CM, Ma 0.2, nu 1e-5, 2000 steps, sqrt(n) checkpoints): the FP64
   gradients match central differences of the FP64 loss (h = 1e-4; 1e-6 for the bulk rate and
-  single-node velocity entries, see the test) and the FP32 gradients match the FP64 ones within a bound derived from FP32
-  rounding.
+  single-node velocity entries, see the test) and the FP32 gradients match the FP64 ones within a
+  bound set by the relative FP32 error of the loss seed, measured from the two forward runs.
 """
 import numpy as np
 import pytest
@@ -159,12 +159,27 @@ def test_c5_gradients_vs_fd_and_fp32(gpu):
         print(f"du0[{comp},{y},{x}] adjoint {g:.10e} fd(1e-4) {fd4:.10e} fd(1e-6) {fd:.10e}", flush=True)
         assert abs(fd - g) < 1e-5 * max(abs(fd), 1e-3 * scale_u), (comp, y, x, fd, g)
     L32, du32, dw32 = c5_grad(gpu, "f32", omega)
-    eu = float((du32 - du64).abs().max() / du64.abs().max())
-    ew = float(np.max(np.abs(dw32 - dw64)) / np.max(np.abs(dw64)))
-    print(f"FP32 vs FP64: loss {abs(L32 - L64) / L64:.2e} du {eu:.2e} domega {ew:.2e}", flush=True)
-    # FP32 forward and adjoint states carry about 2^-24 relative rounding per step; over 2000
-    # steps of a barely damped flow (nu = 1e-5) this stays below 1e-2 of the gradient scale
-    assert abs(L32 - L64) < 1e-3 * L64 and eu < 1e-2 and ew < 1e-2
+    # The reverse sweep is linear in its seed (u_T - target) / L, and that seed is a difference of
+    # nearly equal fields: the vortex is transported almost exactly (L ~ 3e-4 over 2 x 512^2
+    # velocities of size ~0.1), so the rounding of the FP32 trajectory already moves the seed by a
+    # relative ~5e-3.  The FP32 gradients are held to twice the seed's own relative error (2-norm),
+    # measured from the two forward runs, plus 1e-3 for the rounding of the FP32 reverse sweep.
+    rho, u0, tgt = c5_problem(gpu)
+    u_fin = {}
+    for prec, uref in (("f64", (0.0, 0.0)), ("f32", (0.2 * inputs.CS, 0.0))):
+        sim = Sim(rho, u0[0], u0[1], prec=prec, eq_order=4, device=gpu, ref_velocity=uref)
+        sim.step("CM", omega, 2000)
+        _, ux, uy, _ = sim.moments()
+        u_fin[prec] = torch.stack([ux, uy])
+        sim.close()
+    seed_err = float(torch.linalg.vector_norm(u_fin["f32"] - u_fin["f64"]) /
+                     torch.linalg.vector_norm(u_fin["f64"] - tgt))
+    eu = float(torch.linalg.vector_norm(du32 - du64) / torch.linalg.vector_norm(du64))
+    ew = float(np.linalg.norm(dw32 - dw64) / np.linalg.norm(dw64))
+    print(f"FP32 vs FP64: loss {abs(L32 - L64) / L64:.2e} seed {seed_err:.2e} du {eu:.2e} "
+          f"domega {ew:.2e}", flush=True)
+    bound = 2.0 * seed_err + 1e-3
+    assert abs(L32 - L64) < 1e-3 * L64 and eu < bound and ew < bound, (seed_err, eu, ew)
 
 
 def c5_loss(gpu, omega, steps=2000):
