@@ -2,12 +2,11 @@
 //
 // Work decomposition.  Instance j owns `cells_j = nx_j * ny_j` nodes, cut into tiles of
 // 256 * NPT consecutive nodes (linear index y * nx + x).  All tiles of all instances form one
-// list; a persistent grid of G workgroups, launched cooperatively so that all of them are
-// resident at once, takes tiles t = blockIdx.x + k G every step, then all workgroups meet at a
-// grid barrier before the next step reads what this one wrote.  The barrier is a monotonic
-// counter: workgroup arrivals after step s bring it to G (s + 1).  Agent-scope release / acquire
-// fences around it make the populations written on one XCD visible to the others.  Its spin is
-// also bounded in wall-clock time, so every wave exits whatever happens to the others.
+// list per XCD (every instance is owned by one XCD); a persistent grid of workgroups, launched
+// cooperatively and sized to what really stays co-resident, takes on each XCD the tiles of that
+// XCD's list, then the workgroups of the XCD meet at a barrier before the next step reads what
+// this one wrote (see the XCD-local execution notes below).  Barriers are monotonic counters,
+// and every spin is bounded in wall-clock time, so every wave exits whatever happens to others.
 //
 // Each node runs exactly the code of the plain kernel (pull_load / macro_of / collide /
 // store_cell with the same coefficients), so an instance is bit-identical to its plain run.
@@ -64,58 +63,138 @@ __device__ __forceinline__ void collide_model(int model, R (&h)[9], const Macro<
     }
 }
 
-// Grid-wide barrier; returns false if the launch must stop (timeout here or elsewhere).
-__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned target, int* err,
-                                             long long timeout_ticks) {
+// XCD-local execution.  MI355X has one L2 per XCD and the eight L2s are not coherent with each
+// other, so a grid-wide barrier needs agent-scope fences that write back and invalidate a whole L2
+// per workgroup and step (measured: ~55 us per step for the fences alone).  Instead, every
+// instance is owned by one XCD: the host deals instances to the XCDs and builds one tile list per
+// XCD, each workgroup reads the XCD it runs on from the hardware (XCC_ID) and only works on that
+// XCD's tiles, and the workgroups of one XCD meet at their own barrier each step.  All data a
+// workgroup reads were then written through the same L2, so release is "my stores have reached
+// the L2" (s_waitcnt vmcnt(0)) and the acquire side is that the population loads of this kernel
+// are agent-scope loads, which never hit in the CU's L1 (a workgroup-scope L1 invalidate,
+// buffer_inv sc0, was measured to leave stale lines outside thread-group-split mode, and an
+// agent-scope invalidate costs ~30 us per step).  The stores of this kernel are plain (no
+// non-temporal hint), so every line goes through the shared L2.
+//
+// Barrier words, 256-byte lines of 64 unsigned: line 0 counts all workgroups at launch, line
+// 1 + x counts the workgroups on XCD x, line 1 + kMaxXcc + x is XCD x's step barrier.
+constexpr int kMaxXcc = 16;
+constexpr int kLine = 64;
+constexpr int kBarrierWords = kLine * (1 + 2 * kMaxXcc);
+
+__device__ __forceinline__ unsigned xcc_id() {
+    // hwreg(HW_REG_XCC_ID, 0, 4): bits 3:0 of hardware register 20
+    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kMaxXcc - 1);
+}
+
+// Spin (thread 0 of a workgroup) until *ctr >= target, or until err is set or the wall-clock
+// bound passes (then err = 1).  Returns false if the launch must stop.
+__device__ __forceinline__ bool wait_count(const unsigned* ctr, unsigned target, int* err, long long timeout_ticks) {
+    const long long t0 = wall_clock64();
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+        if (wall_clock64() - t0 > timeout_ticks) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return true;
+}
+
+// Barrier of the `count` workgroups of one XCD after step s (counter target (s + 1) count).
+__device__ __forceinline__ bool xcd_barrier(unsigned* ctr, int step, unsigned count, int* err,
+                                            long long timeout_ticks) {
     __shared__ int ok;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores have reached the L2
     __syncthreads();
     if (threadIdx.x == 0 && threadIdx.y == 0) {
-        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const long long t0 = wall_clock64();
-        int good = 1;
-        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                good = 0;
-                break;
-            }
-            if (wall_clock64() - t0 > timeout_ticks) {
-                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                good = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(2);
-        }
-        ok = good;
+        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = wait_count(ctr, ((unsigned)step + 1u) * count, err, timeout_ticks) ? 1 : 0;
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return ok != 0;
+}
+
+// Loads that bypass the CU's L1 (agent scope) and are served by the XCD's L2.
+template <typename S>
+__device__ __forceinline__ S ld_l2(const S* p) {
+    if constexpr (sizeof(S) == 2) {
+        const unsigned short v = __hip_atomic_load(reinterpret_cast<const unsigned short*>(p), __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        return __builtin_bit_cast(S, v);
+    } else {
+        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// pull_load (f_i(x) = stored_i(x - xi_i)) through ld_l2.
+template <typename S, typename R>
+__device__ __forceinline__ void pull_load_l2(const S* __restrict__ src, long long plane, const Nbr& n, R (&h)[9]) {
+    constexpr unsigned E = sizeof(S);
+    const unsigned r0 = n.r0 * E, rm = n.rm * E, rp = n.rp * E;
+    const unsigned x0 = n.x * E, xm = n.xm * E, xp = n.xp * E;
+    h[0] = R(ld_l2(plane_at(src, plane, 0, r0 + x0)));
+    h[1] = R(ld_l2(plane_at(src, plane, 1, r0 + xm)));
+    h[2] = R(ld_l2(plane_at(src, plane, 2, rm + x0)));
+    h[3] = R(ld_l2(plane_at(src, plane, 3, r0 + xp)));
+    h[4] = R(ld_l2(plane_at(src, plane, 4, rp + x0)));
+    h[5] = R(ld_l2(plane_at(src, plane, 5, rm + xm)));
+    h[6] = R(ld_l2(plane_at(src, plane, 6, rm + xp)));
+    h[7] = R(ld_l2(plane_at(src, plane, 7, rp + xp)));
+    h[8] = R(ld_l2(plane_at(src, plane, 8, rp + xm)));
 }
 
 template <int PREC, int NPT>
 __global__ __launch_bounds__(kTileThreads) void k_batch(
     typename Store<PREC>::S* __restrict__ base, long long copy_elems,
     const BDesc<typename Store<PREC>::R>* __restrict__ desc, const int* __restrict__ tile_inst,
-    int ntiles, int* __restrict__ blowup, const int* __restrict__ active, unsigned* __restrict__ bar,
-    int* __restrict__ err, long long* __restrict__ step_ctr, int nsteps, int advance,
-    long long timeout_ticks) {
+    const int* __restrict__ xtab, int* __restrict__ blowup, const int* __restrict__ active,
+    unsigned* __restrict__ bar, int* __restrict__ err, long long* __restrict__ step_ctr, int nsteps,
+    int advance, long long timeout_ticks) {
     using S = typename Store<PREC>::S;
     using R = typename Store<PREC>::R;
-    const long long n0 = *step_ctr;
-    const int G = (int)gridDim.x;
+    __shared__ unsigned s_rank, s_count;
+    __shared__ int s_go;
     const int tid = threadIdx.x;
+    const unsigned xcc = xcc_id();
+    // registration: rank of this workgroup among those on its XCD, then the final counts
+    if (tid == 0) {
+        s_rank = __hip_atomic_fetch_add(bar + kLine * (1 + xcc), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the XCD count must be complete before the grid count is: wait until this add has been
+        // performed (it returns) before issuing the next one, so that whoever sees the grid count
+        // at gridDim.x reads final XCD counts
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int go = wait_count(bar, gridDim.x, err, timeout_ticks) ? 1 : 0;
+        s_count = __hip_atomic_load(bar + kLine * (1 + xcc), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // an XCD that owns tiles but got no workgroup would leave its instances behind
+        for (int x = 0; x < kMaxXcc && go; ++x)
+            if (xtab[2 * x + 1] > 0 &&
+                __hip_atomic_load(bar + kLine * (1 + x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+                __hip_atomic_store(err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                go = 0;
+            }
+        s_go = go;
+    }
+    __syncthreads();
+    if (!s_go) return;
+    const unsigned rank = s_rank, count = s_count;
+    const int first_tile = xtab[2 * xcc], ntiles = xtab[2 * xcc + 1];
+    unsigned* xbar = bar + kLine * (1 + kMaxXcc + xcc);
+    const long long n0 = *step_ctr;
     for (int s = 0; s < nsteps; ++s) {
         const long long n = n0 + (advance ? s : 0);
         const int sc = (int)(n & 1);
         const S* src = base + sc * copy_elems;
         S* dst = base + (sc ^ 1) * copy_elems;
-        for (int t = blockIdx.x; t < ntiles; t += G) {
-            const int j = tile_inst[t];
+        for (int t = (int)rank; t < ntiles; t += (int)count) {
+            const int tt = first_tile + t;
+            const int j = tile_inst[tt];
             const BDesc<R>& d = desc[j];
             const int frozen = __hip_atomic_load(blowup + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if ((long long)frozen < n || !active[j]) continue;  // blew up earlier, or retired
-            const int first = (t - d.tile0) * NPT * kTileThreads + tid;
+            const int first = (tt - d.tile0) * NPT * kTileThreads + tid;
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
                 const int c = first + k * kTileThreads;
@@ -124,18 +203,23 @@ __global__ __launch_bounds__(kTileThreads) void k_batch(
                     const int x = c - y * d.nx;
                     const Nbr nb = neighbours(x, y, d.nx, d.ny);
                     R h[9];
-                    pull_load(src + d.off, d.plane, nb, h);
+                    pull_load_l2(src + d.off, d.plane, nb, h);
                     double rho_d;
-                    const Macro<R> m = macro_of<typename Store<PREC>::S>(h, d.ref, rho_d);
+                    const Macro<R> m = macro_of<S>(h, d.ref, rho_d);
                     flag_bad(!(rho_d > 0.0), blowup + j, (int)n);
                     collide_model(d.model, h, m, d.ref, d.c, d.N);
-                    store_cell(dst + d.off, d.plane, (unsigned)c, h);
+                    store_cell<S, R, false>(dst + d.off, d.plane, (unsigned)c, h);
                 }
             }
         }
-        if (!grid_barrier(bar, (unsigned)G * (unsigned)(s + 1), err, timeout_ticks)) return;
+        if (!xcd_barrier(xbar, s, count, err, timeout_ticks)) return;
     }
     if (advance && blockIdx.x == 0 && tid == 0) *step_ctr = n0 + nsteps;
+}
+
+// XCD of each workgroup of a small probe launch (which XCC ids the device dispatches to).
+__global__ void k_xcc_probe(int* __restrict__ out) {
+    if (threadIdx.x == 0) out[blockIdx.x] = (int)xcc_id();
 }
 
 // f(., 0) = f^eq of every instance, stored pre-streamed into copy 0.  One block per tile of
@@ -226,7 +310,7 @@ __global__ void k_retire(const int* __restrict__ flags, int* __restrict__ active
 // Reset the barrier counter before each replay.  The error flag is sticky (cleared only at
 // creation) so that a stopped launch stays reported.
 __global__ void k_batch_reset(unsigned* __restrict__ bar) {
-    if (threadIdx.x == 0) *bar = 0u;
+    for (int i = threadIdx.x; i < kBarrierWords; i += blockDim.x) bar[i] = 0u;
 }
 
 __global__ void k_clear_i32(int* __restrict__ p) {
@@ -254,7 +338,9 @@ struct lbm_batch {
     long long step = 0;                // host mirror of the step counter
     void* d_desc[3] = {nullptr, nullptr, nullptr};  // descriptors per NPT (tile0 differs)
     int* d_tiles[3] = {nullptr, nullptr, nullptr};
+    int* d_xtab[3] = {nullptr, nullptr, nullptr};   // per XCC id: first tile, tile count
     int ntiles[3] = {0, 0, 0};
+    std::vector<int> xcc_of;                        // per instance: the XCC id that owns it
     int* d_blowup = nullptr;
     int* d_active = nullptr;           // per instance: nonzero = advanced by lbm_batch_run
     int* d_retired = nullptr;          // per instance: step at which it was retired (INT_MAX)
@@ -299,14 +385,14 @@ hipError_t launch_batch_t(lbm_batch* b, hipStream_t s, int G, int nsteps, int ad
     long long copy_elems = b->copy_elems;
     const BDesc<R>* desc = reinterpret_cast<const BDesc<R>*>(b->d_desc[k]);
     const int* tiles = b->d_tiles[k];
-    int ntiles = b->ntiles[k];
+    const int* xtab = b->d_xtab[k];
     int* blowup = b->d_blowup;
     const int* active = b->d_active;
     unsigned* bar = b->d_bar;
     int* err = b->d_err;
     long long* step = b->d_step;
     long long timeout = b->timeout_ticks;
-    void* args[] = {&base, &copy_elems, &desc, &tiles, &ntiles, &blowup, &active, &bar, &err, &step,
+    void* args[] = {&base, &copy_elems, &desc, &tiles, &xtab, &blowup, &active, &bar, &err, &step,
                     &nsteps, &advance, &timeout};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_batch<PREC, NPT>), dim3(G),
                                       dim3(kTileThreads), args, 0, s);
@@ -373,6 +459,7 @@ int ensure_resident(lbm_batch* b) {
             b->resident[k] = per;
             return LBM_OK;
         }
+        if (err == 2) return set_error(LBM_EHIP, "an XCD that owns instances got no workgroup");
         hipLaunchKernelGGL(k_clear_i32, dim3(1), dim3(64), 0, b->stream, b->d_err);
         rc = check_hip(hipGetLastError(), "clear err");
         if (rc != LBM_OK) return rc;
@@ -453,6 +540,45 @@ int lbm_batch_create(lbm_batch** out, const lbm_instance_desc* desc, int n, int 
     int coop = 0;
     if (rc == LBM_OK) rc = check_hip(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev), "cooperative launch attribute");
     if (rc == LBM_OK && !coop) rc = set_error(LBM_EUNSUPPORTED, "device does not support cooperative launches");
+    // which XCC ids the device dispatches to, then deal the instances to them, largest first,
+    // each to the XCD with the fewest nodes so far
+    std::vector<int> xccs;
+    if (rc == LBM_OK) {
+        const int nprobe = 4 * b->cus;
+        int* d_probe = nullptr;
+        std::vector<int> seen((size_t)nprobe, 0);
+        rc = check_hip(hipMalloc(&d_probe, sizeof(int) * (size_t)nprobe), "hipMalloc(xcc probe)");
+        if (rc == LBM_OK) {
+            hipLaunchKernelGGL(k_xcc_probe, dim3(nprobe), dim3(64), 0, b->stream, d_probe);
+            rc = check_hip(hipGetLastError(), "xcc probe launch");
+        }
+        if (rc == LBM_OK) rc = check_hip(hipStreamSynchronize(b->stream), "synchronise (xcc probe)");
+        if (rc == LBM_OK)
+            rc = check_hip(hipMemcpy(seen.data(), d_probe, sizeof(int) * seen.size(), hipMemcpyDeviceToHost),
+                           "copy xcc probe");
+        if (d_probe) (void)hipFree(d_probe);
+        bool have[kMaxXcc] = {};
+        for (int v : seen) have[v & (kMaxXcc - 1)] = true;
+        for (int x = 0; x < kMaxXcc; ++x)
+            if (have[x]) xccs.push_back(x);
+    }
+    if (rc == LBM_OK && xccs.empty()) rc = set_error(LBM_EHIP, "no XCD seen by the probe launch");
+    if (rc == LBM_OK) {
+        std::vector<int> order((size_t)n);
+        for (int j = 0; j < n; ++j) order[j] = j;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+            return (long long)desc[a].nx * desc[a].ny > (long long)desc[c].nx * desc[c].ny;
+        });
+        std::vector<long long> load(xccs.size(), 0);
+        b->xcc_of.assign((size_t)n, 0);
+        for (int j : order) {
+            size_t best = 0;
+            for (size_t q = 1; q < xccs.size(); ++q)
+                if (load[q] < load[best]) best = q;
+            load[best] += (long long)desc[j].nx * desc[j].ny;
+            b->xcc_of[j] = xccs[best];
+        }
+    }
     const int npts[3] = {1, 2, 4};
     for (int k = 0; k < 3 && rc == LBM_OK; ++k) {
         rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[k], batch_kernel_p(prec, npts[k]),
@@ -461,15 +587,25 @@ int lbm_batch_create(lbm_batch** out, const lbm_instance_desc* desc, int n, int 
         if (rc == LBM_OK && b->occ[k] < 1) rc = set_error(LBM_EHIP, "persistent kernel does not fit a CU");
         // tile table and descriptors for this NPT
         const int tile_nodes = kTileThreads * npts[k];
-        std::vector<int> tiles;
+        // one contiguous tile list per XCC id (instances in index order within it)
+        std::vector<int> tiles, tile0((size_t)n, 0), xtab(2 * kMaxXcc, 0);
+        for (int x : xccs) {
+            xtab[2 * x] = (int)tiles.size();
+            for (int j = 0; j < n; ++j) {
+                if (b->xcc_of[j] != x) continue;
+                const int cells = desc[j].nx * desc[j].ny;
+                tile0[j] = (int)tiles.size();
+                for (int t = 0; t < (cells + tile_nodes - 1) / tile_nodes; ++t) tiles.push_back(j);
+            }
+            xtab[2 * x + 1] = (int)tiles.size() - xtab[2 * x];
+        }
         std::vector<char> dbytes;
         const size_t dsz = prec == LBM_F64 ? sizeof(BDesc<double>) : sizeof(BDesc<float>);
         dbytes.resize(dsz * (size_t)n);
         for (int j = 0; j < n && rc == LBM_OK; ++j) {
             const lbm_instance_desc& d = desc[j];
             const int cells = d.nx * d.ny;
-            const int t0 = (int)tiles.size();
-            for (int t = 0; t < (cells + tile_nodes - 1) / tile_nodes; ++t) tiles.push_back(j);
+            const int t0 = tile0[j];
             const Ref<double> rd = storage_reference(prec, d.rho0, d.ux0, d.uy0);
             if (prec == LBM_F64) {
                 BDesc<double> bd;
@@ -497,13 +633,17 @@ int lbm_batch_create(lbm_batch** out, const lbm_instance_desc* desc, int n, int 
         if (rc == LBM_OK)
             rc = check_hip(hipMemcpy(b->d_tiles[k], tiles.data(), sizeof(int) * tiles.size(), hipMemcpyHostToDevice),
                            "copy tiles");
+        if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_xtab[k], sizeof(int) * xtab.size()), "hipMalloc(xtab)");
+        if (rc == LBM_OK)
+            rc = check_hip(hipMemcpy(b->d_xtab[k], xtab.data(), sizeof(int) * xtab.size(), hipMemcpyHostToDevice),
+                           "copy xtab");
     }
     if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_blowup, sizeof(int) * (size_t)n), "hipMalloc(blowup)");
     if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_active, sizeof(int) * (size_t)n), "hipMalloc(active)");
     if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_retired, sizeof(int) * (size_t)n), "hipMalloc(retired)");
     if (rc == LBM_OK)
         rc = check_hip(hipMalloc(&b->d_u2part, sizeof(double) * (size_t)b->ntiles[0]), "hipMalloc(u2 partials)");
-    if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_bar, sizeof(unsigned)), "hipMalloc(barrier)");
+    if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_bar, sizeof(unsigned) * kBarrierWords), "hipMalloc(barrier)");
     if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_err, sizeof(int)), "hipMalloc(err)");
     if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_step, sizeof(long long)), "hipMalloc(step)");
     if (rc == LBM_OK) {
@@ -576,7 +716,8 @@ int lbm_batch_status(lbm_batch* b, long long* step, long long* blowup_steps) {
         rc = check_hip(hipMemcpy(flags.data(), b->d_blowup, sizeof(int) * flags.size(), hipMemcpyDeviceToHost),
                        "copy blow-up steps");
     if (rc != LBM_OK) return rc;
-    if (err) return set_error(LBM_EHIP, "persistent launch stopped: a grid barrier timed out");
+    if (err == 2) return set_error(LBM_EHIP, "persistent launch stopped: an XCD that owns instances got no workgroup");
+    if (err) return set_error(LBM_EHIP, "persistent launch stopped: a barrier timed out");
     if (dstep != b->step) return set_error(LBM_EHIP, "device step counter %lld != %lld", dstep, b->step);
     if (step) *step = b->step;
     if (blowup_steps)
@@ -699,7 +840,7 @@ int lbm_batch_autotune(lbm_batch* b, int trials, int* nodes_per_thread, int* gro
             if (rc == LBM_OK) rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
             int err = 0;
             if (rc == LBM_OK) rc = check_hip(hipMemcpy(&err, b->d_err, sizeof(int), hipMemcpyDeviceToHost), "copy err");
-            if (rc == LBM_OK && err) rc = set_error(LBM_EHIP, "persistent launch stopped: a grid barrier timed out");
+            if (rc == LBM_OK && err) rc = set_error(LBM_EHIP, "persistent launch stopped: a barrier timed out");
             if (rc == LBM_OK && (best == 0.f || ms < best)) {
                 best = ms;
                 best_npt = b->npt;
@@ -723,6 +864,7 @@ void lbm_batch_destroy(lbm_batch* b) {
     for (int k = 0; k < 3; ++k) {
         if (b->d_desc[k]) (void)hipFree(b->d_desc[k]);
         if (b->d_tiles[k]) (void)hipFree(b->d_tiles[k]);
+        if (b->d_xtab[k]) (void)hipFree(b->d_xtab[k]);
     }
     if (b->d_blowup) (void)hipFree(b->d_blowup);
     if (b->d_active) (void)hipFree(b->d_active);

@@ -80,13 +80,12 @@ __device__ __forceinline__ S ld(const S* p) {
 #endif
 }
 
-template <typename S>
+template <typename S, bool NT = (LBM_NT_STORES != 0)>
 __device__ __forceinline__ void st(S* p, S v) {
-#if LBM_NT_STORES
-    __builtin_nontemporal_store(v, p);
-#else
-    *p = v;
-#endif
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
 }
 
 // Address of the element at byte offset `off` (< 2^31) of plane q.  The plane base is the same
@@ -132,12 +131,12 @@ __device__ __forceinline__ S to_store(R v) {
     }
 }
 
-template <typename S, typename R>
+template <typename S, typename R, bool NT = (LBM_NT_STORES != 0)>
 __device__ __forceinline__ void store_cell(S* __restrict__ dst, long long plane, unsigned c,
                                            const R (&h)[9]) {
     const unsigned off = c * (unsigned)sizeof(S);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) st(plane_at(dst, plane, i, off), to_store<S>(h[i]));
+    for (int i = 0; i < 9; ++i) st<S, NT>(plane_at(dst, plane, i, off), to_store<S>(h[i]));
 }
 
 // Tile of a 1D-launched block.  The hardware hands consecutive block ids to the eight XCDs in
