@@ -121,8 +121,9 @@ def time_models(prec: str, n: int, models, steps: int, warmup: int, omega, field
 def batched_sweep(steps: int, plain_f64_mlups: float, n_inst: int = 512):
     """Random stability sweep: n_inst instances (side in {64..512}, Ma in [0, 0.6], log10 nu in
     [-7, -2], model uniform over the eight, one Fourier-mode perturbation of amplitude 1e-3),
-    FP64, advanced by one persistent launch.  Throughput counts the nodes actually updated
-    (an instance stops after the step at which it blew up)."""
+    FP64, advanced by the persistent kernel in pieces of 500 steps with the live instances
+    re-dealt over the XCDs in between.  Throughput counts the nodes actually updated (an
+    instance stops after the step at which it blew up)."""
     import torch
 
     from paper_2002_05265_amd import inputs
@@ -139,7 +140,7 @@ def batched_sweep(steps: int, plain_f64_mlups: float, n_inst: int = 512):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
-    b.run(steps)
+    b.run(steps, rebalance_every=500)  # blown-up instances leave the per-XCD work lists
     e1.record()
     torch.cuda.synchronize()
     sec = e0.elapsed_time(e1) * 1e-3
@@ -172,7 +173,7 @@ def batched_sweep(steps: int, plain_f64_mlups: float, n_inst: int = 512):
             "blown_up": int(sum(1 for bl in blow if bl >= 0)),
             "blowup_steps_first10": blow[:10],
             "autotuned": {"nodes_per_thread": tuned[0], "groups_per_cu": tuned[1]},
-            "precision": "f64"}
+            "rebalance_every": 500, "precision": "f64"}
 
 
 def stability_map(L: int = 32, M: float = 50.0):

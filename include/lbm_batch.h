@@ -93,6 +93,12 @@ int lbm_batch_mean_u2(lbm_batch* b, double* mean_u2);
  * Asynchronous. */
 int lbm_batch_set_active(lbm_batch* b, const int* active);
 
+/* Re-deal the live instances (neither blown up nor retired) over the XCDs, largest first, so that
+ * every XCD keeps a similar number of nodes to advance as instances drop out; instances that are
+ * no longer live leave the per-XCD work lists.  Results are unchanged: an instance's arithmetic is
+ * the same on every XCD.  Synchronises the stream. */
+int lbm_batch_rebalance(lbm_batch* b);
+
 /* Launch shape of the persistent kernel: nodes per thread per tile (1, 2 or 4) and resident
  * workgroups per CU (1 .. the probed residency limit; 0 = that limit).  Takes effect at the next
  * lbm_batch_run. */

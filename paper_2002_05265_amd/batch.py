@@ -36,8 +36,23 @@ class Batch:
                                          self.pop.data_ptr(), nbytes, self.stream.cuda_stream)
         self.stream.synchronize()
 
-    def run(self, nsteps: int):
-        B.lbm_batch_run(self.handle, nsteps)
+    def run(self, nsteps: int, rebalance_every: int = 0):
+        """Advance nsteps; with rebalance_every > 0 the run is cut into pieces of that many steps
+        and the live instances are re-dealt over the XCDs between pieces (synchronising)."""
+        if rebalance_every <= 0:
+            B.lbm_batch_run(self.handle, nsteps)
+            return
+        done = 0
+        while done < nsteps:
+            k = min(rebalance_every, nsteps - done)
+            B.lbm_batch_run(self.handle, k)
+            done += k
+            if done < nsteps:
+                B.lbm_batch_rebalance(self.handle)
+
+    def rebalance(self):
+        """Re-deal the live instances over the XCDs (synchronises)."""
+        B.lbm_batch_rebalance(self.handle)
 
     def status(self):
         """(step, [blow-up step per instance, -1 if none])"""

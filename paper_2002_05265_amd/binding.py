@@ -26,7 +26,8 @@ EXPORTS = (
     "lbm_get_state", "lbm_set_state", "lbm_set_launch", "lbm_autotune", "lbm_destroy",
     "lbm_last_error",
     "lbm_batch_population_bytes", "lbm_batch_create", "lbm_batch_run", "lbm_batch_status",
-    "lbm_batch_get_state", "lbm_batch_mean_u2", "lbm_batch_set_active", "lbm_batch_set_launch",
+    "lbm_batch_get_state", "lbm_batch_mean_u2", "lbm_batch_set_active", "lbm_batch_rebalance",
+    "lbm_batch_set_launch",
     "lbm_batch_autotune", "lbm_batch_destroy",
     "lbm_state_bytes", "lbm_adjoint_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_raw",
     "lbm_step_raw_many", "lbm_adjoint_many", "lbm_adjoint_flush",
@@ -75,6 +76,7 @@ def _declare(L: ctypes.CDLL):
         "lbm_batch_get_state": (_i, [_vp, _i, _vp]),
         "lbm_batch_mean_u2": (_i, [_vp, _vp]),
         "lbm_batch_set_active": (_i, [_vp, _vp]),
+        "lbm_batch_rebalance": (_i, [_vp]),
         "lbm_batch_set_launch": (_i, [_vp, _i, _i]),
         "lbm_batch_autotune": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), _dp]),
         "lbm_batch_destroy": (None, [_vp]),
@@ -234,6 +236,10 @@ def lbm_batch_mean_u2(b: int, mean_u2: int):
 
 def lbm_batch_set_active(b: int, active: int):
     _check(lib().lbm_batch_set_active(b, active), "lbm_batch_set_active")
+
+
+def lbm_batch_rebalance(b: int):
+    _check(lib().lbm_batch_rebalance(b), "lbm_batch_rebalance")
 
 
 def lbm_batch_set_launch(b: int, nodes_per_thread: int, groups_per_cu: int):

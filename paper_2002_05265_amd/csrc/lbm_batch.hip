@@ -148,7 +148,7 @@ __device__ __forceinline__ void pull_load_l2(const S* __restrict__ src, long lon
 template <int PREC, int NPT>
 __global__ __launch_bounds__(kTileThreads) void k_batch(
     typename Store<PREC>::S* __restrict__ base, long long copy_elems,
-    const BDesc<typename Store<PREC>::R>* __restrict__ desc, const int* __restrict__ tile_inst,
+    const BDesc<typename Store<PREC>::R>* __restrict__ desc, const int2* __restrict__ run,
     const int* __restrict__ xtab, int* __restrict__ blowup, const int* __restrict__ active,
     unsigned* __restrict__ bar, int* __restrict__ err, long long* __restrict__ step_ctr, int nsteps,
     int advance, long long timeout_ticks) {
@@ -189,12 +189,12 @@ __global__ __launch_bounds__(kTileThreads) void k_batch(
         const S* src = base + sc * copy_elems;
         S* dst = base + (sc ^ 1) * copy_elems;
         for (int t = (int)rank; t < ntiles; t += (int)count) {
-            const int tt = first_tile + t;
-            const int j = tile_inst[tt];
+            const int2 e = run[first_tile + t];  // (instance, tile within the instance)
+            const int j = e.x;
             const BDesc<R>& d = desc[j];
             const int frozen = __hip_atomic_load(blowup + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if ((long long)frozen < n || !active[j]) continue;  // blew up earlier, or retired
-            const int first = (tt - d.tile0) * NPT * kTileThreads + tid;
+            const int first = e.y * NPT * kTileThreads + tid;
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
                 const int c = first + k * kTileThreads;
@@ -337,10 +337,11 @@ struct lbm_batch {
     int npt = 1, gpc = 0;              // launch shape (gpc 0 = occupancy limit)
     long long step = 0;                // host mirror of the step counter
     void* d_desc[3] = {nullptr, nullptr, nullptr};  // descriptors per NPT (tile0 differs)
-    int* d_tiles[3] = {nullptr, nullptr, nullptr};
-    int* d_xtab[3] = {nullptr, nullptr, nullptr};   // per XCC id: first tile, tile count
+    int* d_tiles[3] = {nullptr, nullptr, nullptr};  // every tile of every instance, instance order
     int ntiles[3] = {0, 0, 0};
-    std::vector<int> xcc_of;                        // per instance: the XCC id that owns it
+    int2* d_run[3] = {nullptr, nullptr, nullptr};   // tiles of live instances, one list per XCD
+    int* d_xtab[3] = {nullptr, nullptr, nullptr};   // per XCC id: first run entry, entry count
+    std::vector<int> xccs;                          // XCC ids the device dispatches to
     int* d_blowup = nullptr;
     int* d_active = nullptr;           // per instance: nonzero = advanced by lbm_batch_run
     int* d_retired = nullptr;          // per instance: step at which it was retired (INT_MAX)
@@ -384,7 +385,7 @@ hipError_t launch_batch_t(lbm_batch* b, hipStream_t s, int G, int nsteps, int ad
     S* base = reinterpret_cast<S*>(b->buf);
     long long copy_elems = b->copy_elems;
     const BDesc<R>* desc = reinterpret_cast<const BDesc<R>*>(b->d_desc[k]);
-    const int* tiles = b->d_tiles[k];
+    const int2* tiles = b->d_run[k];
     const int* xtab = b->d_xtab[k];
     int* blowup = b->d_blowup;
     const int* active = b->d_active;
@@ -405,6 +406,51 @@ hipError_t launch_batch_p(lbm_batch* b, hipStream_t s, int G, int nsteps, int ad
         case 2: return launch_batch_t<PREC, 2>(b, s, G, nsteps, advance);
         default: return launch_batch_t<PREC, 1>(b, s, G, nsteps, advance);
     }
+}
+
+// Deal the live instances to the XCDs, largest first, each to the XCD with the fewest nodes so
+// far, and write each launch shape's run table (one contiguous list of (instance, tile) per XCD,
+// instances in index order within it) and XCD table.  Synchronous.
+int deal_tables(lbm_batch* b, const std::vector<char>& live) {
+    const int n = b->n;
+    std::vector<int> order;
+    for (int j = 0; j < n; ++j)
+        if (live[j]) order.push_back(j);
+    auto cells = [&](int j) { return (long long)b->hdesc[j].nx * b->hdesc[j].ny; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cells(a) > cells(c); });
+    std::vector<long long> load(b->xccs.size(), 0);
+    std::vector<int> owner((size_t)n, -1);
+    for (int j : order) {
+        size_t best = 0;
+        for (size_t q = 1; q < b->xccs.size(); ++q)
+            if (load[q] < load[best]) best = q;
+        load[best] += cells(j);
+        owner[j] = b->xccs[best];
+    }
+    const int npts[3] = {1, 2, 4};
+    for (int k = 0; k < 3; ++k) {
+        const long long tile_nodes = (long long)kTileThreads * npts[k];
+        std::vector<int2> run;
+        std::vector<int> xtab(2 * kMaxXcc, 0);
+        for (int x : b->xccs) {
+            xtab[2 * x] = (int)run.size();
+            for (int j = 0; j < n; ++j) {
+                if (owner[j] != x) continue;
+                const int nt = (int)((cells(j) + tile_nodes - 1) / tile_nodes);
+                for (int t = 0; t < nt; ++t) run.push_back(make_int2(j, t));
+            }
+            xtab[2 * x + 1] = (int)run.size() - xtab[2 * x];
+        }
+        int rc = LBM_OK;
+        if (!run.empty())
+            rc = check_hip(hipMemcpy(b->d_run[k], run.data(), sizeof(int2) * run.size(), hipMemcpyHostToDevice),
+                           "copy run table");
+        if (rc == LBM_OK)
+            rc = check_hip(hipMemcpy(b->d_xtab[k], xtab.data(), sizeof(int) * xtab.size(), hipMemcpyHostToDevice),
+                           "copy xtab");
+        if (rc != LBM_OK) return rc;
+    }
+    return LBM_OK;
 }
 
 int groups_limit(lbm_batch* b) {
@@ -540,9 +586,8 @@ int lbm_batch_create(lbm_batch** out, const lbm_instance_desc* desc, int n, int 
     int coop = 0;
     if (rc == LBM_OK) rc = check_hip(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev), "cooperative launch attribute");
     if (rc == LBM_OK && !coop) rc = set_error(LBM_EUNSUPPORTED, "device does not support cooperative launches");
-    // which XCC ids the device dispatches to, then deal the instances to them, largest first,
-    // each to the XCD with the fewest nodes so far
-    std::vector<int> xccs;
+    // which XCC ids the device dispatches to (the instances are dealt to them below)
+    std::vector<int>& xccs = b->xccs;
     if (rc == LBM_OK) {
         const int nprobe = 4 * b->cus;
         int* d_probe = nullptr;
@@ -563,22 +608,6 @@ int lbm_batch_create(lbm_batch** out, const lbm_instance_desc* desc, int n, int 
             if (have[x]) xccs.push_back(x);
     }
     if (rc == LBM_OK && xccs.empty()) rc = set_error(LBM_EHIP, "no XCD seen by the probe launch");
-    if (rc == LBM_OK) {
-        std::vector<int> order((size_t)n);
-        for (int j = 0; j < n; ++j) order[j] = j;
-        std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
-            return (long long)desc[a].nx * desc[a].ny > (long long)desc[c].nx * desc[c].ny;
-        });
-        std::vector<long long> load(xccs.size(), 0);
-        b->xcc_of.assign((size_t)n, 0);
-        for (int j : order) {
-            size_t best = 0;
-            for (size_t q = 1; q < xccs.size(); ++q)
-                if (load[q] < load[best]) best = q;
-            load[best] += (long long)desc[j].nx * desc[j].ny;
-            b->xcc_of[j] = xccs[best];
-        }
-    }
     const int npts[3] = {1, 2, 4};
     for (int k = 0; k < 3 && rc == LBM_OK; ++k) {
         rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[k], batch_kernel_p(prec, npts[k]),
@@ -587,17 +616,11 @@ int lbm_batch_create(lbm_batch** out, const lbm_instance_desc* desc, int n, int 
         if (rc == LBM_OK && b->occ[k] < 1) rc = set_error(LBM_EHIP, "persistent kernel does not fit a CU");
         // tile table and descriptors for this NPT
         const int tile_nodes = kTileThreads * npts[k];
-        // one contiguous tile list per XCC id (instances in index order within it)
-        std::vector<int> tiles, tile0((size_t)n, 0), xtab(2 * kMaxXcc, 0);
-        for (int x : xccs) {
-            xtab[2 * x] = (int)tiles.size();
-            for (int j = 0; j < n; ++j) {
-                if (b->xcc_of[j] != x) continue;
-                const int cells = desc[j].nx * desc[j].ny;
-                tile0[j] = (int)tiles.size();
-                for (int t = 0; t < (cells + tile_nodes - 1) / tile_nodes; ++t) tiles.push_back(j);
-            }
-            xtab[2 * x + 1] = (int)tiles.size() - xtab[2 * x];
+        std::vector<int> tiles, tile0((size_t)n, 0);
+        for (int j = 0; j < n; ++j) {
+            const int cells = desc[j].nx * desc[j].ny;
+            tile0[j] = (int)tiles.size();
+            for (int t = 0; t < (cells + tile_nodes - 1) / tile_nodes; ++t) tiles.push_back(j);
         }
         std::vector<char> dbytes;
         const size_t dsz = prec == LBM_F64 ? sizeof(BDesc<double>) : sizeof(BDesc<float>);
@@ -633,11 +656,10 @@ int lbm_batch_create(lbm_batch** out, const lbm_instance_desc* desc, int n, int 
         if (rc == LBM_OK)
             rc = check_hip(hipMemcpy(b->d_tiles[k], tiles.data(), sizeof(int) * tiles.size(), hipMemcpyHostToDevice),
                            "copy tiles");
-        if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_xtab[k], sizeof(int) * xtab.size()), "hipMalloc(xtab)");
-        if (rc == LBM_OK)
-            rc = check_hip(hipMemcpy(b->d_xtab[k], xtab.data(), sizeof(int) * xtab.size(), hipMemcpyHostToDevice),
-                           "copy xtab");
+        if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_run[k], sizeof(int2) * tiles.size()), "hipMalloc(run)");
+        if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_xtab[k], sizeof(int) * 2 * kMaxXcc), "hipMalloc(xtab)");
     }
+    if (rc == LBM_OK) rc = deal_tables(b, std::vector<char>((size_t)n, 1));
     if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_blowup, sizeof(int) * (size_t)n), "hipMalloc(blowup)");
     if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_active, sizeof(int) * (size_t)n), "hipMalloc(active)");
     if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_retired, sizeof(int) * (size_t)n), "hipMalloc(retired)");
@@ -802,6 +824,22 @@ int lbm_batch_set_active(lbm_batch* b, const int* active) {
     return check_hip(hipGetLastError(), "batch set_active launch");
 }
 
+int lbm_batch_rebalance(lbm_batch* b) {
+    if (!b) return set_error(LBM_ESTATE, "batch is NULL");
+    std::vector<int> blow((size_t)b->n), ret((size_t)b->n);
+    int rc = check_hip(hipStreamSynchronize(b->stream), "synchronise");
+    if (rc == LBM_OK)
+        rc = check_hip(hipMemcpy(blow.data(), b->d_blowup, sizeof(int) * blow.size(), hipMemcpyDeviceToHost),
+                       "copy blow-up steps");
+    if (rc == LBM_OK)
+        rc = check_hip(hipMemcpy(ret.data(), b->d_retired, sizeof(int) * ret.size(), hipMemcpyDeviceToHost),
+                       "copy retired steps");
+    if (rc != LBM_OK) return rc;
+    std::vector<char> live((size_t)b->n);
+    for (int j = 0; j < b->n; ++j) live[j] = blow[j] == INT_MAX && ret[j] == INT_MAX;
+    return deal_tables(b, live);
+}
+
 int lbm_batch_set_launch(lbm_batch* b, int nodes_per_thread, int groups_per_cu) {
     if (!b) return set_error(LBM_ESTATE, "batch is NULL");
     if (nodes_per_thread != 1 && nodes_per_thread != 2 && nodes_per_thread != 4)
@@ -865,6 +903,7 @@ void lbm_batch_destroy(lbm_batch* b) {
         if (b->d_desc[k]) (void)hipFree(b->d_desc[k]);
         if (b->d_tiles[k]) (void)hipFree(b->d_tiles[k]);
         if (b->d_xtab[k]) (void)hipFree(b->d_xtab[k]);
+        if (b->d_run[k]) (void)hipFree(b->d_run[k]);
     }
     if (b->d_blowup) (void)hipFree(b->d_blowup);
     if (b->d_active) (void)hipFree(b->d_active);

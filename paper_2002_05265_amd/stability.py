@@ -84,8 +84,10 @@ def run_stability(instances, prec: str = "f64", check_every: int = 64, beta: flo
             active = (live & ~bad & (budget_d > step)).to(torch.int32)
             b.set_active(active)
             k_chunk += 1
-            if k_chunk % 64 == 0 and not bool(active.any()):
-                break
+            if k_chunk % 16 == 0:
+                if not bool(active.any()):
+                    break
+                b.rebalance()  # retired runs leave the per-XCD work lists
         e1.record()
         _, blow = b.status()
         sec = e0.elapsed_time(e1) * 1e-3

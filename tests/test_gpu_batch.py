@@ -4,7 +4,8 @@
   for every model, equilibrium order, uneven grid sizes and all three precisions.
 - Blow-up steps equal those of the plain kernel; a NaN injected into one instance's initial
   fields flags that instance at step 0 and leaves every other instance bit-identical.
-- Autotuning and chunked runs leave the results unchanged.
+- Autotuning, chunked runs and re-dealing the live instances over the XCDs leave the results
+  unchanged.
 - A stratified subset (every model, small grids) matches the oracle (FP64 within 1e-12, or
   the same blow-up step within one step).  Random sweep parameters include linearly unstable
   runs that have not yet lost positivity; there rounding-level differences grow step by step,
@@ -86,6 +87,13 @@ def test_batch_shapes_and_chunks_agree(gpu):
         for k in range(len(insts)):
             np.testing.assert_array_equal(b.state(k).cpu().numpy(), want[k])
         b.close()
+    # re-dealing the instances over the XCDs between pieces of a run changes nothing
+    b = Batch(insts, fields, device=gpu)
+    b.run(24, rebalance_every=5)
+    assert b.status()[0] == 24
+    for k in range(len(insts)):
+        np.testing.assert_array_equal(b.state(k).cpu().numpy(), want[k])
+    b.close()
     b = Batch(insts, fields, device=gpu)
     b.run(5)
     npt, gpc, us = b.autotune(3)
@@ -126,7 +134,7 @@ def test_batch_blowup_and_nan_isolation(gpu):
     bad = [tuple(np.array(a) for a in f) for f in fields]
     bad[5][1][10, 20] = np.nan
     b2 = Batch(insts, bad, device=gpu)
-    b2.run(steps)
+    b2.run(steps, rebalance_every=50)  # the blown-up instances leave the work lists
     _, blow2 = b2.status()
     assert blow2[5] == 0
     for k in range(len(insts)):
