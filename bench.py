@@ -195,6 +195,49 @@ def stability_map(L: int = 32, M: float = 50.0):
             "nu": nus, "max_stable_mach": table}
 
 
+def dsl_study():
+    """Double shear layer (Re = 3e4): PR at Ma 0.12 on L = 128, 256, 512 (time of the instability,
+    in t_c), and the largest stable Ma over 3 t_c of PR and RR on L = 128, 256."""
+    from paper_2002_05265_amd import inputs
+    from paper_2002_05265_amd import stability as S
+
+    inst = S.dsl_instances([("PR", "REG")], [128, 256, 512], [0.12], M=3)
+    fb, sec1, upd1 = S.run_stability(inst, field=S.dsl_field)
+    times = {d["nx"]: (round(float(f) / (d["nx"] / (0.12 * inputs.CS)), 3) if f >= 0 else None)
+             for d, f in zip(inst, fb)}
+    machs = [round(0.02 * k, 2) for k in range(2, 36)]
+    inst = S.dsl_instances([("PR", "REG"), ("RR", "SRT")], [128, 256], machs, M=3)
+    fb, sec2, upd2 = S.run_stability(inst, field=S.dsl_field)
+    pts = {}
+    for d, f in zip(inst, fb):
+        pts.setdefault(f"{d['model']}-L{d['nx']}", []).append((d["mach"], f))
+    best = {}
+    for key, v in pts.items():
+        best[key] = 0.0
+        for ma, f in sorted(v):
+            if f >= 0:
+                break
+            best[key] = ma
+    return {"workload": "double shear layer, Re 3e4, |u|^2 criterion, FP64",
+            "pr_ma012_unstable_at_tc": times, "max_stable_mach_3tc": best,
+            "seconds": round(sec1 + sec2, 3), "mlups": round((upd1 + upd2) / (sec1 + sec2) / 1e6, 1)}
+
+
+def transport_study():
+    """Convected vortex at Ma 0.5, nu 1e-4 over 50 t_c (SRT-RR, REG-CHM, REG-K; L = 256, 512):
+    vorticity error against the initial field."""
+    from paper_2002_05265_amd import accuracy as A
+
+    res, tim = A.transport_accuracy([("RR", "SRT"), ("CHM", "REG"), ("K", "REG")], [256, 512])
+    sec = sum(t for t, _ in tim.values())
+    upd = sum(u for _, u in tim.values())
+    return {"workload": "convected vortex Ma 0.5, nu 1e-4, 50 t_c, FP64",
+            "metrics": {f"{m}-{p}-L{L}": {"l2": round(v["l2"], 6), "peak": round(v["peak"], 6),
+                                            "shift": [round(x, 3) for x in v["shift"]]}
+                        for (m, p, L), v in res.items()},
+            "seconds": round(sec, 3), "mlups": round(upd / sec / 1e6, 1)}
+
+
 def precision_errors(n: int = 4096, steps: int = 5000, models=("CM", "K")):
     """Shifted FP32 and FP16 storage against FP64 on the double shear layer: relative L2 error
     of the velocity field after `steps` steps (same initial fields, rates and model)."""
@@ -507,6 +550,8 @@ def main():
         line["adjoint"] = adjoint_run()
         line["precision_error"] = precision_errors(n)
         line["stability_map"] = stability_map()
+        line["dsl_study"] = dsl_study()
+        line["transport_study"] = transport_study()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(models)
     print(json.dumps(line), flush=True)

@@ -44,14 +44,41 @@ def check_schedule(budgets, check_every: int = 64):
     return out
 
 
+def vortex_field(d, beta: float = 0.5, radius_frac: float = 0.05):
+    """Initial fields of a convected-vortex instance (Section 5a)."""
+    return inputs.vortex_fields(d["nx"], d["ny"], d["mach"], beta=beta, radius_frac=radius_frac)
+
+
+def dsl_field(d):
+    """Initial fields of a double-shear-layer instance (Appendix C)."""
+    return inputs.dsl_fields(d["nx"], d["ny"], d["mach"])
+
+
+def dsl_instances(models_presets, Ls, machs, M: float, reynolds: float = 3.0e4):
+    """Double shear layer runs (Appendix C) at Re = u0 L / nu, one per ((model, preset), L, Ma),
+    each with its budget of M convective times t_c = L / u0."""
+    out = []
+    for model, preset in models_presets:
+        for L in Ls:
+            for ma in machs:
+                nu = inputs.dsl_nu(L, ma, reynolds)
+                out.append({"nx": L, "ny": L, "model": model, "preset": preset, "nu": float(nu), "mach": float(ma),
+                            "eq_order": 4, "omega": inputs.rates(float(nu), preset),
+                            "budget": int(math.ceil(M * L / (ma * inputs.CS)))})
+    return out
+
+
 def run_stability(instances, prec: str = "f64", check_every: int = 64, beta: float = 0.5,
                   radius_frac: float = 0.05, device="cuda:0", autotune: bool = True,
-                  criterion: str = "u2"):
+                  criterion: str = "u2", field=None):
     """Classify every instance; returns (first_bad_step per instance (-1 = stable), seconds of GPU
     time, node updates performed).  criterion "u2" is the |u|^2 test above; "blowup" counts only
-    a loss of positivity within the budget."""
-    fields = [inputs.vortex_fields(d["nx"], d["ny"], d["mach"], beta=beta, radius_frac=radius_frac)
-              for d in instances]
+    a loss of positivity within the budget.  field(d) gives an instance's initial (rho, ux, uy);
+    the default is the convected vortex with beta and radius_frac."""
+    if field is None:
+        fields = [vortex_field(d, beta, radius_frac) for d in instances]
+    else:
+        fields = [field(d) for d in instances]
     dev = torch.device(device)
     b = Batch(instances, fields, prec=prec, device=dev)
     try:
