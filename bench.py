@@ -238,6 +238,24 @@ def transport_study():
             "seconds": round(sec, 3), "mlups": round(upd / sec / 1e6, 1)}
 
 
+def lsa_domain(n: int = 128):
+    """Linear stability domain (Section 4c): every model under SRT and REG, nu in 1e-6 .. 1e-1,
+    Ma in 0 .. 0.9, five flow directions in [0, pi/4], n x n wave numbers; largest stable Ma."""
+    import math
+
+    from paper_2002_05265_amd import inputs, lsa
+
+    mp = [(m, p) for m in inputs.MODEL_NAMES for p in ("SRT", "REG")]
+    nus = [1e-6, 1e-5, 1e-4, 1e-3, 1e-2, 1e-1]
+    machs = [round(0.025 * k, 3) for k in range(0, 37)]
+    phis = list(np.linspace(0.0, math.pi / 4, 5))
+    table, _, sec = lsa.stability_domain(mp, nus, machs, phis, n=n)
+    mats = len(mp) * len(nus) * len(machs) * len(phis) * n * n
+    return {"workload": f"9x9 complex eigenproblems, {len(mp) * len(nus) * len(machs) * len(phis)} flows x {n}^2 "
+                        "wave numbers, FP64", "seconds": round(sec, 3), "matrices_per_s": round(mats / sec, 1),
+            "nu": nus, "max_stable_mach": {f"{m}-{p}": [table[(m, p, nu)] for nu in nus] for m, p in mp}}
+
+
 def precision_errors(n: int = 4096, steps: int = 5000, models=("CM", "K")):
     """Shifted FP32 and FP16 storage against FP64 on the double shear layer: relative L2 error
     of the velocity field after `steps` steps (same initial fields, rates and model)."""
@@ -552,6 +570,7 @@ def main():
         line["stability_map"] = stability_map()
         line["dsl_study"] = dsl_study()
         line["transport_study"] = transport_study()
+        line["lsa_domain"] = lsa_domain()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(models)
     print(json.dumps(line), flush=True)

@@ -203,3 +203,39 @@ def adjoint_run(rho0, ux0, uy0, ux_t, uy_t, model: int, N: int, omega, nsteps: i
 def forward_loss(rho0, ux0, uy0, ux_t, uy_t, model: int, N: int, omega, nsteps: int) -> float:
     f = step(init_eq(N, rho0, ux0, uy0), model, N, omega, nsteps)
     return velocity_loss(f, ux_t, uy_t)[0]
+
+
+# ---------------------------------------------------------------------------------------------
+# Linear stability analysis (Section 4, Appendix A), built from the collision Jacobian above and
+# a library eigenvalue routine.
+
+def velocities():
+    """(cx, cy) of the nine lattice velocities in the oracle's order."""
+    cx, cy = (ctypes.c_int * 9)(), (ctypes.c_int * 9)()
+    lib().oracle_velocities(cx, cy)
+    return np.array(cx[:], dtype=np.float64), np.array(cy[:], dtype=np.float64)
+
+
+def lsa_jacobian(model: int, N: int, omega, ux: float, uy: float) -> np.ndarray:
+    """delta + J of eq. DiscretePerturbedEq: d f*_i / d f_j at the uniform flow f = f^eq_N(1, U)."""
+    return collide_jacobian(model, N, omega, feq_cell(N, 1.0, ux, uy))[0]
+
+
+def lsa_matrix(J: np.ndarray, kx: float, ky: float) -> np.ndarray:
+    """M^D(k) = E^D (delta + J), E^D = diag(exp(-i xi_i . k)) (Appendix A, eigenvalue problem)."""
+    cx, cy = velocities()
+    return np.exp(-1j * (cx * kx + cy * ky))[:, None] * J
+
+
+def lsa_eigenvalues(J: np.ndarray, kx: float, ky: float) -> np.ndarray:
+    """Eigenvalues exp(-i omega) of M^D(k); the growth rate of each wave is log |lambda|."""
+    return np.linalg.eigvals(lsa_matrix(J, kx, ky))
+
+
+def dvbe_matrix(N: int, tau: float, ux: float, uy: float, kx: float, ky: float) -> np.ndarray:
+    """M^C = E^C + i J^C of the BGK discrete-velocity Boltzmann equation (Appendix A), with
+    E^C = diag(xi_i . k) and J^C = -(I - F) / tau, F = d f^eq / d f at f^eq_N(1, U).  F is the
+    Jacobian of the BGK collision at omega = 1 (whose post-collision state is f^eq itself)."""
+    cx, cy = velocities()
+    F = lsa_jacobian(BGK, N, [1.0] * 5, ux, uy)
+    return np.diag(cx * kx + cy * ky) + 1j * (-(np.eye(9) - F) / tau)

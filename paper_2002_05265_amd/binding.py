@@ -32,6 +32,7 @@ EXPORTS = (
     "lbm_state_bytes", "lbm_adjoint_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_raw",
     "lbm_step_raw_many", "lbm_adjoint_many", "lbm_adjoint_flush",
     "lbm_adjoint_seed_velocity_l2", "lbm_adjoint_step", "lbm_eq_vjp",
+    "lbm_lsa_jacobian", "lbm_lsa_eigenvalues", "lbm_lsa_radius",
 )
 
 
@@ -40,6 +41,12 @@ class InstanceDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("model", ctypes.c_int),
                 ("eq_order", ctypes.c_int), ("omega", ctypes.c_double * 5), ("rho0", ctypes.c_double),
                 ("ux0", ctypes.c_double), ("uy0", ctypes.c_double)]
+
+
+class LsaPoint(ctypes.Structure):
+    """lbm_lsa_point (include/lbm_lsa.h)."""
+    _fields_ = [("model", ctypes.c_int), ("eq_order", ctypes.c_int), ("omega", ctypes.c_double * 5),
+                ("ux", ctypes.c_double), ("uy", ctypes.c_double)]
 
 
 class LbmError(RuntimeError):
@@ -77,6 +84,9 @@ def _declare(L: ctypes.CDLL):
         "lbm_batch_mean_u2": (_i, [_vp, _vp]),
         "lbm_batch_set_active": (_i, [_vp, _vp]),
         "lbm_batch_rebalance": (_i, [_vp]),
+        "lbm_lsa_jacobian": (_i, [_vp, _i, _vp, _vp]),
+        "lbm_lsa_eigenvalues": (_i, [_vp, _vp, _vp, _i, _vp, _vp]),
+        "lbm_lsa_radius": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp]),
         "lbm_batch_set_launch": (_i, [_vp, _i, _i]),
         "lbm_batch_autotune": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), _dp]),
         "lbm_batch_destroy": (None, [_vp]),
@@ -313,3 +323,26 @@ def lbm_eq_vjp(ctx: int, rho0: int, ux0: int, uy0: int, lam0: int, dux: int, duy
 
 def lbm_last_error() -> str:
     return lib().lbm_last_error().decode(errors="replace")
+
+
+def make_lsa_points(points) -> ctypes.Array:
+    """Array of LsaPoint from dicts with model (code), eq_order, omega, ux, uy."""
+    arr = (LsaPoint * len(points))()
+    for a, d in zip(arr, points):
+        a.model, a.eq_order = int(d["model"]), int(d["eq_order"])
+        for k in range(5):
+            a.omega[k] = float(d["omega"][k])
+        a.ux, a.uy = float(d["ux"]), float(d["uy"])
+    return arr
+
+
+def lbm_lsa_jacobian(points: ctypes.Array, J: int, stream=None):
+    _check(lib().lbm_lsa_jacobian(ctypes.cast(points, _vp), len(points), J, stream), "lbm_lsa_jacobian")
+
+
+def lbm_lsa_eigenvalues(points: ctypes.Array, kx: int, ky: int, nk: int, lam: int, stream=None):
+    _check(lib().lbm_lsa_eigenvalues(ctypes.cast(points, _vp), kx, ky, nk, lam, stream), "lbm_lsa_eigenvalues")
+
+
+def lbm_lsa_radius(points: ctypes.Array, kx: int, ky: int, nk: int, radius: int, stream=None):
+    _check(lib().lbm_lsa_radius(ctypes.cast(points, _vp), len(points), kx, ky, nk, radius, stream), "lbm_lsa_radius")
