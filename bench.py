@@ -437,7 +437,27 @@ def profile_summary(out_root: str, prec: str, n: int, commands: dict):
     print(json.dumps(blob), flush=True)
 
 
+def extras_trace_summary(out_root: str, command: str):
+    """Kernel-trace summary of a bench run with the extra workloads (every kernel of the batched,
+    adjoint, stability and linear-analysis paths), written to profiles/."""
+    d = os.path.join(out_root, "rp_trace_all")
+    if not os.path.isdir(d):
+        return
+    stats = _csv_rows(_find_csv(d, "kernel_stats.csv"))
+    lines = ["# All kernels of a bench run with the extra workloads: kernel trace", "",
+             "Command (from the repository root):", "", "```", command, "```", "",
+             "| kernel | calls | total ms | average us | share % |", "|---|---|---|---|---|"]
+    for r in stats[:40]:
+        name = r["Name"].replace("(anonymous namespace)::", "").replace("void ", "", 1).split("(")[0][:80]
+        lines.append(f"| {name} | {r['Calls']} | {float(r['TotalDurationNs']) * 1e-6:.2f} | "
+                     f"{float(r['AverageNs']) * 1e-3:.2f} | {float(r['Percentage']):.2f} |")
+    with open(os.path.join(PROFILE_DIR, "bench_extras_all_kernels_trace.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 PROFILE_ARGS = "--steps 20 --warmup 2 --no-cpu --no-extras"
+EXTRAS_PROFILE_COMMAND = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/rp_trace_all -o bench -- "
+                          "python bench.py --steps 20 --warmup 2 --no-cpu --batch-steps 2000")
 PROFILE_COMMANDS = {
     "trace": f"rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/rp_trace -o bench -- "
              f"python bench.py {PROFILE_ARGS}",
@@ -472,6 +492,7 @@ def main():
     args = ap.parse_args()
     if args.profile_summary:
         profile_summary(args.profile_summary, args.prec, args.n, PROFILE_COMMANDS)
+        extras_trace_summary(args.profile_summary, EXTRAS_PROFILE_COMMAND)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
