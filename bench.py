@@ -446,6 +446,8 @@ def extras_trace_summary(out_root: str, command: str):
     stats = _csv_rows(_find_csv(d, "kernel_stats.csv"))
     lines = ["# All kernels of a bench run with the extra workloads: kernel trace", "",
              "Command (from the repository root):", "", "```", command, "```", "",
+             "The batched kernel is launched cooperatively; the profiler may crash on its own exit after",
+             "the program has finished, with its result files complete.", "",
              "| kernel | calls | total ms | average us | share % |", "|---|---|---|---|---|"]
     for r in stats[:40]:
         name = r["Name"].replace("(anonymous namespace)::", "").replace("void ", "", 1).split("(")[0][:80]
