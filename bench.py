@@ -547,6 +547,14 @@ def main():
         per_model[m] = {"mlups": round(mlups, 1), "us_per_step": round(ms * 1e3 / args.steps, 2),
                         "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
     status = {m: s.status() for m, s in sims.items()}
+    # the same grid, layout and launch with the collision left out: the rate of this access pattern
+    ref_sim = next(iter(sims.values()))
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    ref_sim.step("STREAM_ONLY", omega, args.steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    stream_us = ev0.elapsed_time(ev1) * 1e3 / args.steps
     value = cells * args.steps * len(models) / wall / 1e6
     dominant = max(models, key=lambda m: per_model[m]["us_per_step"])
     dom_us = per_model[dominant]["us_per_step"]
@@ -574,7 +582,9 @@ def main():
                      "traffic": traffic, "traffic_unit": "bytes per launch",
                      "algorithmic_bytes": cells * bytes_per_cell(args.prec),
                      "measured_frac": (None if traffic is None else
-                                       round(traffic / (dom_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4))},
+                                       round(traffic / (dom_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)),
+                     "stream_only_gbs": round(cells * bytes_per_cell(args.prec) / (stream_us * 1e-6) / 1e9, 1),
+                     "frac_of_stream_only": round(stream_us / dom_us, 4)},
         "per_model": per_model,
         "blowup": {m: st[1] for m, st in status.items()},
     }

@@ -186,3 +186,28 @@ def trajectory_sensitivity(fields, d, steps, f_ref):
     sign = np.random.default_rng(0).choice([-1.0, 1.0], size=f0.shape)
     g = oracle.step(f0 * (1.0 + sign * 2.0 ** -52), inputs.MODEL_CODES[d["model"]], 4, d["omega"], steps)
     return float(np.max(np.abs(g - f_ref)) / np.max(np.abs(f_ref)))
+
+
+def test_full_sweep_bit_identical_to_plain(gpu):
+    """The bench's 512-instance random sweep (sides 64..512, every model, SRT and REG alternating),
+    autotuned and re-dealt over the XCDs, against each instance's plain run, after 120 steps."""
+    import torch
+
+    insts = inputs.sweep_instances(512)
+    for k, d in enumerate(insts):
+        d["omega"] = inputs.rates(d["nu"], "SRT" if k % 2 == 0 else "REG")
+        d["eq_order"] = 4
+    fields = [inputs.sweep_fields(d) for d in insts]
+    b = Batch(insts, fields, prec="f64", device=gpu)
+    b.autotune(2)
+    steps = 120
+    b.run(steps, rebalance_every=40)
+    _, blow = b.status()
+    for k, d in enumerate(insts):
+        s = Sim(*fields[k], prec="f64", eq_order=4, device=gpu)
+        s.step(d["model"], d["omega"], steps)
+        st = s.status()[1]
+        same = torch.equal(b.state(k), s.state()) if blow[k] < 0 else True
+        s.close()
+        assert blow[k] == st and same, (k, d["model"], d["nx"], blow[k], st)
+    b.close()

@@ -162,6 +162,31 @@ def test_state_roundtrip_and_resume(gpu):
         sim.close()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_degenerate_grids_and_rates(gpu, prec):
+    # the smallest grids (every neighbour wraps onto the node itself or its single partner), very
+    # thin ones, rates at the ends of [0, 2], and zero-step calls
+    rng = np.random.default_rng(5)
+    bar = 1e-12 if prec == "f64" else 1e-5
+    for nx, ny in [(2, 2), (2, 17), (19, 2), (3, 3), (257, 2)]:
+        rho = 1.0 + 0.01 * rng.standard_normal((ny, nx))
+        ux = 0.05 * rng.standard_normal((ny, nx))
+        uy = 0.05 * rng.standard_normal((ny, nx))
+        for name in MODELS:
+            N = 4
+            f0 = oracle.init_eq(N, rho, ux, uy)
+            for omega in ([0.0] * 5, [2.0] * 5, [1.0, 0.0, 2.0, 0.5, 1.5]):
+                sim = Sim(rho, ux, uy, prec=prec, eq_order=N, device=gpu)
+                sim.step(name, omega, 0)
+                np.testing.assert_allclose(sim.state().cpu().numpy(), f0, rtol=0, atol=1e-15 if prec == "f64" else 1e-7)
+                sim.step(name, omega, 7)
+                g = sim.state().cpu().numpy()
+                sim.close()
+                ref = oracle.step(f0, inputs.MODEL_CODES[name], N, omega, 7)
+                e = rel(g, ref)
+                assert e < bar, (nx, ny, name, omega, prec, e)
+
+
 def test_blowup_flag(gpu):
     n = 40
     rho, ux, uy = inputs.vortex_fields(n, n, 0.1)
