@@ -349,6 +349,45 @@ def adjoint_run(n: int = 512, steps: int = 2000, prec: str = "f32"):
             "cache_resident": True, **stats}
 
 
+def adjoint_step_rate(n: int, models, rho, ux, uy, omega, prec: str = "f32", steps: int = 20):
+    """Throughput of the reverse step alone at the bench grid: one node of lambda_n = J_C^T S^T
+    lambda_{n+1} reads 9 stored populations and gathers 9 adjoint values and writes 9 (27 values,
+    9 s + 18 a bytes), against the same HBM peak as the forward step."""
+    import torch
+
+    from paper_2002_05265_amd import binding as B
+    from paper_2002_05265_amd import inputs
+    from paper_2002_05265_amd.sim import Sim
+
+    sb, ab = (8, 8) if prec == "f64" else (4, 4)
+    dev = torch.device("cuda:0")
+    sim = Sim(rho, ux, uy, prec=prec, eq_order=4, device=dev)
+    sim.step("CM", omega, 3)
+    st = torch.empty(B.lbm_state_bytes(sim.ctx), dtype=torch.uint8, device=dev)
+    B.lbm_save_state(sim.ctx, st.data_ptr())
+    lam = [torch.zeros(B.lbm_adjoint_bytes(sim.ctx), dtype=torch.uint8, device=dev) for _ in range(2)]
+    states = [st.data_ptr()] * steps
+    ptrs = [lam[k % 2].data_ptr() for k in range(steps + 1)]
+    dw = torch.zeros(5, dtype=torch.float64, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {}
+    for m in models:
+        code = inputs.MODEL_CODES[m]
+        B.lbm_adjoint_many(sim.ctx, code, omega, states[:2], ptrs[:3], dw.data_ptr())
+        torch.cuda.synchronize()
+        e0.record()
+        B.lbm_adjoint_many(sim.ctx, code, omega, states, ptrs, dw.data_ptr())
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / steps
+        gbs = n * n * (9 * sb + 18 * ab) / us / 1e3
+        out[m] = {"us_per_step": round(us, 1), "mlups": round(n * n / us, 1), "gbs": round(gbs, 1),
+                  "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    sim.close()
+    return {"workload": f"reverse step alone, {n}x{n} double shear layer state, {prec}, {steps} steps",
+            "bytes_per_node": 9 * sb + 18 * ab, "models": out}
+
+
 def _csv_rows(path):
     import csv
 
@@ -599,6 +638,7 @@ def main():
         f64_mlups = min(v["mlups"] for v in line["precisions"]["f64"].values())
         line["batched"] = batched_sweep(args.batch_steps, f64_mlups)
         line["adjoint"] = adjoint_run()
+        line["adjoint"]["reverse_step"] = adjoint_step_rate(n, models, rho, ux, uy, omega)
         line["precision_error"] = precision_errors(n)
         line["stability_map"] = stability_map()
         line["dsl_study"] = dsl_study()

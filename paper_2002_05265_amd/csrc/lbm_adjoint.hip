@@ -20,6 +20,19 @@ using namespace lbm;
 
 namespace {
 
+// Every reverse step of a context uses this one launch shape, so the launches that feed one set
+// of rate-gradient slots (block b writes slot b) have the same blocks.  Two nodes per thread
+// halve the per-block gradient reductions; at 4096^2 that is 4-7% faster with 4-byte adjoint
+// values and 2% slower with 8-byte ones (one node per thread there).
+StepShape adjoint_shape(const lbm_ctx* ctx) {
+    return step_shape(ctx->nx, ctx->ny, ctx->prec == LBM_F64 ? 1 : 2, LBM_DEFAULT_XCD);
+}
+
+unsigned adjoint_blocks(const lbm_ctx* ctx) {
+    const StepShape sh = adjoint_shape(ctx);
+    return sh.gx * sh.gy;
+}
+
 template <int PREC> struct AdjT;
 template <> struct AdjT<kF64> { using T = double; };
 template <> struct AdjT<kF32> { using T = float; };
@@ -51,7 +64,7 @@ __device__ __forceinline__ void block_accumulate(double (&v)[5], double* __restr
     block_sum<5>(v, tot);
     __syncthreads();
     if (threadIdx.x == 0 && threadIdx.y == 0) {
-        double* p = slots + 5 * (size_t)(blockIdx.y * gridDim.x + blockIdx.x);
+        double* p = slots + 5 * (size_t)blockIdx.x;
         for (int k = 0; k < 5; ++k) p[k] = (accumulate ? p[k] : 0.0) + tot[k];
     }
 }
@@ -69,31 +82,45 @@ __global__ __launch_bounds__(256) void k_finalize_add(const double* __restrict__
         for (int k = 0; k < 5; ++k) out[k] += tot[k];
 }
 
-template <int MODEL, int PREC>
+template <int MODEL, int PREC, int ROWS>
 __global__ __launch_bounds__(256) void k_adjoint_step(const typename Store<PREC>::S* __restrict__ state,
                                                       const typename AdjT<PREC>::T* __restrict__ lam_next,
                                                       typename AdjT<PREC>::T* __restrict__ lam, Geom g,
                                                       Coef<typename Store<PREC>::R> c,
                                                       Ref<typename Store<PREC>::R> ref, int N,
-                                                      double* __restrict__ slots, int accumulate) {
+                                                      double* __restrict__ slots, int accumulate,
+                                                      unsigned gx, unsigned nb, int xcd) {
     using R = typename Store<PREC>::R;
     using T = typename AdjT<PREC>::T;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    unsigned bx, by;
+    tile_of_block(blockIdx.x, gx, nb, xcd, bx, by);
+    const int x = bx * blockDim.x + threadIdx.x;
+    const int y0 = by * blockDim.y * ROWS + threadIdx.y;
     double wb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (x < g.nx && y < g.ny) {
-        const Nbr nb = neighbours(x, y, g.nx, g.ny);
-        R h[9], mu[9], hb[9];
-        pull_load(state, g.plane, nb, h);
-        push_gather(lam_next, g.plane, nb, mu);
-        double rho_d;
-        const Macro<R> m = macro_of<typename Store<PREC>::S>(h, ref, rho_d);
-        R cb[7] = {R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
-        collide_adjoint<MODEL>(h, m, ref, c, N, mu, hb, cb);
-        const unsigned o = nb.r0 + (unsigned)x;
+    if (x < g.nx) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) *plane_at(lam, g.plane, i, o * (unsigned)sizeof(T)) = T(hb[i]);
-        omega_adjoint(cb, wb);
+        for (int r = 0; r < ROWS; ++r) {
+            const int y = y0 + r * (int)blockDim.y;
+            if (y < g.ny) {
+                const Nbr n = neighbours(x, y, g.nx, g.ny);
+                R h[9], mu[9], hb[9];
+                pull_load(state, g.plane, n, h);
+                push_gather(lam_next, g.plane, n, mu);
+                double rho_d;
+                const Macro<R> m = macro_of<typename Store<PREC>::S>(h, ref, rho_d);
+                R cb[7] = {R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
+                collide_adjoint<MODEL>(h, m, ref, c, N, mu, hb, cb);
+                const unsigned o = (n.r0 + (unsigned)x) * (unsigned)sizeof(T);
+                // lambda_n is read back only by the next reverse step, as a gather over the
+                // whole grid: streaming stores keep it from displacing reusable lines
+#pragma unroll
+                for (int i = 0; i < 9; ++i) st<T>(plane_at(lam, g.plane, i, o), T(hb[i]));
+                double wn[5];
+                omega_adjoint(cb, wn);
+#pragma unroll
+                for (int k = 0; k < 5; ++k) wb[k] += wn[k];
+            }
+        }
     }
     block_accumulate(wb, slots, accumulate);
 }
@@ -176,17 +203,27 @@ __global__ __launch_bounds__(256) void k_eq_vjp(Geom g, Ref<double> ref, int N, 
     duy[c] = mb.uy + mb.duy + m.rho * mb.jy;
 }
 
-template <int MODEL, int PREC>
-void launch_adj_t(lbm_ctx* ctx, const double* w, const void* state, const void* lam_next, void* lam,
-                  int accumulate) {
+template <int MODEL, int PREC, int ROWS>
+void launch_adj_r(lbm_ctx* ctx, const StepShape& sh, const double* w, const void* state, const void* lam_next,
+                  void* lam, int accumulate) {
     using S = typename Store<PREC>::S;
     using R = typename Store<PREC>::R;
     using T = typename AdjT<PREC>::T;
-    const Launch l = launch_for(ctx->nx, ctx->ny);
-    hipLaunchKernelGGL((k_adjoint_step<MODEL, PREC>), l.grid, l.block, 0, ctx->stream,
+    const unsigned nb = sh.gx * sh.gy;
+    hipLaunchKernelGGL((k_adjoint_step<MODEL, PREC, ROWS>), dim3(nb), dim3(sh.bw, sh.bh), 0, ctx->stream,
                        reinterpret_cast<const S*>(state), reinterpret_cast<const T*>(lam_next),
                        reinterpret_cast<T*>(lam), ctx->geom(), make_coef<R>(w), ref_as<R>(ctx->ref),
-                       ctx->eq_order, ctx->d_wslots, accumulate);
+                       ctx->eq_order, ctx->d_wslots, accumulate, sh.gx, nb, sh.xcd);
+}
+
+template <int MODEL, int PREC>
+void launch_adj_t(lbm_ctx* ctx, const double* w, const void* state, const void* lam_next, void* lam,
+                  int accumulate) {
+    const StepShape sh = adjoint_shape(ctx);
+    if (sh.rows == 2)
+        launch_adj_r<MODEL, PREC, 2>(ctx, sh, w, state, lam_next, lam, accumulate);
+    else
+        launch_adj_r<MODEL, PREC, 1>(ctx, sh, w, state, lam_next, lam, accumulate);
 }
 
 template <int PREC>
@@ -307,7 +344,7 @@ int lbm_adjoint_many(lbm_ctx* ctx, int model, const double* omega, const void* c
     if (rc == LBM_OK) rc = validate_omega(omega);
     if (rc != LBM_OK) return rc;
     if (!ctx->d_wslots) {
-        rc = check_hip(hipMalloc(&ctx->d_wslots, sizeof(double) * 5 * (size_t)ctx->nblocks), "hipMalloc(slots)");
+        rc = check_hip(hipMalloc(&ctx->d_wslots, sizeof(double) * 5 * (size_t)adjoint_blocks(ctx)), "hipMalloc(slots)");
         if (rc != LBM_OK) return rc;
     }
     for (int k = 0; k < count; ++k) {
@@ -328,7 +365,8 @@ int lbm_adjoint_flush(lbm_ctx* ctx, double* domega) {
     if (!ctx) return set_error(LBM_ESTATE, "context is NULL");
     if (!domega) return set_error(LBM_EINVAL, "domega is NULL");
     if (!ctx->wslots_live) return LBM_OK;
-    hipLaunchKernelGGL(k_finalize_add, dim3(1), dim3(256), 0, ctx->stream, ctx->d_wslots, ctx->nblocks, domega);
+    hipLaunchKernelGGL(k_finalize_add, dim3(1), dim3(256), 0, ctx->stream, ctx->d_wslots,
+                       (int)adjoint_blocks(ctx), domega);
     ctx->wslots_live = false;
     return check_hip(hipGetLastError(), "adjoint reduction launch");
 }
