@@ -43,15 +43,16 @@ def step_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def step_kernel_key(model: str, prec: str) -> str:
-    """Template arguments of the plain step kernel as they appear in a kernel trace."""
-    return f"k_step<{MODEL_ORDER.index(model)}, {PREC_CODE[prec]}, "
+def step_kernel_keys(model: str, prec: str):
+    """(label, name prefix in a kernel trace) of the two-step and the single-step kernel."""
+    args = f"{MODEL_ORDER.index(model)}, {PREC_CODE[prec]}, "
+    return [("k_step2", f"k_step2<{args}"), ("k_step", f"k_step<{args}")]
 
 
 def measured_traffic(model: str, prec: str):
     """HBM bytes per launch of the step kernel from the committed counter summary, or None when
     there is none for this kernel or its sources changed since it was taken."""
-    path = os.path.join(PROFILE_DIR, f"k_step_{prec}_dsl4096_counters.md")
+    path = os.path.join(PROFILE_DIR, f"k_step2_{prec}_dsl4096_counters.md")
     try:
         with open(path) as fh:
             text = fh.read()
@@ -91,6 +92,28 @@ def cpu_baseline(models, budget_s: float = 16.0):
                       f"{elapsed:.1f} s total"}
 
 
+def single_step_rates(sims, models, omega, cells, bpc, steps):
+    """The same grids with one step per launch (two-step launches switched off), for comparison;
+    each sim's own setting is restored afterwards."""
+    import torch
+
+    out = {}
+    for m in models:
+        s = sims[m]
+        ring, strip = s.fusion(m)
+        s.set_fusion(m, 0)
+        s.step(m, omega, 2)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.step(m, omega, steps)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / steps
+        s.set_fusion(m, ring, strip)
+        out[m] = {"mlups": round(cells / us, 1), "hbm_gbs": round(cells * bpc / us / 1e3, 1)}
+    return out
+
+
 def time_models(prec: str, n: int, models, steps: int, warmup: int, omega, fields):
     """Per-model timing of `steps` launches on an n x n grid (HIP events on the launch stream)."""
     import torch
@@ -108,10 +131,11 @@ def time_models(prec: str, n: int, models, steps: int, warmup: int, omega, field
         e1.record()
         torch.cuda.synchronize()
         us = e0.elapsed_time(e1) * 1e3 / steps
+        spl = 2 if s.fusion(m)[0] else 1
         mlups = n * n / us
-        gbs = mlups * 1e6 * bytes_per_cell(prec) / 1e9
-        out[m] = {"mlups": round(mlups, 1), "us_per_step": round(us, 2), "hbm_gbs": round(gbs, 1),
-                  "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "blowup": s.status()[1]}
+        gbs = mlups * 1e6 * bytes_per_cell(prec) / spl / 1e9
+        out[m] = {"mlups": round(mlups, 1), "us_per_step": round(us, 2), "steps_per_launch": spl,
+                  "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "blowup": s.status()[1]}
         s.close()
         del s
         torch.cuda.empty_cache()
@@ -417,10 +441,11 @@ def profile_summary(out_root: str, prec: str, n: int, commands: dict):
     stats = _csv_rows(_find_csv(os.path.join(out_root, "rp_trace"), "kernel_stats.csv"))
     cells = n * n
     alg = cells * bytes_per_cell(prec)
-    lines = [f"# k_step ({prec}, {n}x{n} double shear layer): kernel trace", "",
+    lines = [f"# k_step2 / k_step ({prec}, {n}x{n} double shear layer): kernel trace", "",
              "Command (from the repository root, with `cd /tmp && export TMPDIR=/tmp` semantics for",
              "the profiler's scratch files):", "", "```", commands["trace"], "```", "",
-             f"Algorithmic bytes per launch: {n}*{n} nodes * 18 * {bytes_per_cell(prec) // 18} B = {alg} B.",
+             f"Algorithmic bytes per launch: {n}*{n} nodes * 18 * {bytes_per_cell(prec) // 18} B = {alg} B "
+             "(every population read and written once; k_step2 advances two steps per launch, k_step one).",
              "", "| kernel | calls | average us | min us | max us | GB/s at algorithmic bytes |",
              "|---|---|---|---|---|---|"]
     for r in stats:
@@ -429,12 +454,13 @@ def profile_summary(out_root: str, prec: str, n: int, commands: dict):
         avg = float(r["AverageNs"]) * 1e-3
         gbs = ""
         for m in MODEL_ORDER:
-            if step_kernel_key(m, prec) in name:
-                gbs = f"{alg / (avg * 1e-6) / 1e9:.1f}"
-                short = f"k_step<{m}, {prec}>"
+            for label, key in step_kernel_keys(m, prec):
+                if key in name:
+                    gbs = f"{alg / (avg * 1e-6) / 1e9:.1f}"
+                    short = f"{label}<{m}, {prec}>"
         lines.append(f"| {short} | {r['Calls']} | {avg:.2f} | {float(r['MinNs']) * 1e-3:.2f} | "
                      f"{float(r['MaxNs']) * 1e-3:.2f} | {gbs} |")
-    with open(os.path.join(PROFILE_DIR, f"k_step_{prec}_dsl4096_trace.md"), "w") as fh:
+    with open(os.path.join(PROFILE_DIR, f"k_step2_{prec}_dsl4096_trace.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
     fetch = _csv_rows(_find_csv(os.path.join(out_root, "rp_fetch"), "counter_collection.csv"))
@@ -450,19 +476,20 @@ def profile_summary(out_root: str, prec: str, n: int, commands: dict):
     rows = ["| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) | / algorithmic |",
             "|---|---|---|---|---|---|"]
     for m in MODEL_ORDER:
-        key = step_kernel_key(m, prec)
-        f_kib, nf = _per_dispatch(fetch, key)
-        w_kib, _ = _per_dispatch(write, key)
-        if f_kib is None or w_kib is None:
-            continue
-        hbm = f_kib * 1024 * fscale + w_kib * 1024 * wscale
-        per_launch[m] = {"fetch_kib": round(f_kib, 1), "write_kib": round(w_kib, 1),
-                         "hbm_bytes": int(round(hbm)), "vs_algorithmic": round(hbm / alg, 4)}
-        rows.append(f"| k_step<{m}, {prec}> | {nf} | {f_kib:.1f} | {w_kib:.1f} | {hbm:.4g} | {hbm / alg:.4f} |")
+        # the first kernel of the model found (two-step before single-step) is the one reported
+        for label, key in step_kernel_keys(m, prec):
+            f_kib, nf = _per_dispatch(fetch, key)
+            w_kib, _ = _per_dispatch(write, key)
+            if f_kib is None or w_kib is None:
+                continue
+            hbm = f_kib * 1024 * fscale + w_kib * 1024 * wscale
+            rows.append(f"| {label}<{m}, {prec}> | {nf} | {f_kib:.1f} | {w_kib:.1f} | {hbm:.4g} | {hbm / alg:.4f} |")
+            per_launch.setdefault(m, {"kernel": label, "fetch_kib": round(f_kib, 1), "write_kib": round(w_kib, 1),
+                                      "hbm_bytes": int(round(hbm)), "vs_algorithmic": round(hbm / alg, 4)})
     blob = {"step_source_hash": step_source_hash(), "prec": prec, "n": n, "algorithmic_bytes": alg,
             "copy_probe_kib": {"fetch": round(cf, 1), "write": round(cw, 1), "true": gib_kib},
             "scale": {"fetch": round(fscale, 4), "write": round(wscale, 4)}, "per_launch": per_launch}
-    text = [f"# k_step ({prec}, {n}x{n} double shear layer): HBM counters", "",
+    text = [f"# k_step2 / k_step ({prec}, {n}x{n} double shear layer): HBM counters", "",
             "Commands (each counter in a run of its own):", "", "```", commands["fetch"], commands["write"],
             commands["copy_fetch"], commands["copy_write"], "```", "",
             "Calibration: a plain device copy of 1 GiB (torch, same box) reads "
@@ -471,7 +498,7 @@ def profile_summary(out_root: str, prec: str, n: int, commands: dict):
             f"WRITE_SIZE by {wscale:.4f}.", "", *rows, "",
             "Machine-readable (bench.py reports `roofline.traffic` from this block while the step "
             "kernel's sources hash to `step_source_hash`):", "", "```json", json.dumps(blob, indent=1), "```", ""]
-    with open(os.path.join(PROFILE_DIR, f"k_step_{prec}_dsl4096_counters.md"), "w") as fh:
+    with open(os.path.join(PROFILE_DIR, f"k_step2_{prec}_dsl4096_counters.md"), "w") as fh:
         fh.write("\n".join(text))
     print(json.dumps(blob), flush=True)
 
@@ -496,7 +523,7 @@ def extras_trace_summary(out_root: str, command: str):
         fh.write("\n".join(lines) + "\n")
 
 
-PROFILE_ARGS = "--steps 20 --warmup 2 --no-cpu --no-extras"
+PROFILE_ARGS = "--steps 40 --warmup 4 --no-cpu --no-extras"
 EXTRAS_PROFILE_COMMAND = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/rp_trace_all -o bench -- "
                           "python bench.py --steps 20 --warmup 2 --no-cpu --batch-steps 2000")
 PROFILE_COMMANDS = {
@@ -578,27 +605,34 @@ def main():
     wall = time.perf_counter() - t0
 
     cells = n * n
+    bpc = bytes_per_cell(args.prec)
     per_model = {}
     for m in models:
         ms = ev[m][0].elapsed_time(ev[m][1])
+        ring, strip = sims[m].fusion(m)
+        spl = 2 if ring else 1
         mlups = cells * args.steps / (ms * 1e-3) / 1e6
-        gbs = mlups * 1e6 * bytes_per_cell(args.prec) / 1e9
+        gbs = mlups * 1e6 * bpc / spl / 1e9
         per_model[m] = {"mlups": round(mlups, 1), "us_per_step": round(ms * 1e3 / args.steps, 2),
+                        "steps_per_launch": spl, "ring_rows": ring, "strip_rows": strip,
                         "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
     status = {m: s.status() for m, s in sims.items()}
-    # the same grid, layout and launch with the collision left out: the rate of this access pattern
+    # the same grid, layout and launches with the collision left out: the rate of this access pattern
     ref_sim = next(iter(sims.values()))
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
     ref_sim.step("STREAM_ONLY", omega, args.steps)
     ev1.record()
     torch.cuda.synchronize()
-    stream_us = ev0.elapsed_time(ev1) * 1e3 / args.steps
+    stream_launch_us = ev0.elapsed_time(ev1) * 1e3 / args.steps * (2 if ref_sim.fusion("STREAM_ONLY")[0] else 1)
+    single = single_step_rates(sims, models, omega, cells, bpc, max(10, args.steps // 10))
     value = cells * args.steps * len(models) / wall / 1e6
     dominant = max(models, key=lambda m: per_model[m]["us_per_step"])
-    dom_us = per_model[dominant]["us_per_step"]
-    achieved = cells * bytes_per_cell(args.prec) / (dom_us * 1e-6) / 1e9
+    spl = per_model[dominant]["steps_per_launch"]
+    launch_us = per_model[dominant]["us_per_step"] * spl
+    achieved = cells * bpc / (launch_us * 1e-6) / 1e9
     traffic = measured_traffic(dominant, args.prec) if n == 4096 else None
+    kname = "k_step2" if spl == 2 else "k_step"
     line = {
         "metric": "MLUPS per collision model at 4096^2 FP32 + % HBM roofline; adjoint/batched vs plain",
         "value": round(value, 1),
@@ -616,14 +650,19 @@ def main():
                                f"{'shifted ' if args.prec != 'f64' else ''}{args.prec} populations, "
                                f"REG rates, 8 collision models (one grid each)",
                    "nx": n, "ny": n, "models": models, "omega": [round(w, 6) for w in omega]},
-        "roofline": {"bound": "hbm", "kernel": f"k_step<{dominant}>", "achieved": round(achieved, 1),
+        # one launch of the dominant kernel reads and writes every population once; with two
+        # steps per launch it advances the grid two steps for those bytes
+        "roofline": {"bound": "hbm", "kernel": f"{kname}<{dominant}>", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "traffic_unit": "bytes per launch",
-                     "algorithmic_bytes": cells * bytes_per_cell(args.prec),
+                     "algorithmic_bytes": cells * bpc, "launch_us": round(launch_us, 2),
+                     "steps_per_launch": spl,
+                     "single_step_equivalent_gbs": round(achieved * spl, 1),
                      "measured_frac": (None if traffic is None else
-                                       round(traffic / (dom_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)),
-                     "stream_only_gbs": round(cells * bytes_per_cell(args.prec) / (stream_us * 1e-6) / 1e9, 1),
-                     "frac_of_stream_only": round(stream_us / dom_us, 4)},
+                                       round(traffic / (launch_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)),
+                     "stream_only_gbs": round(cells * bpc / (stream_launch_us * 1e-6) / 1e9, 1),
+                     "frac_of_stream_only": round(stream_launch_us / launch_us, 4)},
+        "single_step": single,
         "per_model": per_model,
         "blowup": {m: st[1] for m, st in status.items()},
     }

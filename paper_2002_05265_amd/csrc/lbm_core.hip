@@ -137,6 +137,133 @@ __global__ __launch_bounds__(256) void k_step(const typename Store<PREC>::S* __r
     }
 }
 
+// Two steps per pass over memory (temporal blocking).  A block owns a strip of columns and `hs`
+// rows and walks down it RING rows at a time: the first step's post-collision values of the
+// strip plus one halo column on each side are kept in a ring of RING + 2 rows in LDS, and the
+// second step pulls from that ring and writes to memory.  Per two steps each population is read
+// from and written to memory once, against twice for two single steps; the halo columns and the
+// two rows above and below the strip are collided twice (by both strips that need them).  Every
+// node is computed by the same arithmetic as in k_step and the ring holds the values in the
+// storage type, so the result is bit-identical to two launches of k_step.
+//
+// A strip is 64 columns wide, so every output row segment is whole 256-byte lines; lane l takes
+// column x0 + l, and one wave collides the two halo columns of the pass's rows in an extra pass.
+// (A 62-column strip with the halo columns in lanes 0 and 63 saves that pass, but its stores
+// start mid-line and two strips write parts of the same lines: measured 0.6x as fast.)
+constexpr int kStripW = 64;
+
+// Strip height a new context starts with (ring of 8 rows), 0 for single steps.  Measured on
+// MI355X (CM, double shear layer): two steps per launch win in FP32 and FP64 from 512^2 up
+// (strips of 16 rows: 256 blocks at 512^2), and in FP16, whose step is bound by arithmetic
+// rather than bytes, only once strips of 64 rows still give 1024 blocks (2048^2 and up); FP64
+// takes strips of 64 rows when they give 1024 blocks.
+int default_fusion_strip(int nx, int ny, int prec) {
+    const long long sx = (nx + kStripW - 1) / kStripW;
+    const long long s16 = sx * ((ny + 15) / 16), s64 = sx * ((ny + 63) / 64);
+    if (prec == LBM_F16_SHIFTED) return s64 >= 1024 ? 64 : 0;
+    if (prec == LBM_F64 && s64 >= 1024) return 64;
+    return s16 >= 256 ? 16 : 0;
+}
+
+template <int MODEL, int PREC, int RING>
+__global__ __launch_bounds__(256) void k_step2(const typename Store<PREC>::S* __restrict__ src,
+                                               typename Store<PREC>::S* __restrict__ dst, Geom g,
+                                               Coef<typename Store<PREC>::R> c,
+                                               Ref<typename Store<PREC>::R> ref, int N, int step,
+                                               int* __restrict__ blowup, unsigned gsx, int hs) {
+    using S = typename Store<PREC>::S;
+    using R = typename Store<PREC>::R;
+    constexpr int NR = RING + 2;
+    constexpr int W = kStripW;
+    __shared__ S ring[9][NR][W + 2];
+    const int lane = (int)(threadIdx.x & 63u);
+    const int wave = (int)(threadIdx.x >> 6);
+    // strips in hardware order (an XCD-banded order measured no faster: the strips' edge lines
+    // are not what limits this kernel)
+    const unsigned sy = blockIdx.x / gsx;
+    const int x0 = (int)(blockIdx.x - sy * gsx) * W;
+    const int ys = (int)sy * hs;
+    const int ye = min(ys + hs, g.ny);
+    const int w = min(W, g.nx - x0);           // output columns of this strip
+    const int lc = lane + 1;   // this lane's ring column
+    const bool in1 = lane < w;   // the lane has a column of the strip
+
+    // first step at row a (ys - 1 <= a <= ye, unwrapped) and ring column col (column
+    // x0 - 1 + col, wrapped): the pull loads, then the collision into the ring
+    auto load = [&](int a, int col, R (&h)[9]) {
+        const int x = x0 - 1 + col;
+        const int yw = a < 0 ? a + g.ny : (a >= g.ny ? a - g.ny : a);
+        const int xw = x < 0 ? x + g.nx : (x >= g.nx ? x - g.nx : x);
+        pull_load(src, g.plane, neighbours(xw, yw, g.nx, g.ny), h);
+    };
+    auto finish = [&](int a, int col, R (&h)[9]) {
+        double rho_d;
+        const Macro<R> m = macro_of<S>(h, ref, rho_d);
+        flag_bad(!(rho_d > 0.0), blowup, step);
+        collide<MODEL>(h, m, ref, c, N);
+        const int slot = (a - ys + 1) % NR;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) ring[i][slot][col] = to_store<S>(h[i]);
+    };
+    // Rows of a pass starting at yb: wave v takes rows yb + 1 + v + 4 k, and wave 3 also the halo
+    // columns of rows yb + 1 .. (two lanes per row).  The loads of the next pass are
+    // issued before the second step of the current one, so their latency overlaps it.
+    R hn[RING / 4][9];
+    R hh[9];
+    auto prefetch = [&](int yb) {
+        const int top = min(yb + RING, ye);
+#pragma unroll
+        for (int k = 0; k < RING / 4; ++k) {
+            const int a = yb + 1 + wave + 4 * k;
+            if (a <= top && in1) load(a, lc, hn[k]);
+        }
+        if (wave == 3) {
+            const int a = yb + 1 + (lane >> 1);
+            if (a <= top) load(a, (lane & 1) ? w + 1 : 0, hh);
+        }
+    };
+
+    // rows ys - 1 and ys, their loads issued together with those of the first pass
+    {
+        R h[9];
+        const int a = ys - 1 + (wave < 2 ? wave : lane >> 1);
+        const int col = wave < 2 ? lc : ((lane & 1) ? w + 1 : 0);
+        const bool act = wave < 2 ? in1 : (wave == 2 && lane < 4);
+        if (act) load(a, col, h);
+        prefetch(ys);
+        if (act) finish(a, col, h);
+    }
+    for (int yb = ys; yb < ye; yb += RING) {
+        const int top = min(yb + RING, ye);   // first step of rows yb + 1 .. top
+#pragma unroll
+        for (int k = 0; k < RING / 4; ++k) {
+            const int a = yb + 1 + wave + 4 * k;
+            if (a <= top && in1) finish(a, lc, hn[k]);
+        }
+        if (wave == 3) {
+            const int a = yb + 1 + (lane >> 1);
+            if (a <= top) finish(a, (lane & 1) ? w + 1 : 0, hh);
+        }
+        __syncthreads();
+        if (yb + RING < ye) prefetch(yb + RING);
+#pragma unroll
+        for (int k = 0; k < RING / 4; ++k) {
+            const int y = yb + wave + 4 * k;
+            if (y < ye && in1) {
+                R h[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) h[i] = R(ring[i][(y - cy(i) - ys + 1) % NR][lc - cx(i)]);
+                double rho_d;
+                const Macro<R> m = macro_of<S>(h, ref, rho_d);
+                flag_bad(!(rho_d > 0.0), blowup, step + 1);
+                collide<MODEL>(h, m, ref, c, N);
+                store_cell(dst, g.plane, (unsigned)y * (unsigned)g.nx + (unsigned)(x0 + lane), h);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Macroscopic fields of the state f(., n) (pulled from the post-collision copy) and per-block
 // partial sums of {rho, rho ux, rho uy, rho |u|^2 / 2, |u|^2} in FP64.
 template <int PREC>
@@ -272,6 +399,43 @@ void launch_step_raw_p(lbm_ctx* ctx, int model, const double* w, const StepShape
         case LBM_PR: launch_step_raw_t<kPR, PREC>(ctx, sh, c, src, dst, step); break;
         case LBM_RR: launch_step_raw_t<kRR, PREC>(ctx, sh, c, src, dst, step); break;
         default: launch_step_raw_t<kStreamOnly, PREC>(ctx, sh, c, src, dst, step); break;
+    }
+}
+
+template <int MODEL, int PREC, int RING>
+void launch_step2_r(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int hs, int src_copy) {
+    using S = typename Store<PREC>::S;
+    const S* src = reinterpret_cast<const S*>(ctx->copy(src_copy));
+    S* dst = reinterpret_cast<S*>(ctx->copy(src_copy ^ 1));
+    const unsigned gsx = (unsigned)((ctx->nx + kStripW - 1) / kStripW);
+    const unsigned gsy = (unsigned)((ctx->ny + hs - 1) / hs);
+    hipLaunchKernelGGL((k_step2<MODEL, PREC, RING>), dim3(gsx * gsy), dim3(256), 0, ctx->stream, src,
+                       dst, ctx->geom(), c, ref_as<typename Store<PREC>::R>(ctx->ref), ctx->eq_order,
+                       (int)ctx->step, ctx->d_flag, gsx, hs);
+}
+
+template <int MODEL, int PREC>
+void launch_step2_t(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int ring, int hs, int src_copy) {
+    switch (ring) {
+        case 4: launch_step2_r<MODEL, PREC, 4>(ctx, c, hs, src_copy); break;
+        case 16: launch_step2_r<MODEL, PREC, 16>(ctx, c, hs, src_copy); break;
+        default: launch_step2_r<MODEL, PREC, 8>(ctx, c, hs, src_copy); break;
+    }
+}
+
+template <int PREC>
+void launch_step2_p(lbm_ctx* ctx, int model, const double* w, int ring, int hs, int src_copy) {
+    const Coef<typename Store<PREC>::R> c = make_coef<typename Store<PREC>::R>(w);
+    switch (model) {
+        case LBM_BGK: launch_step2_t<kBGK, PREC>(ctx, c, ring, hs, src_copy); break;
+        case LBM_RM: launch_step2_t<kRM, PREC>(ctx, c, ring, hs, src_copy); break;
+        case LBM_HM: launch_step2_t<kHM, PREC>(ctx, c, ring, hs, src_copy); break;
+        case LBM_CM: launch_step2_t<kCM, PREC>(ctx, c, ring, hs, src_copy); break;
+        case LBM_CHM: launch_step2_t<kCHM, PREC>(ctx, c, ring, hs, src_copy); break;
+        case LBM_K: launch_step2_t<kK, PREC>(ctx, c, ring, hs, src_copy); break;
+        case LBM_PR: launch_step2_t<kPR, PREC>(ctx, c, ring, hs, src_copy); break;
+        case LBM_RR: launch_step2_t<kRR, PREC>(ctx, c, ring, hs, src_copy); break;
+        default: launch_step2_t<kStreamOnly, PREC>(ctx, c, ring, hs, src_copy); break;
     }
 }
 
@@ -425,6 +589,12 @@ int lbm_init_shifted(lbm_ctx** out, int nx, int ny, int prec, int eq_order, doub
     // FP16 rows are 128 bytes per wave and plane: two nodes per thread keep enough bytes in
     // flight (measured on MI355X; lbm_autotune can revise it)
     for (int k = 0; k < 9; ++k) ctx->rows[k] = prec == LBM_F16_SHIFTED ? 2 : 1;
+    const int fstrip = default_fusion_strip(nx, ny, prec);
+    if (fstrip > 0)
+        for (int k = 0; k < 9; ++k) {
+            ctx->fuse_ring[k] = 8;
+            ctx->fuse_strip[k] = fstrip;
+        }
     int rc = check_hip(hipGetDevice(&ctx->device), "hipGetDevice");
     if (rc == LBM_OK) rc = check_hip(hipMalloc(&ctx->d_flag, sizeof(int)), "hipMalloc(flag)");
     if (rc == LBM_OK)
@@ -452,7 +622,15 @@ int lbm_step(lbm_ctx* ctx, int model, const double* omega, int nsteps) {
     if (rc != LBM_OK) return rc;
     if (ctx->step + nsteps >= INT_MAX) return set_error(LBM_EINVAL, "step counter would overflow");
     const StepShape sh = ctx->shape_of(model);
-    for (int s = 0; s < nsteps; ++s) {
+    const int ring = ctx->fuse_ring[lbm_ctx::slot(model)], hs = ctx->fuse_strip[lbm_ctx::slot(model)];
+    int s = 0;
+    if (ring > 0)
+        for (; s + 2 <= nsteps; s += 2) {
+            LBM_DISPATCH_PREC(ctx->prec, launch_step2_p, ctx, model, omega, ring, hs, ctx->cur);
+            ctx->cur ^= 1;
+            ctx->step += 2;
+        }
+    for (; s < nsteps; ++s) {
         LBM_DISPATCH_PREC(ctx->prec, launch_step_p, ctx, model, omega, sh, ctx->cur);
         ctx->cur ^= 1;
         ctx->step += 1;
@@ -554,6 +732,29 @@ int lbm_set_launch(lbm_ctx* ctx, int model, int rows, int xcd) {
     return LBM_OK;
 }
 
+int lbm_set_fusion(lbm_ctx* ctx, int model, int ring_rows, int strip_rows) {
+    if (!ctx) return set_error(LBM_ESTATE, "context is NULL");
+    int rc = validate_model(model, 4);
+    if (rc != LBM_OK) return rc;
+    if (ring_rows != 0 && ring_rows != 4 && ring_rows != 8 && ring_rows != 16)
+        return set_error(LBM_EINVAL, "ring_rows %d not in {0, 4, 8, 16}", ring_rows);
+    if (ring_rows != 0 && (strip_rows < ring_rows || strip_rows > 1 << 20 || strip_rows % ring_rows != 0))
+        return set_error(LBM_EINVAL, "strip_rows %d is not a positive multiple of ring_rows %d", strip_rows,
+                         ring_rows);
+    ctx->fuse_ring[lbm_ctx::slot(model)] = ring_rows;
+    ctx->fuse_strip[lbm_ctx::slot(model)] = ring_rows ? strip_rows : 0;
+    return LBM_OK;
+}
+
+int lbm_get_fusion(lbm_ctx* ctx, int model, int* ring_rows, int* strip_rows) {
+    if (!ctx) return set_error(LBM_ESTATE, "context is NULL");
+    int rc = validate_model(model, 4);
+    if (rc != LBM_OK) return rc;
+    if (ring_rows) *ring_rows = ctx->fuse_ring[lbm_ctx::slot(model)];
+    if (strip_rows) *strip_rows = ctx->fuse_strip[lbm_ctx::slot(model)];
+    return LBM_OK;
+}
+
 int lbm_autotune(lbm_ctx* ctx, int model, const double* omega, int trials, int* rows_out,
                  int* xcd_out, double* us_per_step) {
     if (!ctx) return set_error(LBM_ESTATE, "context is NULL");
@@ -564,33 +765,51 @@ int lbm_autotune(lbm_ctx* ctx, int model, const double* omega, int trials, int* 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     rc = check_hip(hipEventCreate(&e0), "hipEventCreate");
     if (rc == LBM_OK) rc = check_hip(hipEventCreate(&e1), "hipEventCreate");
+    // times `trials` launches of `launch` after one untimed one; milliseconds
+    auto timed = [&](auto&& launch) -> float {
+        launch();
+        if (rc == LBM_OK) rc = check_hip(hipEventRecord(e0, ctx->stream), "hipEventRecord");
+        for (int t = 0; t < trials && rc == LBM_OK; ++t) launch();
+        if (rc == LBM_OK) rc = check_hip(hipGetLastError(), "autotune launch");
+        if (rc == LBM_OK) rc = check_hip(hipEventRecord(e1, ctx->stream), "hipEventRecord");
+        if (rc == LBM_OK) rc = check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+        float ms = 0.f;
+        if (rc == LBM_OK) rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        return ms;
+    };
+    // every launch recomputes from copy `cur` into the other copy: state and counter unchanged
     const int rows_c[3] = {1, 2, 4};
     float best = 0.f;
     int best_rows = ctx->rows[lbm_ctx::slot(model)], best_xcd = ctx->xcd[lbm_ctx::slot(model)];
     for (int ri = 0; ri < 3 && rc == LBM_OK; ++ri)
         for (int xi = 0; xi < 2 && rc == LBM_OK; ++xi) {
             const StepShape sh = step_shape(ctx->nx, ctx->ny, rows_c[ri], xi);
-            // one untimed launch, then `trials` timed ones, all from copy `cur`
-            LBM_DISPATCH_PREC(ctx->prec, launch_step_p, ctx, model, omega, sh, ctx->cur);
-            rc = check_hip(hipEventRecord(e0, ctx->stream), "hipEventRecord");
-            for (int t = 0; t < trials && rc == LBM_OK; ++t)
-                LBM_DISPATCH_PREC(ctx->prec, launch_step_p, ctx, model, omega, sh, ctx->cur);
-            if (rc == LBM_OK) rc = check_hip(hipGetLastError(), "autotune launch");
-            if (rc == LBM_OK) rc = check_hip(hipEventRecord(e1, ctx->stream), "hipEventRecord");
-            if (rc == LBM_OK) rc = check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
-            float ms = 0.f;
-            if (rc == LBM_OK) rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            const float ms = timed([&] { LBM_DISPATCH_PREC(ctx->prec, launch_step_p, ctx, model, omega, sh, ctx->cur); });
             if (rc == LBM_OK && (best == 0.f || ms < best)) {
                 best = ms;
                 best_rows = rows_c[ri];
                 best_xcd = xi;
             }
         }
+    // two-step shapes, per step
+    const int fuse_c[5][2] = {{8, 16}, {8, 32}, {8, 64}, {16, 16}, {4, 64}};
+    int best_ring = 0, best_strip = 0;
+    for (int k = 0; k < 5 && rc == LBM_OK; ++k) {
+        const int ring = fuse_c[k][0], hs = fuse_c[k][1];
+        const float ms = 0.5f * timed([&] { LBM_DISPATCH_PREC(ctx->prec, launch_step2_p, ctx, model, omega, ring, hs, ctx->cur); });
+        if (rc == LBM_OK && ms < best) {
+            best = ms;
+            best_ring = ring;
+            best_strip = hs;
+        }
+    }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (rc != LBM_OK) return rc;
     ctx->rows[lbm_ctx::slot(model)] = best_rows;
     ctx->xcd[lbm_ctx::slot(model)] = best_xcd;
+    ctx->fuse_ring[lbm_ctx::slot(model)] = best_ring;
+    ctx->fuse_strip[lbm_ctx::slot(model)] = best_strip;
     if (rows_out) *rows_out = best_rows;
     if (xcd_out) *xcd_out = best_xcd;
     if (us_per_step) *us_per_step = 1e3 * (double)best / trials;

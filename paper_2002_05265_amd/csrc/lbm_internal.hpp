@@ -320,6 +320,9 @@ struct lbm_ctx {
                   LBM_DEFAULT_XCD, LBM_DEFAULT_XCD, LBM_DEFAULT_XCD, LBM_DEFAULT_XCD,
                   LBM_DEFAULT_XCD};     // XCD-banded tile order, per model
 
+    int fuse_ring[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // two steps per pass: ring rows (0 = off)
+    int fuse_strip[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // and strip height, per model
+
     static int slot(int model) { return (model >= 0 && model < 8) ? model : 8; }
     lbm::StepShape shape_of(int model) const {
         return lbm::step_shape(nx, ny, rows[slot(model)], xcd[slot(model)]);

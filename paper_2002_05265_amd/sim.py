@@ -52,9 +52,17 @@ class Sim:
     def set_launch(self, model, rows: int, xcd: int):
         B.lbm_set_launch(self.ctx, _model_code(model), rows, xcd)
 
+    def set_fusion(self, model, ring_rows: int, strip_rows: int = 0):
+        """Two steps per launch (ring_rows 4, 8 or 16, strip_rows a multiple of it); 0 turns it off."""
+        B.lbm_set_fusion(self.ctx, _model_code(model), ring_rows, strip_rows)
+
+    def fusion(self, model):
+        """(ring_rows, strip_rows) of `model`'s two-step launches, (0, 0) when off."""
+        return B.lbm_get_fusion(self.ctx, _model_code(model))
+
     def autotune(self, model, omega, trials: int = 10):
-        """Pick the fastest launch shape for `model` (state unchanged); returns
-        (rows, xcd, microseconds per step)."""
+        """Pick the fastest launches for `model` (state unchanged); returns the single-step shape
+        (rows, xcd) and the best microseconds per step; fusion() gives the two-step choice."""
         return B.lbm_autotune(self.ctx, _model_code(model), omega, trials)
 
     def moments(self):
