@@ -145,8 +145,8 @@ def time_models(prec: str, n: int, models, steps: int, warmup: int, omega, field
 def batched_sweep(steps: int, plain_f64_mlups: float, n_inst: int = 512):
     """Random stability sweep: n_inst instances (side in {64..512}, Ma in [0, 0.6], log10 nu in
     [-7, -2], model uniform over the eight, one Fourier-mode perturbation of amplitude 1e-3),
-    FP64, advanced by the persistent kernel in pieces of 500 steps with the live instances
-    re-dealt over the XCDs in between.  Throughput counts the nodes actually updated (an
+    FP64, advanced by the persistent kernel (launch shape and one or two steps per pass
+    autotuned) in pieces of 500 steps with the live instances re-dealt over the XCDs in between.  Throughput counts the nodes actually updated (an
     instance stops after the step at which it blew up)."""
     import torch
 
@@ -161,6 +161,7 @@ def batched_sweep(steps: int, plain_f64_mlups: float, n_inst: int = 512):
     fields = [inputs.sweep_fields(d) for d in insts]
     b = Batch(insts, fields, prec="f64", device="cuda:0")
     tuned = b.autotune(3)
+    fused_rows = b.fusion()  # 0: one step per pass won the autotuning
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
@@ -196,11 +197,12 @@ def batched_sweep(steps: int, plain_f64_mlups: float, n_inst: int = 512):
             "vs_plain_same_instances": round(mlups / (plain_updates / plain_sec / 1e6), 3),
             "blown_up": int(sum(1 for bl in blow if bl >= 0)),
             "blowup_steps_first10": blow[:10],
-            "autotuned": {"nodes_per_thread": tuned[0], "groups_per_cu": tuned[1]},
+            "autotuned": {"nodes_per_thread": tuned[0], "groups_per_cu": tuned[1],
+                          "two_step_strip_rows": fused_rows},
             "rebalance_every": 500, "precision": "f64"}
 
 
-def stability_map(L: int = 32, M: float = 50.0):
+def stability_map(L: int = 32, M: float = 50.0, check_every: int = 64, progress_s: float = 0.0):
     """Numerical stability domains of the convected vortex (beta 0.5, R = L/20), every model under
     SRT and REG, nu in {1e-6 .. 1e-2}, Ma in {0.05 .. 0.8}, M convective times each, all runs in
     one batch (FP64).  Reports the largest stable Ma per model, preset and nu."""
@@ -210,11 +212,12 @@ def stability_map(L: int = 32, M: float = 50.0):
     nus = [1e-6, 1e-5, 1e-4, 1e-3, 1e-2]
     machs = [round(0.05 * k, 2) for k in range(1, 17)]
     insts = S.vortex_instances(list(inputs.MODEL_NAMES), ["SRT", "REG"], nus, machs, L=L, M=M)
-    fb, sec, upd = S.run_stability(insts)
+    fb, sec, upd = S.run_stability(insts, check_every=check_every, progress_s=progress_s)
     best = S.max_stable_mach(insts, fb)
     table = {f"{m}-{p}": [best[(m, p, nu)] for nu in nus] for m in inputs.MODEL_NAMES for p in ("SRT", "REG")}
     return {"workload": f"convected vortex L={L}, M={M:g} t_c, {len(insts)} runs (8 models x SRT/REG x "
-                        f"{len(nus)} nu x {len(machs)} Ma), FP64, |u|^2 criterion checked every 64 steps",
+                        f"{len(nus)} nu x {len(machs)} Ma), FP64, |u|^2 criterion checked every "
+                        f"{check_every} steps",
             "seconds": round(sec, 3), "node_updates": upd, "mlups": round(upd / sec / 1e6, 1),
             "nu": nus, "max_stable_mach": table}
 
@@ -554,6 +557,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FP64/FP16, batched and adjoint measurements")
     ap.add_argument("--batch-steps", type=int, default=20000)
+    ap.add_argument("--stability-map", type=int, metavar="L",
+                    help="only run the stability-domain map on L x L vortices (Section 5b; L = 256 is "
+                         "the paper's resolution, minutes of GPU time) and print it as JSON")
     ap.add_argument("--profile-summary", metavar="DIR",
                     help="summarise the rocprofv3 csv output of PROFILE_COMMANDS found under DIR "
                          "into profiles/ (no GPU use)")
@@ -582,6 +588,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 1 << 30, "copy_probe_bytes_written": 1 << 30,
                           "launches": 5}), flush=True)
+        return
+    if args.stability_map:
+        L = args.stability_map
+        out = stability_map(L=L, check_every=max(64, L), progress_s=30.0)
+        print(json.dumps({"stability_map": out}), flush=True)
         return
     models = args.models.split(",")
     n = args.n

@@ -59,7 +59,9 @@ int lbm_batch_create(lbm_batch** out, const lbm_instance_desc* desc, int n, int 
                      const double* rho, const double* ux, const double* uy, void* pop_buf,
                      size_t pop_bytes, void* hip_stream);
 
-/* Advance every live instance by nsteps >= 0 steps in one cooperative persistent launch.
+/* Advance every live instance by nsteps >= 0 steps in one cooperative persistent launch (with
+ * two steps per pass on, lbm_batch_set_fusion: the first 4 * (nsteps / 4) steps in a launch of
+ * the two-step kernel, the rest in one of the single-step kernel).
  * Asynchronous, except that the first run of each launch shape first probes how many workgroups
  * per CU really stay co-resident (the runtime's occupancy figure can be one too high): two
  * non-advancing steps with a 250 ms barrier bound per candidate, from the occupancy figure
@@ -73,9 +75,11 @@ int lbm_batch_run(lbm_batch* b, int nsteps);
 int lbm_batch_status(lbm_batch* b, long long* step, long long* blowup_steps);
 
 /* Current state of one instance as unshifted FP64 populations (device, 9*nx*ny, [q][y][x]).
- * An instance that blew up at step b stops at state b + 1 (the collided state of step b); one
- * retired at step r (lbm_batch_set_active) stops at state r.  Synchronises the stream (to read
- * those records), then enqueues the copy. */
+ * An instance that blew up at step b stops at the state its last pass wrote: state b + 1 (the
+ * collided state of step b) when that pass took one step, the end of the pair containing b
+ * (b + 1 or b + 2) when it took two; either way not a meaningful flow state.  One retired at step
+ * r (lbm_batch_set_active) stops at state r.  Synchronises the stream (to read those records),
+ * then enqueues the copy. */
 int lbm_batch_get_state(lbm_batch* b, int instance, double* f);
 
 /* Domain mean of |u|^2 of every instance's current state, the quantity of the stability
@@ -104,10 +108,26 @@ int lbm_batch_rebalance(lbm_batch* b);
  * lbm_batch_run. */
 int lbm_batch_set_launch(lbm_batch* b, int nodes_per_thread, int groups_per_cu);
 
-/* Autotune the persistent launch: each candidate (nodes per thread in {1, 2, 4} x groups per
- * CU in {limit, limit/2}, limit = the probed residency limit of that shape) runs `trials` (>= 1)
- * steps that all recompute the current step from the same input copy, so states, counters and
- * blow-up records are unchanged.  Keeps and returns the fastest shape.  Synchronises. */
+/* Two steps per pass of the persistent kernel (temporal blocking, as lbm_set_fusion for a single
+ * grid): strip_rows 0 = off (the default), else a positive multiple of 8: each instance is cut
+ * into strips of 64 columns and strip_rows rows, one workgroup advances a strip two steps with
+ * the first step's values in an LDS ring (halo nodes are collided by both strips that need
+ * them), and the workgroups of an XCD meet at one barrier per pair of steps.  Runs of 4 steps
+ * use it (see lbm_batch_run).  Every live instance stays bit-identical to its single-step (and
+ * plain) run and its blow-up step is the same; the state left by a blown-up instance may differ
+ * (see lbm_batch_get_state).  Synchronises the stream when strip_rows changes. */
+int lbm_batch_set_fusion(lbm_batch* b, int strip_rows);
+
+/* The current strip height of two steps per pass (0 = off); strip_rows is a host pointer. */
+int lbm_batch_get_fusion(lbm_batch* b, int* strip_rows);
+
+/* Autotune the persistent launch: each candidate (nodes per thread in {1, 2, 4}, or two steps per
+ * pass at the current strip height (16 rows unless set), x groups per CU in {limit, limit/2},
+ * limit = the probed residency limit of that shape) runs `trials` (>= 1) steps or pairs that all
+ * recompute from the same input copy, so states, counters and blow-up records are unchanged.
+ * Keeps the fastest per step: it sets nodes per thread, groups per CU and whether two steps per
+ * pass are used (lbm_batch_get_fusion), and returns the first two and the time per step.
+ * Synchronises. */
 int lbm_batch_autotune(lbm_batch* b, int trials, int* nodes_per_thread, int* groups_per_cu,
                        double* us_per_step);
 

@@ -82,7 +82,17 @@ class Batch:
     def set_launch(self, nodes_per_thread: int, groups_per_cu: int = 0):
         B.lbm_batch_set_launch(self.handle, nodes_per_thread, groups_per_cu)
 
+    def set_fusion(self, strip_rows: int):
+        """Two steps per pass over strips of strip_rows rows (a multiple of 8); 0 turns it off."""
+        B.lbm_batch_set_fusion(self.handle, strip_rows)
+
+    def fusion(self) -> int:
+        """Strip height of two steps per pass, 0 when off."""
+        return B.lbm_batch_get_fusion(self.handle)
+
     def autotune(self, trials: int = 5):
+        """Fastest launch shape (nodes per thread, groups per CU, us per step); also decides
+        whether two steps per pass are used (see fusion())."""
         return B.lbm_batch_autotune(self.handle, trials)
 
     def close(self):

@@ -21,6 +21,7 @@
 #include "lbm_batch.h"
 #include "lbm_cell.hpp"
 #include "lbm_internal.hpp"
+#include "lbm_step2.hpp"
 
 using namespace lbm;
 
@@ -116,50 +117,15 @@ __device__ __forceinline__ bool xcd_barrier(unsigned* ctr, int step, unsigned co
     return ok != 0;
 }
 
-// Loads that bypass the CU's L1 (agent scope) and are served by the XCD's L2.
-template <typename S>
-__device__ __forceinline__ S ld_l2(const S* p) {
-    if constexpr (sizeof(S) == 2) {
-        const unsigned short v = __hip_atomic_load(reinterpret_cast<const unsigned short*>(p), __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-        return __builtin_bit_cast(S, v);
-    } else {
-        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-}
-
-// pull_load (f_i(x) = stored_i(x - xi_i)) through ld_l2.
-template <typename S, typename R>
-__device__ __forceinline__ void pull_load_l2(const S* __restrict__ src, long long plane, const Nbr& n, R (&h)[9]) {
-    constexpr unsigned E = sizeof(S);
-    const unsigned r0 = n.r0 * E, rm = n.rm * E, rp = n.rp * E;
-    const unsigned x0 = n.x * E, xm = n.xm * E, xp = n.xp * E;
-    h[0] = R(ld_l2(plane_at(src, plane, 0, r0 + x0)));
-    h[1] = R(ld_l2(plane_at(src, plane, 1, r0 + xm)));
-    h[2] = R(ld_l2(plane_at(src, plane, 2, rm + x0)));
-    h[3] = R(ld_l2(plane_at(src, plane, 3, r0 + xp)));
-    h[4] = R(ld_l2(plane_at(src, plane, 4, rp + x0)));
-    h[5] = R(ld_l2(plane_at(src, plane, 5, rm + xm)));
-    h[6] = R(ld_l2(plane_at(src, plane, 6, rm + xp)));
-    h[7] = R(ld_l2(plane_at(src, plane, 7, rp + xp)));
-    h[8] = R(ld_l2(plane_at(src, plane, 8, rp + xm)));
-}
-
-template <int PREC, int NPT>
-__global__ __launch_bounds__(kTileThreads) void k_batch(
-    typename Store<PREC>::S* __restrict__ base, long long copy_elems,
-    const BDesc<typename Store<PREC>::R>* __restrict__ desc, const int2* __restrict__ run,
-    const int* __restrict__ xtab, int* __restrict__ blowup, const int* __restrict__ active,
-    unsigned* __restrict__ bar, int* __restrict__ err, long long* __restrict__ step_ctr, int nsteps,
-    int advance, long long timeout_ticks) {
-    using S = typename Store<PREC>::S;
-    using R = typename Store<PREC>::R;
+// Registration of a workgroup of the persistent grid: its rank among the workgroups on its XCD
+// and their count, once every workgroup of the grid has registered.  False if the launch must
+// stop (a bound passed, or an XCD that owns work got no workgroup: err = 2).
+__device__ __forceinline__ bool register_group(unsigned* __restrict__ bar, const int* __restrict__ xtab,
+                                               int* __restrict__ err, long long timeout_ticks, unsigned xcc,
+                                               unsigned& rank, unsigned& count) {
     __shared__ unsigned s_rank, s_count;
     __shared__ int s_go;
-    const int tid = threadIdx.x;
-    const unsigned xcc = xcc_id();
-    // registration: rank of this workgroup among those on its XCD, then the final counts
-    if (tid == 0) {
+    if (threadIdx.x == 0) {
         s_rank = __hip_atomic_fetch_add(bar + kLine * (1 + xcc), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // the XCD count must be complete before the grid count is: wait until this add has been
         // performed (it returns) before issuing the next one, so that whoever sees the grid count
@@ -178,8 +144,24 @@ __global__ __launch_bounds__(kTileThreads) void k_batch(
         s_go = go;
     }
     __syncthreads();
-    if (!s_go) return;
-    const unsigned rank = s_rank, count = s_count;
+    rank = s_rank;
+    count = s_count;
+    return s_go != 0;
+}
+
+template <int PREC, int NPT>
+__global__ __launch_bounds__(kTileThreads) void k_batch(
+    typename Store<PREC>::S* __restrict__ base, long long copy_elems,
+    const BDesc<typename Store<PREC>::R>* __restrict__ desc, const int2* __restrict__ run,
+    const int* __restrict__ xtab, int* __restrict__ blowup, const int* __restrict__ active,
+    int* __restrict__ lastcopy, unsigned* __restrict__ bar, int* __restrict__ err,
+    long long* __restrict__ step_ctr, int nsteps, int advance, long long timeout_ticks) {
+    using S = typename Store<PREC>::S;
+    using R = typename Store<PREC>::R;
+    const int tid = threadIdx.x;
+    const unsigned xcc = xcc_id();
+    unsigned rank, count;
+    if (!register_group(bar, xtab, err, timeout_ticks, xcc, rank, count)) return;
     const int first_tile = xtab[2 * xcc], ntiles = xtab[2 * xcc + 1];
     unsigned* xbar = bar + kLine * (1 + kMaxXcc + xcc);
     const long long n0 = *step_ctr;
@@ -194,6 +176,7 @@ __global__ __launch_bounds__(kTileThreads) void k_batch(
             const BDesc<R>& d = desc[j];
             const int frozen = __hip_atomic_load(blowup + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if ((long long)frozen < n || !active[j]) continue;  // blew up earlier, or retired
+            if (advance && e.y == 0 && tid == 0) lastcopy[j] = sc ^ 1;
             const int first = e.y * NPT * kTileThreads + tid;
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
@@ -215,6 +198,63 @@ __global__ __launch_bounds__(kTileThreads) void k_batch(
         if (!xcd_barrier(xbar, s, count, err, timeout_ticks)) return;
     }
     if (advance && blockIdx.x == 0 && tid == 0) *step_ctr = n0 + nsteps;
+}
+
+// Two steps per pass: the same persistent grid and XCD-local barriers as k_batch, one barrier
+// per pair of steps, over strips of kStripW columns and `hs` rows of the instances (the strip
+// body of the plain two-step kernel, with loads that bypass L1 and plain stores).  Pair p of a
+// launch reads the copy of its first step's parity at the launch start, flipped p times, so
+// after an even number of pairs every live instance's state is back in the copy of its step's
+// parity.  Whether a strip is skipped (its instance blew up before the pair, or was retired)
+// is decided once per workgroup: the strip body contains block barriers.
+template <int PREC, int RING>
+__global__ __launch_bounds__(kTileThreads) void k_batch2(
+    typename Store<PREC>::S* __restrict__ base, long long copy_elems,
+    const BDesc<typename Store<PREC>::R>* __restrict__ desc, const int2* __restrict__ run,
+    const int* __restrict__ xtab, int* __restrict__ blowup, const int* __restrict__ active,
+    int* __restrict__ lastcopy, unsigned* __restrict__ bar, int* __restrict__ err,
+    long long* __restrict__ step_ctr, int npairs, int advance, long long timeout_ticks, int hs) {
+    using S = typename Store<PREC>::S;
+    using R = typename Store<PREC>::R;
+    __shared__ S ring[9][RING + 2][kStripW + 2];
+    __shared__ int s_skip;
+    const int tid = threadIdx.x;
+    const unsigned xcc = xcc_id();
+    unsigned rank, count;
+    if (!register_group(bar, xtab, err, timeout_ticks, xcc, rank, count)) return;
+    const int first_strip = xtab[2 * xcc], nstrips = xtab[2 * xcc + 1];
+    unsigned* xbar = bar + kLine * (1 + kMaxXcc + xcc);
+    const long long n0 = *step_ctr;
+    for (int p = 0; p < npairs; ++p) {
+        const long long n = n0 + (advance ? 2 * p : 0);
+        const int sc = (int)(n0 & 1) ^ (advance ? (p & 1) : 0);
+        const S* src = base + sc * copy_elems;
+        S* dst = base + (sc ^ 1) * copy_elems;
+        for (int t = (int)rank; t < nstrips; t += (int)count) {
+            const int2 e = run[first_strip + t];  // (instance, strip within the instance)
+            const int j = e.x;
+            const BDesc<R>& d = desc[j];
+            if (tid == 0) {
+                const int frozen = __hip_atomic_load(blowup + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_skip = ((long long)frozen < n || !active[j]) ? 1 : 0;  // blew up earlier, or retired
+                if (!s_skip && advance && e.y == 0) lastcopy[j] = sc ^ 1;
+            }
+            __syncthreads();
+            const bool skip = s_skip != 0;
+            __syncthreads();  // s_skip is rewritten for the next strip only after every thread read it
+            if (skip) continue;
+            const int gsx = (d.nx + kStripW - 1) / kStripW;
+            const int sy = e.y / gsx;
+            const int x0 = (e.y - sy * gsx) * kStripW, ys = sy * hs;
+            const Geom g{d.nx, d.ny, d.plane};
+            strip_two_steps<RING, true, false>(ring, src + d.off, dst + d.off, g, d.ref, x0, ys, min(ys + hs, d.ny),
+                                               (int)n, blowup + j, [&](R(&h)[9], const Macro<R>& m) {
+                                                   collide_model(d.model, h, m, d.ref, d.c, d.N);
+                                               });
+        }
+        if (!xcd_barrier(xbar, p, count, err, timeout_ticks)) return;
+    }
+    if (advance && blockIdx.x == 0 && tid == 0) *step_ctr = n0 + 2LL * npairs;
 }
 
 // XCD of each workgroup of a small probe launch (which XCC ids the device dispatches to).
@@ -332,19 +372,24 @@ struct lbm_batch {
     char* buf = nullptr;
     size_t bytes = 0;
     hipStream_t stream = nullptr;      // caller's stream
-    int cus = 0, occ[3] = {0, 0, 0};   // CUs, occupancy limit per NPT index (runtime query)
-    int resident[3] = {0, 0, 0};       // groups per CU confirmed co-resident (0 = not probed)
+    // launch shapes k: 0, 1, 2 = one step per pass with 1, 2, 4 nodes per thread; 3 = two
+    // steps per pass over strips
+    int cus = 0, occ[4] = {0, 0, 0, 0};        // CUs, occupancy limit per shape (runtime query)
+    int resident[4] = {0, 0, 0, 0};            // groups per CU confirmed co-resident (0 = not probed)
     int npt = 1, gpc = 0;              // launch shape (gpc 0 = occupancy limit)
+    int fuse = 0, hs = 16;             // two steps per pass (strip height hs) for runs of 4 steps
     long long step = 0;                // host mirror of the step counter
     void* d_desc[3] = {nullptr, nullptr, nullptr};  // descriptors per NPT (tile0 differs)
     int* d_tiles[3] = {nullptr, nullptr, nullptr};  // every tile of every instance, instance order
     int ntiles[3] = {0, 0, 0};
-    int2* d_run[3] = {nullptr, nullptr, nullptr};   // tiles of live instances, one list per XCD
-    int* d_xtab[3] = {nullptr, nullptr, nullptr};   // per XCC id: first run entry, entry count
+    int2* d_run[4] = {nullptr, nullptr, nullptr, nullptr};  // tiles / strips of live instances, one list per XCD
+    int* d_xtab[4] = {nullptr, nullptr, nullptr, nullptr};  // per XCC id: first run entry, entry count
+    long long run_cap[4] = {0, 0, 0, 0};                    // entries d_run[k] can hold
     std::vector<int> xccs;                          // XCC ids the device dispatches to
     int* d_blowup = nullptr;
     int* d_active = nullptr;           // per instance: nonzero = advanced by lbm_batch_run
     int* d_retired = nullptr;          // per instance: step at which it was retired (INT_MAX)
+    int* d_lastcopy = nullptr;         // per instance: copy its last pass wrote (0 before any)
     double* d_u2part = nullptr;        // per 256-node tile: partial sums of |u|^2
     unsigned* d_bar = nullptr;
     int* d_err = nullptr;
@@ -389,14 +434,52 @@ hipError_t launch_batch_t(lbm_batch* b, hipStream_t s, int G, int nsteps, int ad
     const int* xtab = b->d_xtab[k];
     int* blowup = b->d_blowup;
     const int* active = b->d_active;
+    int* lastcopy = b->d_lastcopy;
     unsigned* bar = b->d_bar;
     int* err = b->d_err;
     long long* step = b->d_step;
     long long timeout = b->timeout_ticks;
-    void* args[] = {&base, &copy_elems, &desc, &tiles, &xtab, &blowup, &active, &bar, &err, &step,
+    void* args[] = {&base, &copy_elems, &desc, &tiles, &xtab, &blowup, &active, &lastcopy, &bar, &err, &step,
                     &nsteps, &advance, &timeout};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_batch<PREC, NPT>), dim3(G),
                                       dim3(kTileThreads), args, 0, s);
+}
+
+constexpr int kBatchRing = 8;
+
+template <int PREC>
+hipError_t launch_batch2_t(lbm_batch* b, hipStream_t s, int G, int npairs, int advance) {
+    using S = typename Store<PREC>::S;
+    using R = typename Store<PREC>::R;
+    S* base = reinterpret_cast<S*>(b->buf);
+    long long copy_elems = b->copy_elems;
+    const BDesc<R>* desc = reinterpret_cast<const BDesc<R>*>(b->d_desc[0]);
+    const int2* strips = b->d_run[3];
+    const int* xtab = b->d_xtab[3];
+    int* blowup = b->d_blowup;
+    const int* active = b->d_active;
+    int* lastcopy = b->d_lastcopy;
+    unsigned* bar = b->d_bar;
+    int* err = b->d_err;
+    long long* step = b->d_step;
+    long long timeout = b->timeout_ticks;
+    int hs = b->hs;
+    void* args[] = {&base, &copy_elems, &desc, &strips, &xtab, &blowup, &active, &lastcopy, &bar, &err, &step,
+                    &npairs, &advance, &timeout, &hs};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_batch2<PREC, kBatchRing>), dim3(G),
+                                      dim3(kTileThreads), args, 0, s);
+}
+
+const void* batch2_kernel_p(int prec) {
+    switch (prec) {
+        case LBM_F64: return reinterpret_cast<const void*>(&k_batch2<kF64, kBatchRing>);
+        case LBM_F32_SHIFTED: return reinterpret_cast<const void*>(&k_batch2<kF32, kBatchRing>);
+        default: return reinterpret_cast<const void*>(&k_batch2<kF16, kBatchRing>);
+    }
+}
+
+long long strips_of(const lbm_instance_desc& d, int hs) {
+    return (long long)((d.nx + kStripW - 1) / kStripW) * ((d.ny + hs - 1) / hs);
 }
 
 template <int PREC>
@@ -428,19 +511,21 @@ int deal_tables(lbm_batch* b, const std::vector<char>& live) {
         owner[j] = b->xccs[best];
     }
     const int npts[3] = {1, 2, 4};
-    for (int k = 0; k < 3; ++k) {
-        const long long tile_nodes = (long long)kTileThreads * npts[k];
+    for (int k = 0; k < 4; ++k) {
         std::vector<int2> run;
         std::vector<int> xtab(2 * kMaxXcc, 0);
         for (int x : b->xccs) {
             xtab[2 * x] = (int)run.size();
             for (int j = 0; j < n; ++j) {
                 if (owner[j] != x) continue;
-                const int nt = (int)((cells(j) + tile_nodes - 1) / tile_nodes);
-                for (int t = 0; t < nt; ++t) run.push_back(make_int2(j, t));
+                const long long nt = k < 3 ? (cells(j) + (long long)kTileThreads * npts[k] - 1) /
+                                                 ((long long)kTileThreads * npts[k])
+                                           : strips_of(b->hdesc[j], b->hs);
+                for (int t = 0; t < (int)nt; ++t) run.push_back(make_int2(j, t));
             }
             xtab[2 * x + 1] = (int)run.size() - xtab[2 * x];
         }
+        if ((long long)run.size() > b->run_cap[k]) return set_error(LBM_EHIP, "run table %d overflow", k);
         int rc = LBM_OK;
         if (!run.empty())
             rc = check_hip(hipMemcpy(b->d_run[k], run.data(), sizeof(int2) * run.size(), hipMemcpyHostToDevice),
@@ -453,50 +538,57 @@ int deal_tables(lbm_batch* b, const std::vector<char>& live) {
     return LBM_OK;
 }
 
-int groups_limit(lbm_batch* b) {
-    const int k = npt_index(b->npt);
-    return b->resident[k] > 0 ? b->resident[k] : b->occ[k];
-}
+int shape_of(const lbm_batch* b, bool fused) { return fused ? 3 : npt_index(b->npt); }
 
-int grid_size(lbm_batch* b) {
-    const int lim = groups_limit(b);
+int groups_limit(lbm_batch* b, int k) { return b->resident[k] > 0 ? b->resident[k] : b->occ[k]; }
+
+int grid_size(lbm_batch* b, int k) {
+    const int lim = groups_limit(b, k);
     const int per = (b->gpc <= 0 || b->gpc > lim) ? lim : b->gpc;
     return b->cus * per;
 }
 
-// Reset the barrier counter, then one cooperative launch of the persistent kernel on G groups.
-int run_persistent_on(lbm_batch* b, int G, int nsteps, int advance, long long ticks) {
+// Reset the barrier counter, then one cooperative launch of the persistent kernel of shape k on
+// G groups: `units` steps (shapes 0-2) or pairs of steps (shape 3).
+int run_persistent_on(lbm_batch* b, int k, int G, int units, int advance, long long ticks) {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, b->stream, b->d_bar);
     int rc = check_hip(hipGetLastError(), "barrier reset launch");
     if (rc != LBM_OK) return rc;
     const long long keep = b->timeout_ticks;
     b->timeout_ticks = ticks;
     hipError_t e;
-    switch (b->prec) {
-        case LBM_F64: e = launch_batch_p<kF64>(b, b->stream, G, nsteps, advance); break;
-        case LBM_F32_SHIFTED: e = launch_batch_p<kF32>(b, b->stream, G, nsteps, advance); break;
-        default: e = launch_batch_p<kF16>(b, b->stream, G, nsteps, advance); break;
+    if (k == 3) {
+        switch (b->prec) {
+            case LBM_F64: e = launch_batch2_t<kF64>(b, b->stream, G, units, advance); break;
+            case LBM_F32_SHIFTED: e = launch_batch2_t<kF32>(b, b->stream, G, units, advance); break;
+            default: e = launch_batch2_t<kF16>(b, b->stream, G, units, advance); break;
+        }
+    } else {
+        switch (b->prec) {
+            case LBM_F64: e = launch_batch_p<kF64>(b, b->stream, G, units, advance); break;
+            case LBM_F32_SHIFTED: e = launch_batch_p<kF32>(b, b->stream, G, units, advance); break;
+            default: e = launch_batch_p<kF16>(b, b->stream, G, units, advance); break;
+        }
     }
     b->timeout_ticks = keep;
     return check_hip(e, "cooperative launch of the persistent kernel");
 }
 
-int run_persistent(lbm_batch* b, int nsteps, int advance) {
-    return run_persistent_on(b, grid_size(b), nsteps, advance, b->timeout_ticks);
+int run_persistent(lbm_batch* b, int k, int units, int advance) {
+    return run_persistent_on(b, k, grid_size(b, k), units, advance, b->timeout_ticks);
 }
 
 // The occupancy query can promise more resident workgroups per CU than the hardware actually
 // co-schedules for a kernel (measured on MI355X: 8 reported, 7 resident for the FP32 and FP16
 // kernels), and a persistent grid larger than what is resident cannot pass its first barrier.
-// Before the first run of each nodes-per-thread shape, a probe runs two non-advancing steps
-// (they recompute the current step from the same copy: state, counters and records unchanged)
-// with a short barrier bound, at `per` groups per CU from the query's value down, and keeps the
-// first `per` whose grid passed every barrier.  A failed probe ends by its bound: every wave exits.
-int ensure_resident(lbm_batch* b) {
-    const int k = npt_index(b->npt);
+// Before the first run of each launch shape, a probe runs two non-advancing steps (or pairs;
+// they recompute from the same copy: state, counters and records unchanged) with a short
+// barrier bound, at `per` groups per CU from the query's value down, and keeps the first `per`
+// whose grid passed every barrier.  A failed probe ends by its bound: every wave exits.
+int ensure_resident(lbm_batch* b, int k) {
     if (b->resident[k] > 0) return LBM_OK;
     for (int per = b->occ[k]; per >= 1; --per) {
-        int rc = run_persistent_on(b, b->cus * per, 2, 0, b->probe_ticks);
+        int rc = run_persistent_on(b, k, b->cus * per, 2, 0, b->probe_ticks);
         if (rc == LBM_OK) rc = check_hip(hipStreamSynchronize(b->stream), "synchronise (residency probe)");
         int err = 0;
         if (rc == LBM_OK) rc = check_hip(hipMemcpy(&err, b->d_err, sizeof(int), hipMemcpyDeviceToHost), "copy err");
@@ -511,6 +603,55 @@ int ensure_resident(lbm_batch* b) {
         if (rc != LBM_OK) return rc;
     }
     return set_error(LBM_EHIP, "no persistent grid of this shape stays co-resident");
+}
+
+// Advance every live instance by `units` steps (k < 3) or pairs (k = 3), in launches short
+// enough that the barrier counter G * units stays below 2^31.
+int run_units(lbm_batch* b, int k, int units) {
+    if (units <= 0) return LBM_OK;
+    int rc = ensure_resident(b, k);
+    if (rc != LBM_OK) return rc;
+    const long long G = grid_size(b, k);
+    const int chunk = (int)std::min<long long>(units, (1LL << 31) / G);
+    int left = units;
+    while (left > 0) {
+        const int u = std::min(left, chunk);
+        rc = run_persistent(b, k, u, 1);
+        if (rc != LBM_OK) return rc;
+        left -= u;
+        b->step += k == 3 ? 2LL * u : (long long)u;
+    }
+    return LBM_OK;
+}
+
+// Live instances: neither blown up nor retired.  Synchronous.
+int live_set(lbm_batch* b, std::vector<char>& live) {
+    std::vector<int> blow((size_t)b->n), ret((size_t)b->n);
+    int rc = check_hip(hipStreamSynchronize(b->stream), "synchronise");
+    if (rc == LBM_OK)
+        rc = check_hip(hipMemcpy(blow.data(), b->d_blowup, sizeof(int) * blow.size(), hipMemcpyDeviceToHost),
+                       "copy blow-up steps");
+    if (rc == LBM_OK)
+        rc = check_hip(hipMemcpy(ret.data(), b->d_retired, sizeof(int) * ret.size(), hipMemcpyDeviceToHost),
+                       "copy retired steps");
+    if (rc != LBM_OK) return rc;
+    live.assign((size_t)b->n, 0);
+    for (int j = 0; j < b->n; ++j) live[j] = blow[j] == INT_MAX && ret[j] == INT_MAX;
+    return LBM_OK;
+}
+
+// (Re)allocate the strip table for the current strip height.
+int alloc_strips(lbm_batch* b) {
+    long long total = 0;
+    for (int j = 0; j < b->n; ++j) total += strips_of(b->hdesc[j], b->hs);
+    if (total >= INT_MAX) return set_error(LBM_EINVAL, "too many strips (%lld)", total);
+    if (total <= b->run_cap[3]) return LBM_OK;
+    if (b->d_run[3]) (void)hipFree(b->d_run[3]);
+    b->d_run[3] = nullptr;
+    b->run_cap[3] = 0;
+    int rc = check_hip(hipMalloc(&b->d_run[3], sizeof(int2) * (size_t)total), "hipMalloc(strip run)");
+    if (rc == LBM_OK) b->run_cap[3] = total;
+    return rc;
 }
 
 }  // namespace
@@ -657,12 +798,21 @@ int lbm_batch_create(lbm_batch** out, const lbm_instance_desc* desc, int n, int 
             rc = check_hip(hipMemcpy(b->d_tiles[k], tiles.data(), sizeof(int) * tiles.size(), hipMemcpyHostToDevice),
                            "copy tiles");
         if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_run[k], sizeof(int2) * tiles.size()), "hipMalloc(run)");
+        if (rc == LBM_OK) b->run_cap[k] = (long long)tiles.size();
         if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_xtab[k], sizeof(int) * 2 * kMaxXcc), "hipMalloc(xtab)");
     }
+    // two steps per pass: occupancy, strip table
+    if (rc == LBM_OK)
+        rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[3], batch2_kernel_p(prec), kTileThreads, 0),
+                       "occupancy");
+    if (rc == LBM_OK && b->occ[3] < 1) rc = set_error(LBM_EHIP, "persistent two-step kernel does not fit a CU");
+    if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_xtab[3], sizeof(int) * 2 * kMaxXcc), "hipMalloc(xtab)");
+    if (rc == LBM_OK) rc = alloc_strips(b);
     if (rc == LBM_OK) rc = deal_tables(b, std::vector<char>((size_t)n, 1));
     if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_blowup, sizeof(int) * (size_t)n), "hipMalloc(blowup)");
     if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_active, sizeof(int) * (size_t)n), "hipMalloc(active)");
     if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_retired, sizeof(int) * (size_t)n), "hipMalloc(retired)");
+    if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_lastcopy, sizeof(int) * (size_t)n), "hipMalloc(lastcopy)");
     if (rc == LBM_OK)
         rc = check_hip(hipMalloc(&b->d_u2part, sizeof(double) * (size_t)b->ntiles[0]), "hipMalloc(u2 partials)");
     if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_bar, sizeof(unsigned) * kBarrierWords), "hipMalloc(barrier)");
@@ -676,6 +826,7 @@ int lbm_batch_create(lbm_batch** out, const lbm_instance_desc* desc, int n, int 
         hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, b->stream, b->d_blowup, n, INT_MAX);
         hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, b->stream, b->d_active, n, 1);
         hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, b->stream, b->d_retired, n, INT_MAX);
+        hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, b->stream, b->d_lastcopy, n, 0);
         hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, b->stream, b->d_bar);
         hipLaunchKernelGGL(k_clear_i32, dim3(1), dim3(64), 0, b->stream, b->d_err);
         switch (prec) {
@@ -710,20 +861,12 @@ int lbm_batch_run(lbm_batch* b, int nsteps) {
     if (nsteps < 0) return set_error(LBM_EINVAL, "nsteps %d < 0", nsteps);
     if (b->step + nsteps >= INT_MAX) return set_error(LBM_EINVAL, "step counter would overflow");
     if (nsteps == 0) return LBM_OK;
-    const int rc0 = ensure_resident(b);
-    if (rc0 != LBM_OK) return rc0;
-    // keep the barrier counter G * nsteps below 2^32
-    const long long G = grid_size(b);
-    const int chunk = (int)std::min<long long>(nsteps, (1LL << 31) / G);
-    int left = nsteps;
-    while (left > 0) {
-        const int k = std::min(left, chunk);
-        const int rc = run_persistent(b, k, 1);
-        if (rc != LBM_OK) return rc;
-        left -= k;
-        b->step += k;
-    }
-    return LBM_OK;
+    // two steps per pass in runs of 4 steps (an even number of pairs leaves every live state in
+    // the copy of its step's parity), the rest one step per pass
+    const int pairs = b->fuse ? 2 * (nsteps / 4) : 0;
+    int rc = run_units(b, 3, pairs);
+    if (rc == LBM_OK) rc = run_units(b, npt_index(b->npt), nsteps - 2 * pairs);
+    return rc;
 }
 
 int lbm_batch_status(lbm_batch* b, long long* step, long long* blowup_steps) {
@@ -754,18 +897,18 @@ int lbm_batch_get_state(lbm_batch* b, int instance, double* f) {
     const lbm_instance_desc& d = b->hdesc[instance];
     const Launch l = launch_for(d.nx, d.ny);
     const Geom g{d.nx, d.ny, b->plane[instance]};
-    // the instance's own last step: it stops advancing after blowing up or being retired
-    int blow = INT_MAX, ret = INT_MAX;
+    // a live instance's state is in the copy of the step's parity; one that blew up or was
+    // retired stopped advancing, and its state is in the copy its last pass wrote
+    int blow = INT_MAX, ret = INT_MAX, last = 0;
     int rc = check_hip(hipStreamSynchronize(b->stream), "synchronise");
     if (rc == LBM_OK)
         rc = check_hip(hipMemcpy(&blow, b->d_blowup + instance, sizeof(int), hipMemcpyDeviceToHost), "copy blow-up");
     if (rc == LBM_OK)
         rc = check_hip(hipMemcpy(&ret, b->d_retired + instance, sizeof(int), hipMemcpyDeviceToHost), "copy retired");
+    if (rc == LBM_OK)
+        rc = check_hip(hipMemcpy(&last, b->d_lastcopy + instance, sizeof(int), hipMemcpyDeviceToHost), "copy last copy");
     if (rc != LBM_OK) return rc;
-    long long own = b->step;
-    if (blow != INT_MAX) own = std::min(own, (long long)blow + 1);
-    if (ret != INT_MAX) own = std::min(own, (long long)ret);
-    const int sc = (int)(own & 1);
+    const int sc = (blow == INT_MAX && ret == INT_MAX) ? (int)(b->step & 1) : last;
     const size_t eoff = (size_t)(sc * b->copy_elems + b->off[instance]);
     const Pop9 fref = reference_populations(storage_reference(b->prec, d.rho0, d.ux0, d.uy0), d.eq_order);
     switch (b->prec) {
@@ -826,18 +969,32 @@ int lbm_batch_set_active(lbm_batch* b, const int* active) {
 
 int lbm_batch_rebalance(lbm_batch* b) {
     if (!b) return set_error(LBM_ESTATE, "batch is NULL");
-    std::vector<int> blow((size_t)b->n), ret((size_t)b->n);
-    int rc = check_hip(hipStreamSynchronize(b->stream), "synchronise");
-    if (rc == LBM_OK)
-        rc = check_hip(hipMemcpy(blow.data(), b->d_blowup, sizeof(int) * blow.size(), hipMemcpyDeviceToHost),
-                       "copy blow-up steps");
-    if (rc == LBM_OK)
-        rc = check_hip(hipMemcpy(ret.data(), b->d_retired, sizeof(int) * ret.size(), hipMemcpyDeviceToHost),
-                       "copy retired steps");
-    if (rc != LBM_OK) return rc;
-    std::vector<char> live((size_t)b->n);
-    for (int j = 0; j < b->n; ++j) live[j] = blow[j] == INT_MAX && ret[j] == INT_MAX;
-    return deal_tables(b, live);
+    std::vector<char> live;
+    const int rc = live_set(b, live);
+    return rc != LBM_OK ? rc : deal_tables(b, live);
+}
+
+int lbm_batch_set_fusion(lbm_batch* b, int strip_rows) {
+    if (!b) return set_error(LBM_ESTATE, "batch is NULL");
+    if (strip_rows < 0 || (strip_rows > 0 && (strip_rows % kBatchRing != 0 || strip_rows > (1 << 20))))
+        return set_error(LBM_EINVAL, "strip_rows %d: 0 or a positive multiple of %d", strip_rows, kBatchRing);
+    if (strip_rows == 0) {
+        b->fuse = 0;
+        return LBM_OK;
+    }
+    b->fuse = 1;
+    if (strip_rows == b->hs) return LBM_OK;
+    b->hs = strip_rows;
+    int rc = alloc_strips(b);
+    std::vector<char> live;
+    if (rc == LBM_OK) rc = live_set(b, live);
+    return rc != LBM_OK ? rc : deal_tables(b, live);
+}
+
+int lbm_batch_get_fusion(lbm_batch* b, int* strip_rows) {
+    if (!b) return set_error(LBM_ESTATE, "batch is NULL");
+    if (strip_rows) *strip_rows = b->fuse ? b->hs : 0;
+    return LBM_OK;
 }
 
 int lbm_batch_set_launch(lbm_batch* b, int nodes_per_thread, int groups_per_cu) {
@@ -858,24 +1015,27 @@ int lbm_batch_autotune(lbm_batch* b, int trials, int* nodes_per_thread, int* gro
     int rc = check_hip(hipEventCreate(&e0), "hipEventCreate");
     if (rc == LBM_OK) rc = check_hip(hipEventCreate(&e1), "hipEventCreate");
     const int npts[3] = {1, 2, 4};
-    const int keep_npt = b->npt, keep_gpc = b->gpc;
+    const int keep_npt = b->npt, keep_gpc = b->gpc, keep_fuse = b->fuse;
     float best = 0.f;
-    int best_npt = keep_npt, best_gpc = keep_gpc;
-    for (int k = 0; k < 3 && rc == LBM_OK; ++k)
+    int best_npt = keep_npt, best_gpc = keep_gpc, best_fuse = keep_fuse;
+    // candidates: one step per pass (1, 2, 4 nodes per thread), then two steps per pass; each at
+    // the residency limit and at half of it; times per step
+    for (int k = 0; k < 4 && rc == LBM_OK; ++k)
         for (int half = 0; half < 2 && rc == LBM_OK; ++half) {
-            b->npt = npts[k];
-            rc = ensure_resident(b);
+            if (k < 3) b->npt = npts[k];
+            rc = ensure_resident(b, k);
             if (rc != LBM_OK) break;
-            const int lim = groups_limit(b);
+            const int lim = groups_limit(b, k);
             b->gpc = half ? std::max(1, lim / 2) : 0;
             if (half && b->gpc == lim) continue;
-            rc = run_persistent(b, 1, 0);  // warm-up (non-advancing)
+            rc = run_persistent(b, k, 1, 0);  // warm-up (non-advancing)
             if (rc == LBM_OK) rc = check_hip(hipEventRecord(e0, b->stream), "hipEventRecord");
-            if (rc == LBM_OK) rc = run_persistent(b, trials, 0);
+            if (rc == LBM_OK) rc = run_persistent(b, k, trials, 0);
             if (rc == LBM_OK) rc = check_hip(hipEventRecord(e1, b->stream), "hipEventRecord");
             if (rc == LBM_OK) rc = check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
             float ms = 0.f;
             if (rc == LBM_OK) rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            if (k == 3) ms *= 0.5f;
             int err = 0;
             if (rc == LBM_OK) rc = check_hip(hipMemcpy(&err, b->d_err, sizeof(int), hipMemcpyDeviceToHost), "copy err");
             if (rc == LBM_OK && err) rc = set_error(LBM_EHIP, "persistent launch stopped: a barrier timed out");
@@ -883,15 +1043,17 @@ int lbm_batch_autotune(lbm_batch* b, int trials, int* nodes_per_thread, int* gro
                 best = ms;
                 best_npt = b->npt;
                 best_gpc = b->gpc;
+                best_fuse = k == 3 ? 1 : 0;
             }
         }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     b->npt = rc == LBM_OK ? best_npt : keep_npt;
     b->gpc = rc == LBM_OK ? best_gpc : keep_gpc;
+    b->fuse = rc == LBM_OK ? best_fuse : keep_fuse;
     if (rc != LBM_OK) return rc;
     if (nodes_per_thread) *nodes_per_thread = best_npt;
-    if (groups_per_cu) *groups_per_cu = best_gpc == 0 ? b->resident[npt_index(best_npt)] : best_gpc;
+    if (groups_per_cu) *groups_per_cu = best_gpc == 0 ? b->resident[shape_of(b, best_fuse)] : best_gpc;
     if (us_per_step) *us_per_step = 1e3 * (double)best / trials;
     return LBM_OK;
 }
@@ -902,9 +1064,12 @@ void lbm_batch_destroy(lbm_batch* b) {
     for (int k = 0; k < 3; ++k) {
         if (b->d_desc[k]) (void)hipFree(b->d_desc[k]);
         if (b->d_tiles[k]) (void)hipFree(b->d_tiles[k]);
+    }
+    for (int k = 0; k < 4; ++k) {
         if (b->d_xtab[k]) (void)hipFree(b->d_xtab[k]);
         if (b->d_run[k]) (void)hipFree(b->d_run[k]);
     }
+    if (b->d_lastcopy) (void)hipFree(b->d_lastcopy);
     if (b->d_blowup) (void)hipFree(b->d_blowup);
     if (b->d_active) (void)hipFree(b->d_active);
     if (b->d_retired) (void)hipFree(b->d_retired);

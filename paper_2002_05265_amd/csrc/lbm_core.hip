@@ -21,6 +21,7 @@
 #include "lbm.h"
 #include "lbm_cell.hpp"
 #include "lbm_internal.hpp"
+#include "lbm_step2.hpp"
 
 using namespace lbm;
 
@@ -137,20 +138,6 @@ __global__ __launch_bounds__(256) void k_step(const typename Store<PREC>::S* __r
     }
 }
 
-// Two steps per pass over memory (temporal blocking).  A block owns a strip of columns and `hs`
-// rows and walks down it RING rows at a time: the first step's post-collision values of the
-// strip plus one halo column on each side are kept in a ring of RING + 2 rows in LDS, and the
-// second step pulls from that ring and writes to memory.  Per two steps each population is read
-// from and written to memory once, against twice for two single steps; the halo columns and the
-// two rows above and below the strip are collided twice (by both strips that need them).  Every
-// node is computed by the same arithmetic as in k_step and the ring holds the values in the
-// storage type, so the result is bit-identical to two launches of k_step.
-//
-// A strip is 64 columns wide, so every output row segment is whole 256-byte lines; lane l takes
-// column x0 + l, and one wave collides the two halo columns of the pass's rows in an extra pass.
-// (A 62-column strip with the halo columns in lanes 0 and 63 saves that pass, but its stores
-// start mid-line and two strips write parts of the same lines: measured 0.6x as fast.)
-constexpr int kStripW = 64;
 
 // Strip height a new context starts with (ring of 8 rows), 0 for single steps.  Measured on
 // MI355X (CM, double shear layer): two steps per launch win in FP32 and FP64 from 512^2 up
@@ -173,95 +160,14 @@ __global__ __launch_bounds__(256) void k_step2(const typename Store<PREC>::S* __
                                                int* __restrict__ blowup, unsigned gsx, int hs) {
     using S = typename Store<PREC>::S;
     using R = typename Store<PREC>::R;
-    constexpr int NR = RING + 2;
-    constexpr int W = kStripW;
-    __shared__ S ring[9][NR][W + 2];
-    const int lane = (int)(threadIdx.x & 63u);
-    const int wave = (int)(threadIdx.x >> 6);
+    __shared__ S ring[9][RING + 2][kStripW + 2];
     // strips in hardware order (an XCD-banded order measured no faster: the strips' edge lines
     // are not what limits this kernel)
     const unsigned sy = blockIdx.x / gsx;
-    const int x0 = (int)(blockIdx.x - sy * gsx) * W;
+    const int x0 = (int)(blockIdx.x - sy * gsx) * kStripW;
     const int ys = (int)sy * hs;
-    const int ye = min(ys + hs, g.ny);
-    const int w = min(W, g.nx - x0);           // output columns of this strip
-    const int lc = lane + 1;   // this lane's ring column
-    const bool in1 = lane < w;   // the lane has a column of the strip
-
-    // first step at row a (ys - 1 <= a <= ye, unwrapped) and ring column col (column
-    // x0 - 1 + col, wrapped): the pull loads, then the collision into the ring
-    auto load = [&](int a, int col, R (&h)[9]) {
-        const int x = x0 - 1 + col;
-        const int yw = a < 0 ? a + g.ny : (a >= g.ny ? a - g.ny : a);
-        const int xw = x < 0 ? x + g.nx : (x >= g.nx ? x - g.nx : x);
-        pull_load(src, g.plane, neighbours(xw, yw, g.nx, g.ny), h);
-    };
-    auto finish = [&](int a, int col, R (&h)[9]) {
-        double rho_d;
-        const Macro<R> m = macro_of<S>(h, ref, rho_d);
-        flag_bad(!(rho_d > 0.0), blowup, step);
-        collide<MODEL>(h, m, ref, c, N);
-        const int slot = (a - ys + 1) % NR;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) ring[i][slot][col] = to_store<S>(h[i]);
-    };
-    // Rows of a pass starting at yb: wave v takes rows yb + 1 + v + 4 k, and wave 3 also the halo
-    // columns of rows yb + 1 .. (two lanes per row).  The loads of the next pass are
-    // issued before the second step of the current one, so their latency overlaps it.
-    R hn[RING / 4][9];
-    R hh[9];
-    auto prefetch = [&](int yb) {
-        const int top = min(yb + RING, ye);
-#pragma unroll
-        for (int k = 0; k < RING / 4; ++k) {
-            const int a = yb + 1 + wave + 4 * k;
-            if (a <= top && in1) load(a, lc, hn[k]);
-        }
-        if (wave == 3) {
-            const int a = yb + 1 + (lane >> 1);
-            if (a <= top) load(a, (lane & 1) ? w + 1 : 0, hh);
-        }
-    };
-
-    // rows ys - 1 and ys, their loads issued together with those of the first pass
-    {
-        R h[9];
-        const int a = ys - 1 + (wave < 2 ? wave : lane >> 1);
-        const int col = wave < 2 ? lc : ((lane & 1) ? w + 1 : 0);
-        const bool act = wave < 2 ? in1 : (wave == 2 && lane < 4);
-        if (act) load(a, col, h);
-        prefetch(ys);
-        if (act) finish(a, col, h);
-    }
-    for (int yb = ys; yb < ye; yb += RING) {
-        const int top = min(yb + RING, ye);   // first step of rows yb + 1 .. top
-#pragma unroll
-        for (int k = 0; k < RING / 4; ++k) {
-            const int a = yb + 1 + wave + 4 * k;
-            if (a <= top && in1) finish(a, lc, hn[k]);
-        }
-        if (wave == 3) {
-            const int a = yb + 1 + (lane >> 1);
-            if (a <= top) finish(a, (lane & 1) ? w + 1 : 0, hh);
-        }
-        __syncthreads();
-        if (yb + RING < ye) prefetch(yb + RING);
-#pragma unroll
-        for (int k = 0; k < RING / 4; ++k) {
-            const int y = yb + wave + 4 * k;
-            if (y < ye && in1) {
-                R h[9];
-#pragma unroll
-                for (int i = 0; i < 9; ++i) h[i] = R(ring[i][(y - cy(i) - ys + 1) % NR][lc - cx(i)]);
-                double rho_d;
-                const Macro<R> m = macro_of<S>(h, ref, rho_d);
-                flag_bad(!(rho_d > 0.0), blowup, step + 1);
-                collide<MODEL>(h, m, ref, c, N);
-                store_cell(dst, g.plane, (unsigned)y * (unsigned)g.nx + (unsigned)(x0 + lane), h);
-            }
-        }
-        __syncthreads();
-    }
+    strip_two_steps<RING, false, true>(ring, src, dst, g, ref, x0, ys, min(ys + hs, g.ny), step, blowup,
+                                       [&](R(&h)[9], const Macro<R>& m) { collide<MODEL>(h, m, ref, c, N); });
 }
 
 // Macroscopic fields of the state f(., n) (pulled from the post-collision copy) and per-block
@@ -418,7 +324,13 @@ template <int MODEL, int PREC>
 void launch_step2_t(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int ring, int hs, int src_copy) {
     switch (ring) {
         case 4: launch_step2_r<MODEL, PREC, 4>(ctx, c, hs, src_copy); break;
-        case 16: launch_step2_r<MODEL, PREC, 16>(ctx, c, hs, src_copy); break;
+        case 16:
+            // the ring must fit in the 160 KiB of LDS a workgroup can have
+            if constexpr (9 * 18 * (kStripW + 2) * sizeof(typename Store<PREC>::S) <= 160 * 1024)
+                launch_step2_r<MODEL, PREC, 16>(ctx, c, hs, src_copy);
+            else
+                launch_step2_r<MODEL, PREC, 8>(ctx, c, hs, src_copy);
+            break;
         default: launch_step2_r<MODEL, PREC, 8>(ctx, c, hs, src_copy); break;
     }
 }

@@ -3,9 +3,10 @@
 //
 // J_C comes from the reverse mode of the library's own collision (lbm_adjoint_cell.hpp): with the
 // adjoint seed mu = e_i, collide_adjoint returns J_C^T e_i, i.e. row i of J_C.  The eigenvalues of
-// each 9 x 9 complex M(k) are found by one thread: Householder reduction to upper Hessenberg form,
+// each 9 x 9 complex M(k) are found by one thread: Givens reduction to upper Hessenberg form,
 // then implicit single-shift QR sweeps (Wilkinson shift from the trailing 2 x 2 block, Givens
-// rotations chasing the bulge) with deflation of negligible subdiagonal entries.
+// rotations chasing the bulge) with deflation of negligible subdiagonal entries, the matrix held
+// in registers.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -77,128 +78,184 @@ __global__ void k_lsa_jacobian(const lbm_lsa_point* __restrict__ pts, double* __
     for (int j = 0; j < 9; ++j) J[(size_t)p * 81 + i * 9 + j] = hb[j];
 }
 
-// Eigenvalues of the 9 x 9 complex matrix H (overwritten).  Returns false if an eigenvalue did
-// not converge within the iteration limit.
-__device__ bool eig9(cplx (&H)[kQ][kQ], cplx (&lam)[kQ]) {
-    constexpr int n = kQ;
-    // Householder reduction to upper Hessenberg form: H <- P H P, P = I - 2 v v^H / |v|^2
-    for (int k = 0; k < n - 2; ++k) {
-        double xn2 = 0.0;
-        for (int i = k + 1; i < n; ++i) xn2 += cabs2(H[i][k]);
-        if (xn2 == 0.0) continue;
-        const double xn = sqrt(xn2);
-        const cplx x0 = H[k + 1][k];
-        const double a0 = cabs(x0);
-        const cplx phase = a0 > 0.0 ? cscale(x0, 1.0 / a0) : cplx{1.0, 0.0};
-        const cplx alpha = cscale(phase, -xn);
-        cplx v[kQ];
-        for (int i = 0; i < n; ++i) v[i] = {0.0, 0.0};
-        for (int i = k + 1; i < n; ++i) v[i] = H[i][k];
-        v[k + 1] = csub(v[k + 1], alpha);
-        double vn2 = 0.0;
-        for (int i = k + 1; i < n; ++i) vn2 += cabs2(v[i]);
-        if (vn2 == 0.0) continue;
-        const double s = 2.0 / vn2;
-        for (int j = k; j < n; ++j) {  // left: rows k+1.., w_j = v^H H[:, j]
-            cplx w = {0.0, 0.0};
-            for (int i = k + 1; i < n; ++i) w = cadd(w, cmul(cconj(v[i]), H[i][j]));
-            w = cscale(w, s);
-            for (int i = k + 1; i < n; ++i) H[i][j] = csub(H[i][j], cmul(v[i], w));
-        }
-        for (int i = 0; i < n; ++i) {  // right: columns k+1.., w_i = H[i, :] v
-            cplx w = {0.0, 0.0};
-            for (int j = k + 1; j < n; ++j) w = cadd(w, cmul(H[i][j], v[j]));
-            w = cscale(w, s);
-            for (int j = k + 1; j < n; ++j) H[i][j] = csub(H[i][j], cmul(w, cconj(v[j])));
-        }
-        for (int i = k + 2; i < n; ++i) H[i][k] = {0.0, 0.0};
+// Every loop of the eigenvalue solver has bounds known at compile time (the active block's end
+// HI is a template parameter, its start l a run-time value that predicates the rotations), so
+// the matrix stays in registers: with run-time bounds it was indexed dynamically and lived in
+// scratch memory, which bounded the kernel by scratch traffic.
+
+// Rotation G = [c s; -conj(s) c] (c real) with G (x, y)^T = (r, 0)^T.
+__device__ __forceinline__ void givens(cplx x, cplx y, double& c, cplx& sn) {
+    const double r = sqrt(cabs2(x) + cabs2(y));
+    if (r == 0.0) {
+        c = 1.0;
+        sn = {0.0, 0.0};
+        return;
     }
-    double hnorm = 0.0;
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) hnorm = fmax(hnorm, cabs(H[i][j]));
-    const double eps = 2.220446049250313e-16;
-    int hi = n - 1, its = 0;
-    while (hi >= 0) {
-        if (hi == 0) {
-            lam[0] = H[0][0];
-            break;
-        }
-        // start l of the unreduced block ending at hi
-        int l = hi;
-        while (l > 0) {
-            double sdiag = cabs(H[l - 1][l - 1]) + cabs(H[l][l]);
+    const double ax = cabs(x);
+    if (ax == 0.0) {
+        c = 0.0;
+        sn = cscale(cconj(y), 1.0 / cabs(y));
+    } else {
+        c = ax / r;
+        sn = cscale(cmul(cscale(x, 1.0 / ax), cconj(y)), 1.0 / r);
+    }
+}
+
+// H <- G H G^H with G acting on rows / columns p, p + 1; the row rotation is applied to columns
+// J0.. only (the entries left of J0 are zero in both rows), the column rotation to rows ..I1.
+template <int P, int J0, int I1>
+__device__ __forceinline__ void rotate(cplx (&H)[kQ][kQ], double c, cplx sn) {
+#pragma unroll
+    for (int jj = J0; jj < kQ; ++jj) {
+        const cplx a = H[P][jj], b = H[P + 1][jj];
+        H[P][jj] = cadd(cscale(a, c), cmul(sn, b));
+        H[P + 1][jj] = csub(cscale(b, c), cmul(cconj(sn), a));
+    }
+#pragma unroll
+    for (int i = 0; i <= I1; ++i) {
+        const cplx a = H[i][P], b = H[i][P + 1];
+        H[i][P] = cadd(cscale(a, c), cmul(b, cconj(sn)));
+        H[i][P + 1] = csub(cscale(b, c), cmul(a, sn));
+    }
+}
+
+// Reduction to upper Hessenberg form by Givens rotations: column K is cleared below its
+// subdiagonal from the bottom up, each rotation of rows I - 1, I applied as a similarity (a
+// rotation touches two rows and two columns, so few values are live beyond the matrix).
+template <int K, int I>
+__device__ __forceinline__ void hessenberg_col(cplx (&H)[kQ][kQ]) {
+    if constexpr (I >= K + 2) {
+        double c;
+        cplx sn;
+        givens(H[I - 1][K], H[I][K], c, sn);
+        rotate<I - 1, K, kQ - 1>(H, c, sn);
+        H[I][K] = {0.0, 0.0};
+        // keep the scheduler from interleaving rotations, which would hold two copies of the
+        // touched rows and columns and overflow the registers
+        __builtin_amdgcn_sched_barrier(0);
+        hessenberg_col<K, I - 1>(H);
+    }
+}
+
+// Implicit single-shift QR iterations on the unreduced block l..HI (l found each iteration)
+// until H[HI][HI-1] is negligible; then lam[HI] = H[HI][HI].  False if 90 iterations do not
+// suffice.
+template <int HI>
+__device__ __forceinline__ bool converge_last(cplx (&H)[kQ][kQ], cplx (&lam)[kQ], double hnorm) {
+    constexpr double eps = 2.220446049250313e-16;
+    for (int its = 0;; ++its) {
+        // start l of the unreduced block ending at HI: the last negligible subdiagonal entry
+        int l = 0;
+#pragma unroll
+        for (int k = HI; k >= 1; --k) {
+            double sdiag = cabs(H[k - 1][k - 1]) + cabs(H[k][k]);
             if (sdiag == 0.0) sdiag = hnorm;
-            if (cabs(H[l][l - 1]) <= 2.0 * eps * sdiag) break;
-            --l;
+            if (l == 0 && cabs(H[k][k - 1]) <= 2.0 * eps * sdiag) l = k;
         }
-        if (l > 0) H[l][l - 1] = {0.0, 0.0};
-        if (l == hi) {
-            lam[hi] = H[hi][hi];
-            --hi;
-            its = 0;
-            continue;
+#pragma unroll
+        for (int k = 1; k <= HI; ++k)
+            if (k == l) H[k][k - 1] = {0.0, 0.0};
+        if (l == HI) {
+            lam[HI] = H[HI][HI];
+            return true;
         }
-        if (++its > 90) return false;
-        // Wilkinson shift: eigenvalue of the trailing 2 x 2 block closer to H[hi][hi]
+        if (its >= 90) return false;
+        // Wilkinson shift: eigenvalue of the trailing 2 x 2 block closer to H[HI][HI]
         cplx mu;
-        if (its % 30 == 10 || its % 30 == 20) {  // exceptional shift
-            mu = cadd(H[hi][hi], cplx{0.75 * cabs(H[hi][hi - 1]), 0.0});
+        const int it1 = its + 1;
+        if (it1 % 30 == 10 || it1 % 30 == 20) {  // exceptional shift
+            mu = cadd(H[HI][HI], cplx{0.75 * cabs(H[HI][HI - 1]), 0.0});
         } else {
-            const cplx a = H[hi - 1][hi - 1], b = H[hi - 1][hi], c = H[hi][hi - 1], d = H[hi][hi];
+            const cplx a = H[HI - 1][HI - 1], b = H[HI - 1][HI], c = H[HI][HI - 1], d = H[HI][HI];
             const cplx half = cscale(csub(a, d), 0.5);
             const cplx disc = csqrt(cadd(cmul(half, half), cmul(b, c)));
             const cplx m1 = cadd(d, csub(half, disc)), m2 = cadd(d, cadd(half, disc));
             mu = cabs2(csub(m1, d)) <= cabs2(csub(m2, d)) ? m1 : m2;
         }
-        // implicit single-shift QR sweep on rows / columns l..hi
-        cplx x = csub(H[l][l], mu), y = H[l + 1][l];
-        for (int k = l; k < hi; ++k) {
-            const double r = sqrt(cabs2(x) + cabs2(y));
-            double c;
-            cplx sn;
-            if (r == 0.0) {
-                c = 1.0;
-                sn = {0.0, 0.0};
-            } else {
-                const double ax = cabs(x);
-                if (ax == 0.0) {
-                    c = 0.0;
-                    sn = cscale(cconj(y), 1.0 / cabs(y));
-                } else {
-                    c = ax / r;
-                    sn = cscale(cmul(cscale(x, 1.0 / ax), cconj(y)), 1.0 / r);
+        // first rotation from (H[l][l] - mu, H[l+1][l])
+        cplx x = {0.0, 0.0}, y = {0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < HI; ++k)
+            if (k == l) {
+                x = csub(H[k][k], mu);
+                y = H[k + 1][k];
+            }
+        // bulge chase over rows / columns l..HI.  The column rotations also touch the rows above
+        // l (the coupling to the block above): a similarity of the whole matrix, which keeps it
+        // block upper triangular, so no eigenvalue changes.
+#pragma unroll
+        for (int k = 0; k < HI; ++k) {
+            if (k >= l) {
+                double c;
+                cplx sn;
+                givens(x, y, c, sn);
+                // rows k, k+1: [c s; -conj(s) c]  (entries left of column k - 1 are zero)
+#pragma unroll
+                for (int jj = (k > 0 ? k - 1 : 0); jj <= HI; ++jj) {
+                    const cplx a = H[k][jj], b = H[k + 1][jj];
+                    H[k][jj] = cadd(cscale(a, c), cmul(sn, b));
+                    H[k + 1][jj] = csub(cscale(b, c), cmul(cconj(sn), a));
                 }
-            }
-            // rows k, k+1: [c s; -conj(s) c]
-            for (int j = (k > l ? k - 1 : l); j <= hi; ++j) {
-                const cplx a = H[k][j], b = H[k + 1][j];
-                H[k][j] = cadd(cscale(a, c), cmul(sn, b));
-                H[k + 1][j] = csub(cscale(b, c), cmul(cconj(sn), a));
-            }
-            // columns k, k+1 (similarity with the conjugate transpose)
-            const int iend = k + 2 < hi ? k + 2 : hi;
-            for (int i = l; i <= iend; ++i) {
-                const cplx a = H[i][k], b = H[i][k + 1];
-                H[i][k] = cadd(cscale(a, c), cmul(b, cconj(sn)));
-                H[i][k + 1] = csub(cscale(b, c), cmul(a, sn));
-            }
-            if (k < hi - 1) {
-                x = H[k + 1][k];
-                y = H[k + 2][k];
+                // columns k, k+1 (similarity with the conjugate transpose)
+#pragma unroll
+                for (int i = 0; i <= (k + 2 < HI ? k + 2 : HI); ++i) {
+                    const cplx a = H[i][k], b = H[i][k + 1];
+                    H[i][k] = cadd(cscale(a, c), cmul(b, cconj(sn)));
+                    H[i][k + 1] = csub(cscale(b, c), cmul(a, sn));
+                }
+                if (k < HI - 1) {
+                    x = H[k + 1][k];
+                    y = H[k + 2][k];
+                }
             }
         }
     }
-    return true;
 }
 
-// M(k) = diag(exp(-i xi . k)) J for wave number (kx, ky).
-__device__ void build_m(const double* __restrict__ J, double kx, double ky, cplx (&H)[kQ][kQ]) {
+// Eigenvalues of the 9 x 9 complex matrix H (overwritten).  Returns false if an eigenvalue did
+// not converge within the iteration limit.
+__device__ __forceinline__ bool eig9(cplx (&H)[kQ][kQ], cplx (&lam)[kQ]) {
+    hessenberg_col<0, kQ - 1>(H);
+    hessenberg_col<1, kQ - 1>(H);
+    hessenberg_col<2, kQ - 1>(H);
+    hessenberg_col<3, kQ - 1>(H);
+    hessenberg_col<4, kQ - 1>(H);
+    hessenberg_col<5, kQ - 1>(H);
+    hessenberg_col<6, kQ - 1>(H);
+    double hnorm = 0.0;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i)
+#pragma unroll
+        for (int jj = (i > 0 ? i - 1 : 0); jj < kQ; ++jj) hnorm = fmax(hnorm, cabs(H[i][jj]));
+    bool ok = converge_last<8>(H, lam, hnorm);
+    ok = ok && converge_last<7>(H, lam, hnorm);
+    ok = ok && converge_last<6>(H, lam, hnorm);
+    ok = ok && converge_last<5>(H, lam, hnorm);
+    ok = ok && converge_last<4>(H, lam, hnorm);
+    ok = ok && converge_last<3>(H, lam, hnorm);
+    ok = ok && converge_last<2>(H, lam, hnorm);
+    ok = ok && converge_last<1>(H, lam, hnorm);
+    lam[0] = H[0][0];
+    return ok;
+}
+
+// M(k) = diag(exp(-i xi . k)) J for wave number (kx, ky).  The nine phases are products of
+// exp(-i kx) and exp(-i ky) (or their conjugates): two sincos calls, made before any entry of
+// the matrix is live.
+__device__ __forceinline__ void build_m(const double* __restrict__ J, double kx, double ky, cplx (&H)[kQ][kQ]) {
+    double sx, cxk, sy, cyk;
+    sincos(kx, &sx, &cxk);
+    sincos(ky, &sy, &cyk);
+    const cplx ex = {cxk, -sx}, ey = {cyk, -sy};  // exp(-i kx), exp(-i ky)
+#pragma unroll
     for (int i = 0; i < kQ; ++i) {
-        double sn, cs;
-        sincos(-((double)cx(i) * kx + (double)cy(i) * ky), &sn, &cs);
+        const cplx px = cx(i) == 0 ? cplx{1.0, 0.0} : (cx(i) > 0 ? ex : cconj(ex));
+        const cplx py = cy(i) == 0 ? cplx{1.0, 0.0} : (cy(i) > 0 ? ey : cconj(ey));
+        const cplx ph = cmul(px, py);
+#pragma unroll
         for (int j = 0; j < kQ; ++j) {
             const double v = J[i * 9 + j];
-            H[i][j] = {cs * v, sn * v};
+            H[i][j] = {ph.re * v, ph.im * v};
         }
     }
 }
@@ -213,6 +270,7 @@ __global__ __launch_bounds__(64) void k_lsa_radius(const double* __restrict__ J,
     double r = NAN;
     if (eig9(H, lam)) {
         r = 0.0;
+#pragma unroll
         for (int m = 0; m < kQ; ++m) r = fmax(r, cabs(lam[m]));
     }
     radius[idx] = r;
@@ -225,6 +283,7 @@ __global__ __launch_bounds__(64) void k_lsa_eigenvalues(const double* __restrict
     cplx H[kQ][kQ], lam[kQ];
     build_m(J, kx[q], ky[q], H);
     const bool ok = eig9(H, lam);
+#pragma unroll
     for (int m = 0; m < kQ; ++m) {
         out[((size_t)q * kQ + m) * 2] = ok ? lam[m].re : NAN;
         out[((size_t)q * kQ + m) * 2 + 1] = ok ? lam[m].im : NAN;

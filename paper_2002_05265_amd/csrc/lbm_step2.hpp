@@ -1,0 +1,165 @@
+// Two time steps per pass over one strip of a grid (temporal blocking), shared by the plain
+// two-step kernel and the batched one.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lbm_cell.hpp"
+#include "lbm_internal.hpp"
+
+namespace lbm {
+
+// Two steps per pass over memory (temporal blocking).  A block owns a strip of columns and `hs`
+// rows and walks down it RING rows at a time: the first step's post-collision values of the
+// strip plus one halo column on each side are kept in a ring of RING + 2 rows in LDS, and the
+// second step pulls from that ring and writes to memory.  Per two steps each population is read
+// from and written to memory once, against twice for two single steps; the halo columns and the
+// two rows above and below the strip are collided twice (by both strips that need them).  Every
+// node is computed by the same arithmetic as in k_step and the ring holds the values in the
+// storage type, so the result is bit-identical to two launches of k_step.
+//
+// A strip is 64 columns wide, so every output row segment is whole 256-byte lines; lane l takes
+// column x0 + l, and one wave collides the two halo columns of the pass's rows in an extra pass.
+// (A 62-column strip with the halo columns in lanes 0 and 63 saves that pass, but its stores
+// start mid-line and two strips write parts of the same lines: measured 0.6x as fast.)
+#ifndef LBM_STRIP_W
+#define LBM_STRIP_W 64
+#endif
+constexpr int kStripW = LBM_STRIP_W;
+
+// Loads that bypass the CU's L1 (agent scope) and are served by the XCD's L2: what the batched
+// kernel's workgroups read was written by other workgroups of the same XCD during the launch.
+template <typename S>
+__device__ __forceinline__ S ld_l2(const S* p) {
+    if constexpr (sizeof(S) == 2) {
+        const unsigned short v = __hip_atomic_load(reinterpret_cast<const unsigned short*>(p), __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        return __builtin_bit_cast(S, v);
+    } else {
+        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// pull_load (f_i(x) = stored_i(x - xi_i)) through ld_l2.
+template <typename S, typename R>
+__device__ __forceinline__ void pull_load_l2(const S* __restrict__ src, long long plane, const Nbr& n, R (&h)[9]) {
+    constexpr unsigned E = sizeof(S);
+    const unsigned r0 = n.r0 * E, rm = n.rm * E, rp = n.rp * E;
+    const unsigned x0 = n.x * E, xm = n.xm * E, xp = n.xp * E;
+    h[0] = R(ld_l2(plane_at(src, plane, 0, r0 + x0)));
+    h[1] = R(ld_l2(plane_at(src, plane, 1, r0 + xm)));
+    h[2] = R(ld_l2(plane_at(src, plane, 2, rm + x0)));
+    h[3] = R(ld_l2(plane_at(src, plane, 3, r0 + xp)));
+    h[4] = R(ld_l2(plane_at(src, plane, 4, rp + x0)));
+    h[5] = R(ld_l2(plane_at(src, plane, 5, rm + xm)));
+    h[6] = R(ld_l2(plane_at(src, plane, 6, rm + xp)));
+    h[7] = R(ld_l2(plane_at(src, plane, 7, rp + xp)));
+    h[8] = R(ld_l2(plane_at(src, plane, 8, rp + xm)));
+}
+
+// Steps `step` and `step` + 1 of the strip of columns x0 .. x0 + kStripW - 1 and rows ys .. ye - 1
+// of grid g: pulls from src, writes to dst, collides with coll(h, m).  Called by all 256 threads
+// of a workgroup (it contains block barriers); ring is the workgroup's LDS ring.  VIA_L2 selects
+// L1-bypassing loads, NT streaming stores.  Blow-up records go to *blowup (steps step and
+// step + 1).
+template <int RING, bool VIA_L2, bool NT, typename S, typename R, typename Coll>
+__device__ __forceinline__ void strip_two_steps(S (&ring)[9][RING + 2][kStripW + 2], const S* __restrict__ src,
+                                                S* __restrict__ dst, const Geom& g, const Ref<R>& ref, int x0,
+                                                int ys, int ye, int step, int* __restrict__ blowup, Coll&& coll) {
+    constexpr int NR = RING + 2;
+    constexpr int W = kStripW;
+    constexpr int WPR = W / 64;        // waves per row of the strip
+    constexpr int RPW = 4 / WPR;       // rows the block covers at once
+    constexpr int KR = RING / RPW;     // rows per wave and pass
+    const int lane = (int)(threadIdx.x & 63u);
+    const int wave = (int)(threadIdx.x >> 6);
+    const int cg = wave % WPR, rl = wave / WPR;
+    const int w = min(W, g.nx - x0);           // output columns of this strip
+    const int col = cg * 64 + lane;            // this lane's column in the strip
+    const int lc = col + 1;                    // and in the ring
+    const bool in1 = col < w;
+
+    // first step at row a (ys - 1 <= a <= ye, unwrapped) and ring column cc (column
+    // x0 - 1 + cc, wrapped): the pull loads, then the collision into the ring
+    auto load = [&](int a, int cc, R (&h)[9]) {
+        const int x = x0 - 1 + cc;
+        const int yw = a < 0 ? a + g.ny : (a >= g.ny ? a - g.ny : a);
+        const int xw = x < 0 ? x + g.nx : (x >= g.nx ? x - g.nx : x);
+        if constexpr (VIA_L2)
+            pull_load_l2(src, g.plane, neighbours(xw, yw, g.nx, g.ny), h);
+        else
+            pull_load(src, g.plane, neighbours(xw, yw, g.nx, g.ny), h);
+    };
+    auto finish = [&](int a, int cc, R (&h)[9]) {
+        double rho_d;
+        const Macro<R> m = macro_of<S>(h, ref, rho_d);
+        flag_bad(!(rho_d > 0.0), blowup, step);
+        coll(h, m);
+        const int slot = (a - ys + 1) % NR;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) ring[i][slot][cc] = to_store<S>(h[i]);
+    };
+    // Rows of a pass starting at yb: wave v takes rows yb + 1 + rl + RPW k of its column group,
+    // and wave 3 also the halo columns of rows yb + 1 .. (two lanes per row).  The loads of the
+    // next pass are issued before the second step of the current one, so their latency overlaps
+    // it.
+    R hn[KR][9];
+    R hh[9];
+    auto prefetch = [&](int yb) {
+        const int top = min(yb + RING, ye);
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+            const int a = yb + 1 + rl + RPW * k;
+            if (a <= top && in1) load(a, lc, hn[k]);
+        }
+        if (wave == 3) {
+            const int a = yb + 1 + (lane >> 1);
+            if (a <= top) load(a, (lane & 1) ? w + 1 : 0, hh);
+        }
+    };
+
+    // rows ys - 1 and ys (row lanes 0 and 1) and their halo columns (wave 3), their loads issued
+    // together with those of the first pass
+    {
+        R h[9], hp[9];
+        const bool act = rl < 2 && in1;
+        const bool acth = wave == 3 && lane < 4;
+        const int ah = ys - 1 + (lane >> 1), ch = (lane & 1) ? w + 1 : 0;
+        if (act) load(ys - 1 + rl, lc, h);
+        if (acth) load(ah, ch, hp);
+        prefetch(ys);
+        if (act) finish(ys - 1 + rl, lc, h);
+        if (acth) finish(ah, ch, hp);
+    }
+    for (int yb = ys; yb < ye; yb += RING) {
+        const int top = min(yb + RING, ye);   // first step of rows yb + 1 .. top
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+            const int a = yb + 1 + rl + RPW * k;
+            if (a <= top && in1) finish(a, lc, hn[k]);
+        }
+        if (wave == 3) {
+            const int a = yb + 1 + (lane >> 1);
+            if (a <= top) finish(a, (lane & 1) ? w + 1 : 0, hh);
+        }
+        __syncthreads();
+        if (yb + RING < ye) prefetch(yb + RING);
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+            const int y = yb + rl + RPW * k;
+            if (y < ye && in1) {
+                R h[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) h[i] = R(ring[i][(y - cy(i) - ys + 1) % NR][lc - cx(i)]);
+                double rho_d;
+                const Macro<R> m = macro_of<S>(h, ref, rho_d);
+                flag_bad(!(rho_d > 0.0), blowup, step + 1);
+                coll(h, m);
+                store_cell<S, R, NT>(dst, g.plane, (unsigned)y * (unsigned)g.nx + (unsigned)(x0 + col), h);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace lbm

@@ -11,6 +11,7 @@ last step, and a run leaves the batch once it is classified.
 from __future__ import annotations
 
 import math
+import time
 
 import numpy as np
 import torch
@@ -70,11 +71,12 @@ def dsl_instances(models_presets, Ls, machs, M: float, reynolds: float = 3.0e4):
 
 def run_stability(instances, prec: str = "f64", check_every: int = 64, beta: float = 0.5,
                   radius_frac: float = 0.05, device="cuda:0", autotune: bool = True,
-                  criterion: str = "u2", field=None):
+                  criterion: str = "u2", field=None, progress_s: float = 0.0):
     """Classify every instance; returns (first_bad_step per instance (-1 = stable), seconds of GPU
     time, node updates performed).  criterion "u2" is the |u|^2 test above; "blowup" counts only
     a loss of positivity within the budget.  field(d) gives an instance's initial (rho, ux, uy);
-    the default is the convected vortex with beta and radius_frac."""
+    the default is the convected vortex with beta and radius_frac.  progress_s > 0 prints the step
+    and the number of live runs at most that often (host time)."""
     if field is None:
         fields = [vortex_field(d, beta, radius_frac) for d in instances]
     else:
@@ -96,6 +98,7 @@ def run_stability(instances, prec: str = "f64", check_every: int = 64, beta: flo
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         step, k_chunk = 0, 0
+        t_last = time.perf_counter()
         for nxt in check_schedule(budgets, check_every):
             k = nxt - step
             updates += (active.to(torch.float64) * cells).sum() * k
@@ -112,9 +115,13 @@ def run_stability(instances, prec: str = "f64", check_every: int = 64, beta: flo
             b.set_active(active)
             k_chunk += 1
             if k_chunk % 16 == 0:
-                if not bool(active.any()):
+                live_n = int(active.sum())
+                if live_n == 0:
                     break
                 b.rebalance()  # retired runs leave the per-XCD work lists
+                if progress_s > 0 and time.perf_counter() - t_last > progress_s:
+                    t_last = time.perf_counter()
+                    print(f"stability: step {step}, {live_n} of {n} runs live", flush=True)
         e1.record()
         _, blow = b.status()
         sec = e0.elapsed_time(e1) * 1e-3

@@ -1,5 +1,6 @@
 """Parity at the benchmark's full size and launch configuration (4096 x 4096 double shear
-layer, the same Sim / lbm_step path bench.py times), on sampled nodes.
+layer, the same Sim / lbm_step path bench.py times: a new context's default of two steps per
+launch, then one single step), on sampled nodes.
 
 After k steps a node depends only on nodes within distance k (one lattice link per step), so
 the oracle recomputes a sampled node exactly from a (2k + 3)^2 patch of the analytic initial
@@ -18,7 +19,7 @@ from paper_2002_05265_amd.sim import Sim
 pytestmark = pytest.mark.gpu
 
 N = 4096
-STEPS = 3
+STEPS = 5
 
 
 def sample_nodes(rng, n, count=48):
@@ -50,6 +51,7 @@ def test_fullsize_sampled(gpu, prec, tol):
     for model in inputs.MODEL_NAMES:
         print(f"full size {prec} {model}", flush=True)
         sim = Sim(*fields, prec=prec, eq_order=4, device=gpu)
+        assert sim.fusion(model)[0] > 0  # the two-step kernel is the one timed at this size
         t0 = sim.totals()
         sim.step(model, omega, STEPS)
         state = sim.state()
