@@ -24,7 +24,8 @@ PROFILE_DIR = os.path.join(ROOT, "profiles")
 # the sources the plain step kernel is compiled from: a measured traffic figure is reported only
 # while these are unchanged since the counters were taken
 STEP_SOURCES = ("paper_2002_05265_amd/csrc/lbm_core.hip", "paper_2002_05265_amd/csrc/lbm_cell.hpp",
-                "paper_2002_05265_amd/csrc/lbm_internal.hpp", "paper_2002_05265_amd/build.py")
+                "paper_2002_05265_amd/csrc/lbm_internal.hpp", "paper_2002_05265_amd/csrc/lbm_step2.hpp",
+                "paper_2002_05265_amd/build.py")
 MODEL_ORDER = ("BGK", "RM", "HM", "CM", "CHM", "K", "PR", "RR")
 PREC_CODE = {"f64": 0, "f32": 1, "f16": 2}
 

@@ -118,9 +118,19 @@ __device__ __forceinline__ void strip_two_steps(S (&ring)[9][RING + 2][kStripW +
         }
     };
 
-    // rows ys - 1 and ys (row lanes 0 and 1) and their halo columns (wave 3), their loads issued
-    // together with those of the first pass
-    {
+    // rows ys - 1 and ys (row lanes 0 and 1) and their halo columns, their loads issued together
+    // with those of the first pass.  With one wave per row, wave 2 takes the four halo nodes and
+    // every wave makes one collision call (the kernel stays one collision shorter); with two,
+    // every wave has a row and wave 3 takes the halo nodes as well.
+    if constexpr (WPR == 1) {
+        R h[9];
+        const int a = ys - 1 + (wave < 2 ? wave : lane >> 1);
+        const int cc = wave < 2 ? lc : ((lane & 1) ? w + 1 : 0);
+        const bool act = wave < 2 ? in1 : (wave == 2 && lane < 4);
+        if (act) load(a, cc, h);
+        prefetch(ys);
+        if (act) finish(a, cc, h);
+    } else {
         R h[9], hp[9];
         const bool act = rl < 2 && in1;
         const bool acth = wave == 3 && lane < 4;
