@@ -517,7 +517,9 @@ def extras_trace_summary(out_root: str, command: str):
     lines = ["# All kernels of a bench run with the extra workloads: kernel trace", "",
              "Command (from the repository root):", "", "```", command, "```", "",
              "The batched kernel is launched cooperatively; the profiler may crash on its own exit after",
-             "the program has finished, with its result files complete.", "",
+             "the program has finished, with its result files complete. The batched launch shapes (one or",
+             "two steps per pass) are autotuned inside the run, so a profiled run may pick other shapes than",
+             "an unprofiled one.", "",
              "| kernel | calls | total ms | average us | share % |", "|---|---|---|---|---|"]
     for r in stats[:40]:
         name = r["Name"].replace("(anonymous namespace)::", "").replace("void ", "", 1).split("(")[0][:80]
