@@ -66,6 +66,23 @@ def measured_traffic(model: str, prec: str):
     return None if rec is None else rec["hbm_bytes"]
 
 
+def measured_valu_busy(model: str, prec: str):
+    """Fraction of the vector-ALU issue capacity the step kernel used (rocprofv3 VALUBusy) from the
+    committed counter summary, or None when there is none for this kernel or its sources changed
+    since it was taken."""
+    path = os.path.join(PROFILE_DIR, f"k_step2_{prec}_dsl4096_counters.md")
+    try:
+        with open(path) as fh:
+            text = fh.read()
+        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if blob.get("step_source_hash") != step_source_hash():
+        return None
+    rec = blob.get("per_launch", {}).get(model)
+    return None if rec is None or rec.get("valu_busy") is None else rec["valu_busy"]
+
+
 def cpu_baseline(models, budget_s: float = 16.0):
     """The oracle (single-threaded FP64) on a bounded sample: 256 x 256 double shear layer,
     each model run for whole steps until its share of the time budget is used."""
@@ -472,13 +489,15 @@ def profile_summary(out_root: str, prec: str, n: int, commands: dict):
     cfetch = _csv_rows(_find_csv(os.path.join(out_root, "rp_copy_fetch"), "counter_collection.csv"))
     cwrite = _csv_rows(_find_csv(os.path.join(out_root, "rp_copy_write"), "counter_collection.csv"))
     copy_key = "copyBuffer"  # the runtime's device-to-device copy kernel behind the 1 GiB copy
+    valu_dir = os.path.join(out_root, "rp_valu")
+    valu = _csv_rows(_find_csv(valu_dir, "counter_collection.csv")) if os.path.isdir(valu_dir) else []
     cf, _ = _per_dispatch(cfetch, copy_key)
     cw, _ = _per_dispatch(cwrite, copy_key)
     gib_kib = (1 << 30) / 1024
     fscale, wscale = gib_kib / cf, gib_kib / cw
     per_launch = {}
-    rows = ["| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) | / algorithmic |",
-            "|---|---|---|---|---|---|"]
+    rows = ["| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) | / algorithmic | VALUBusy % |",
+            "|---|---|---|---|---|---|---|"]
     for m in MODEL_ORDER:
         # the first kernel of the model found (two-step before single-step) is the one reported
         for label, key in step_kernel_keys(m, prec):
@@ -487,15 +506,21 @@ def profile_summary(out_root: str, prec: str, n: int, commands: dict):
             if f_kib is None or w_kib is None:
                 continue
             hbm = f_kib * 1024 * fscale + w_kib * 1024 * wscale
-            rows.append(f"| {label}<{m}, {prec}> | {nf} | {f_kib:.1f} | {w_kib:.1f} | {hbm:.4g} | {hbm / alg:.4f} |")
+            vb, _ = _per_dispatch(valu, key)
+            vtxt = "" if vb is None else f"{vb:.1f}"
+            rows.append(f"| {label}<{m}, {prec}> | {nf} | {f_kib:.1f} | {w_kib:.1f} | {hbm:.4g} | {hbm / alg:.4f} | {vtxt} |")
             per_launch.setdefault(m, {"kernel": label, "fetch_kib": round(f_kib, 1), "write_kib": round(w_kib, 1),
-                                      "hbm_bytes": int(round(hbm)), "vs_algorithmic": round(hbm / alg, 4)})
+                                      "hbm_bytes": int(round(hbm)), "vs_algorithmic": round(hbm / alg, 4),
+                                      "valu_busy": None if vb is None else round(vb / 100.0, 4)})
     blob = {"step_source_hash": step_source_hash(), "prec": prec, "n": n, "algorithmic_bytes": alg,
             "copy_probe_kib": {"fetch": round(cf, 1), "write": round(cw, 1), "true": gib_kib},
             "scale": {"fetch": round(fscale, 4), "write": round(wscale, 4)}, "per_launch": per_launch}
     text = [f"# k_step2 / k_step ({prec}, {n}x{n} double shear layer): HBM counters", "",
             "Commands (each counter in a run of its own):", "", "```", commands["fetch"], commands["write"],
-            commands["copy_fetch"], commands["copy_write"], "```", "",
+            commands["copy_fetch"], commands["copy_write"], commands["valu"], "```", "",
+            "VALUBusy is rocprofv3's derived counter 100 * SQ_ACTIVE_INST_VALU / CUs / GRBM_GUI_ACTIVE: the "
+            "share of the SIMDs' vector-ALU issue time in use (100 = every SIMD issues a VALU instruction "
+            "every cycle it can).", "",
             "Calibration: a plain device copy of 1 GiB (torch, same box) reads "
             f"{cf:.1f} KiB of FETCH_SIZE and {cw:.1f} KiB of WRITE_SIZE per dispatch against "
             f"{gib_kib:.0f} KiB moved each way, so FETCH_SIZE is scaled by {fscale:.4f} and "
@@ -543,6 +568,8 @@ PROFILE_COMMANDS = {
                   "python bench.py --copy-probe",
     "copy_write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/rp_copy_write -o copy -- "
                   "python bench.py --copy-probe",
+    "valu": f"rocprofv3 --pmc VALUBusy --output-format csv -d gpurun_out/rp_valu -o bench -- "
+            f"python bench.py {PROFILE_ARGS}",
 }
 
 
@@ -646,6 +673,7 @@ def main():
     launch_us = per_model[dominant]["us_per_step"] * spl
     achieved = cells * bpc / (launch_us * 1e-6) / 1e9
     traffic = measured_traffic(dominant, args.prec) if n == 4096 else None
+    valu_busy = measured_valu_busy(dominant, args.prec) if n == 4096 else None
     kname = "k_step2" if spl == 2 else "k_step"
     line = {
         "metric": "MLUPS per collision model at 4096^2 FP32 + % HBM roofline; adjoint/batched vs plain",
@@ -674,6 +702,7 @@ def main():
                      "single_step_equivalent_gbs": round(achieved * spl, 1),
                      "measured_frac": (None if traffic is None else
                                        round(traffic / (launch_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)),
+                     "valu_busy": valu_busy,
                      "stream_only_gbs": round(cells * bpc / (stream_launch_us * 1e-6) / 1e9, 1),
                      "frac_of_stream_only": round(stream_launch_us / launch_us, 4)},
         "single_step": single,
