@@ -90,12 +90,14 @@ __device__ __forceinline__ void strip_two_steps(S (&ring)[9][RING + 2][kStripW +
         else
             pull_load(src, g.plane, neighbours(xw, yw, g.nx, g.ny), h);
     };
-    auto finish = [&](int a, int cc, R (&h)[9]) {
+    // ring slot of row a is (a - ys + 1) mod NR; within a pass it is reached from the pass's slot
+    // base sb = (yb - ys + 1) mod NR by an offset in [-1, NR), so one conditional wrap suffices
+    auto wrap = [](int t) { return t < 0 ? t + NR : (t >= NR ? t - NR : t); };
+    auto finish = [&](int slot, int cc, R (&h)[9]) {
         double rho_d;
         const Macro<R> m = macro_of<S>(h, ref, rho_d);
         flag_bad(!(rho_d > 0.0), blowup, step);
         coll(h, m);
-        const int slot = (a - ys + 1) % NR;
 #pragma unroll
         for (int i = 0; i < 9; ++i) ring[i][slot][cc] = to_store<S>(h[i]);
     };
@@ -122,35 +124,37 @@ __device__ __forceinline__ void strip_two_steps(S (&ring)[9][RING + 2][kStripW +
     // with those of the first pass.  With one wave per row, wave 2 takes the four halo nodes and
     // every wave makes one collision call (the kernel stays one collision shorter); with two,
     // every wave has a row and wave 3 takes the halo nodes as well.
+    // (rows ys - 1 and ys sit in slots 0 and 1)
     if constexpr (WPR == 1) {
         R h[9];
-        const int a = ys - 1 + (wave < 2 ? wave : lane >> 1);
+        const int r = wave < 2 ? wave : lane >> 1;
         const int cc = wave < 2 ? lc : ((lane & 1) ? w + 1 : 0);
         const bool act = wave < 2 ? in1 : (wave == 2 && lane < 4);
-        if (act) load(a, cc, h);
+        if (act) load(ys - 1 + r, cc, h);
         prefetch(ys);
-        if (act) finish(a, cc, h);
+        if (act) finish(r, cc, h);
     } else {
         R h[9], hp[9];
         const bool act = rl < 2 && in1;
         const bool acth = wave == 3 && lane < 4;
-        const int ah = ys - 1 + (lane >> 1), ch = (lane & 1) ? w + 1 : 0;
+        const int rh = lane >> 1, ch = (lane & 1) ? w + 1 : 0;
         if (act) load(ys - 1 + rl, lc, h);
-        if (acth) load(ah, ch, hp);
+        if (acth) load(ys - 1 + rh, ch, hp);
         prefetch(ys);
-        if (act) finish(ys - 1 + rl, lc, h);
-        if (acth) finish(ah, ch, hp);
+        if (act) finish(rl, lc, h);
+        if (acth) finish(rh, ch, hp);
     }
     for (int yb = ys; yb < ye; yb += RING) {
         const int top = min(yb + RING, ye);   // first step of rows yb + 1 .. top
+        const int sb = (yb - ys + 1) % NR;    // slot of row yb (wave-uniform)
 #pragma unroll
         for (int k = 0; k < KR; ++k) {
             const int a = yb + 1 + rl + RPW * k;
-            if (a <= top && in1) finish(a, lc, hn[k]);
+            if (a <= top && in1) finish(wrap(sb + 1 + rl + RPW * k), lc, hn[k]);
         }
         if (wave == 3) {
             const int a = yb + 1 + (lane >> 1);
-            if (a <= top) finish(a, (lane & 1) ? w + 1 : 0, hh);
+            if (a <= top) finish(wrap(sb + 1 + (lane >> 1)), (lane & 1) ? w + 1 : 0, hh);
         }
         __syncthreads();
         if (yb + RING < ye) prefetch(yb + RING);
@@ -158,9 +162,10 @@ __device__ __forceinline__ void strip_two_steps(S (&ring)[9][RING + 2][kStripW +
         for (int k = 0; k < KR; ++k) {
             const int y = yb + rl + RPW * k;
             if (y < ye && in1) {
+                const int s0 = sb + rl + RPW * k;  // slot of row y, before wrapping
                 R h[9];
 #pragma unroll
-                for (int i = 0; i < 9; ++i) h[i] = R(ring[i][(y - cy(i) - ys + 1) % NR][lc - cx(i)]);
+                for (int i = 0; i < 9; ++i) h[i] = R(ring[i][wrap(s0 - cy(i))][lc - cx(i)]);
                 double rho_d;
                 const Macro<R> m = macro_of<S>(h, ref, rho_d);
                 flag_bad(!(rho_d > 0.0), blowup, step + 1);
