@@ -296,9 +296,15 @@ def lsa_domain(n: int = 128):
     phis = list(np.linspace(0.0, math.pi / 4, 5))
     table, _, sec = lsa.stability_domain(mp, nus, machs, phis, n=n)
     mats = len(mp) * len(nus) * len(machs) * len(phis) * n * n
+    # the BGK discrete-velocity Boltzmann equation (Section 3c): largest stable Ma on a 0.005 grid,
+    # against sqrt(3) - 1 = 0.732
+    dm = [round(0.005 * k, 3) for k in range(1, 200)]
+    dvbe = {f"N{N}-phi{phi:.3f}": lsa.dvbe_critical_mach(N, phi, dm)
+            for N, phi in ((2, 0.0), (2, math.pi / 8), (2, math.pi / 4), (4, 0.0), (4, math.pi / 4))}
     return {"workload": f"9x9 complex eigenproblems, {len(mp) * len(nus) * len(machs) * len(phis)} flows x {n}^2 "
                         "wave numbers, FP64", "seconds": round(sec, 3), "matrices_per_s": round(mats / sec, 1),
-            "nu": nus, "max_stable_mach": {f"{m}-{p}": [table[(m, p, nu)] for nu in nus] for m, p in mp}}
+            "nu": nus, "max_stable_mach": {f"{m}-{p}": [table[(m, p, nu)] for nu in nus] for m, p in mp},
+            "dvbe_max_stable_mach": dvbe}
 
 
 def precision_errors(n: int = 4096, steps: int = 5000, models=("CM", "K")):

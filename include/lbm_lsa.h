@@ -56,6 +56,20 @@ int lbm_lsa_eigenvalues(const lbm_lsa_point* pt, const double* kx, const double*
 int lbm_lsa_radius(const lbm_lsa_point* pts, int npts, const double* kx, const double* ky, int nk,
                    double* radius, void* hip_stream);
 
+/* Linear stability of the discrete-velocity Boltzmann equation with BGK collisions (Section 3c,
+ * Appendix A, eq. EigenvaluePbContinuous): about the same base flows, a plane wave
+ * A exp(i (k . x - omega t)) obeys M^C(k) A = omega A with
+ *     M^C(k) = diag(xi_i . k) + i J^C,   J^C = -(I - F) / tau,   F = d f^eq_N / d f at f^eq_N(1, U),
+ * (F is taken from the library's BGK collision at omega = 1, whose post-collision state is f^eq),
+ * and the wave grows when Im(omega) > 0.
+ *   pts      host, npts points (only eq_order, ux, uy are used)
+ *   tau      relaxation time > 0 (the growth rates scale with it; stability does not depend on it)
+ *   kx, ky   device, nk doubles each
+ *   growth   device, npts * nk doubles, point-major: max_m Im(omega_m(k)) (NaN where the
+ *            eigenvalue iteration did not converge) */
+int lbm_lsa_dvbe_growth(const lbm_lsa_point* pts, int npts, double tau, const double* kx, const double* ky,
+                        int nk, double* growth, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,7 +32,7 @@ EXPORTS = (
     "lbm_state_bytes", "lbm_adjoint_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_raw",
     "lbm_step_raw_many", "lbm_adjoint_many", "lbm_adjoint_flush",
     "lbm_adjoint_seed_velocity_l2", "lbm_adjoint_step", "lbm_eq_vjp",
-    "lbm_lsa_jacobian", "lbm_lsa_eigenvalues", "lbm_lsa_radius",
+    "lbm_lsa_jacobian", "lbm_lsa_eigenvalues", "lbm_lsa_radius", "lbm_lsa_dvbe_growth",
 )
 
 
@@ -89,6 +89,7 @@ def _declare(L: ctypes.CDLL):
         "lbm_lsa_jacobian": (_i, [_vp, _i, _vp, _vp]),
         "lbm_lsa_eigenvalues": (_i, [_vp, _vp, _vp, _i, _vp, _vp]),
         "lbm_lsa_radius": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp]),
+        "lbm_lsa_dvbe_growth": (_i, [_vp, _i, _d, _vp, _vp, _i, _vp, _vp]),
         "lbm_batch_set_launch": (_i, [_vp, _i, _i]),
         "lbm_batch_set_fusion": (_i, [_vp, _i]),
         "lbm_batch_get_fusion": (_i, [_vp, ctypes.POINTER(_i)]),
@@ -370,3 +371,8 @@ def lbm_lsa_eigenvalues(points: ctypes.Array, kx: int, ky: int, nk: int, lam: in
 
 def lbm_lsa_radius(points: ctypes.Array, kx: int, ky: int, nk: int, radius: int, stream=None):
     _check(lib().lbm_lsa_radius(ctypes.cast(points, _vp), len(points), kx, ky, nk, radius, stream), "lbm_lsa_radius")
+
+
+def lbm_lsa_dvbe_growth(points: ctypes.Array, tau: float, kx: int, ky: int, nk: int, growth: int, stream=None):
+    _check(lib().lbm_lsa_dvbe_growth(ctypes.cast(points, _vp), len(points), float(tau), kx, ky, nk, growth, stream),
+           "lbm_lsa_dvbe_growth")

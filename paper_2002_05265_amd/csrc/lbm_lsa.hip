@@ -290,6 +290,39 @@ __global__ __launch_bounds__(64) void k_lsa_eigenvalues(const double* __restrict
     }
 }
 
+// M^C(k) = diag(xi . k) + i J^C, J^C = -(I - F) / tau, for the discrete-velocity Boltzmann
+// equation with BGK collisions; F = d f^eq / d f at the base flow (the Jacobian of the BGK
+// collision at omega = 1, whose post-collision state is f^eq).
+__device__ __forceinline__ void build_dvbe(const double* __restrict__ F, double inv_tau, double kx, double ky,
+                                           cplx (&H)[kQ][kQ]) {
+#pragma unroll
+    for (int i = 0; i < kQ; ++i)
+#pragma unroll
+        for (int j = 0; j < kQ; ++j) {
+            const double re = i == j ? (double)cx(i) * kx + (double)cy(i) * ky : 0.0;
+            H[i][j] = {re, -inv_tau * ((i == j ? 1.0 : 0.0) - F[i * 9 + j])};
+        }
+}
+
+// Largest growth rate max_m Im(omega_m) of a plane wave exp(i (k . x - omega t)) of the DVBE,
+// omega the eigenvalues of M^C(k), for every (point, wave number) pair.
+__global__ __launch_bounds__(64) void k_lsa_dvbe(const double* __restrict__ F, int npts, double inv_tau,
+                                                 const double* __restrict__ kx, const double* __restrict__ ky,
+                                                 int nk, double* __restrict__ growth) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)npts * nk) return;
+    const int p = (int)(idx / nk), q = (int)(idx - (long long)p * nk);
+    cplx H[kQ][kQ], lam[kQ];
+    build_dvbe(F + (size_t)p * 81, inv_tau, kx[q], ky[q], H);
+    double g = NAN;
+    if (eig9(H, lam)) {
+        g = -INFINITY;
+#pragma unroll
+        for (int m = 0; m < kQ; ++m) g = fmax(g, lam[m].im);
+    }
+    growth[idx] = g;
+}
+
 int check_points(const lbm_lsa_point* pts, int npts) {
     if (!pts || npts < 1) return set_error(LBM_EINVAL, "need npts >= 1 points");
     for (int p = 0; p < npts; ++p) {
@@ -369,6 +402,36 @@ int lbm_lsa_radius(const lbm_lsa_point* pts, int npts, const double* kx, const d
     }
     if (rc == LBM_OK) rc = check_hip(hipStreamSynchronize(s), "synchronise");
     if (d_J) (void)hipFree(d_J);
+    return rc;
+}
+
+int lbm_lsa_dvbe_growth(const lbm_lsa_point* pts, int npts, double tau, const double* kx, const double* ky,
+                        int nk, double* growth, void* hip_stream) {
+    if (!pts || npts < 1) return set_error(LBM_EINVAL, "need npts >= 1 points");
+    if (!(tau > 0.0)) return set_error(LBM_EINVAL, "tau %g must be > 0", tau);
+    if (!kx || !ky || !growth) return set_error(LBM_EINVAL, "NULL pointer");
+    if (nk < 1) return set_error(LBM_EINVAL, "nk %d < 1", nk);
+    const long long total = (long long)npts * nk;
+    if (total >= (1LL << 31)) return set_error(LBM_EINVAL, "npts * nk = %lld too large (one launch)", total);
+    // F = d f^eq / d f: the BGK collision's Jacobian at omega = 1, at each point's flow and order
+    std::vector<lbm_lsa_point> bgk(pts, pts + npts);
+    for (auto& q : bgk) {
+        q.model = LBM_BGK;
+        for (int k = 0; k < LBM_NOMEGA; ++k) q.omega[k] = 1.0;
+    }
+    int rc = check_points(bgk.data(), npts);
+    if (rc != LBM_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    double* d_F = nullptr;
+    rc = check_hip(hipMalloc(&d_F, sizeof(double) * 81 * (size_t)npts), "hipMalloc(F)");
+    if (rc == LBM_OK) rc = jacobians(bgk.data(), npts, d_F, s);
+    if (rc == LBM_OK) {
+        hipLaunchKernelGGL(k_lsa_dvbe, dim3((unsigned)((total + 63) / 64)), dim3(64), 0, s, d_F, npts, 1.0 / tau, kx,
+                           ky, nk, growth);
+        rc = check_hip(hipGetLastError(), "DVBE launch");
+    }
+    if (rc == LBM_OK) rc = check_hip(hipStreamSynchronize(s), "synchronise");
+    if (d_F) (void)hipFree(d_F);
     return rc;
 }
 

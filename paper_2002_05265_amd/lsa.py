@@ -60,6 +60,40 @@ def radius(points, kx: torch.Tensor, ky: torch.Tensor, chunk: int = 1 << 26) -> 
     return out
 
 
+def dvbe_growth(points, kx: torch.Tensor, ky: torch.Tensor, tau: float = 1.0, chunk: int = 1 << 26) -> torch.Tensor:
+    """Largest growth rate max Im(omega) (npts, nk) of the BGK discrete-velocity Boltzmann equation
+    about each point's flow (only eq_order, ux, uy are used), for every wave number."""
+    nk = kx.numel()
+    out = torch.empty((len(points), nk), dtype=torch.float64, device=kx.device)
+    per = max(1, chunk // nk)
+    stream = torch.cuda.current_stream(kx.device).cuda_stream
+    for a in range(0, len(points), per):
+        part = points[a:a + per]
+        B.lbm_lsa_dvbe_growth(B.make_lsa_points(part), tau, kx.data_ptr(), ky.data_ptr(), nk,
+                              out[a:a + len(part)].data_ptr(), stream)
+    return out
+
+
+def dvbe_critical_mach(eq_order: int, phi: float, machs, kmax: float = 100.0, n: int = 64, tol: float = 1e-10,
+                       device="cuda:0") -> float:
+    """Largest Ma of `machs` below which (every smaller Ma included) the DVBE is linearly stable in
+    flow direction phi: no wave number of a polar grid (n radii from 1e-2 to kmax, log-spaced, x n
+    angles) grows faster than tol.  The growth rate is homogeneous in (k, 1/tau), so tau = 1."""
+    r = torch.logspace(-2.0, math.log10(kmax), n, dtype=torch.float64, device=device)
+    t = torch.arange(n, dtype=torch.float64, device=device) * (2.0 * math.pi / n)
+    rr, tt = torch.meshgrid(r, t, indexing="ij")
+    kx = (rr * torch.cos(tt)).reshape(-1).contiguous()
+    ky = (rr * torch.sin(tt)).reshape(-1).contiguous()
+    pts = [point("BGK", 0.0, ma, phi, "SRT", eq_order, omega=[1.0] * 5) for ma in machs]
+    g = torch.nan_to_num(dvbe_growth(pts, kx, ky), nan=math.inf).amax(dim=1).cpu().numpy()
+    best = 0.0
+    for ma, gm in zip(machs, g):
+        if gm > tol:
+            break
+        best = ma
+    return best
+
+
 def stability_domain(models_presets, nus, machs, phis, n: int = 64, tol: float = 1e-10, eq_order: int = 4,
                      device="cuda:0"):
     """Largest stable Ma on the grid `machs` per (model, preset, nu): every Ma up to it is stable for

@@ -94,3 +94,34 @@ def test_stability_domain(gpu):
     mac = math.sqrt(3.0) - 1.0
     above = [c for c, ma in enumerate(machs) if ma > mac]
     assert not (R[:, :, above, :] <= 1.0 + 1e-10).all(axis=3).any()
+
+
+def test_dvbe_growth_matches_numpy(gpu):
+    rng = np.random.default_rng(33)
+    pts, taus = [], []
+    for k in range(12):
+        pts.append(lsa.point("BGK", 0.0, float(rng.uniform(0, 1.0)), float(rng.uniform(0, 2 * math.pi)),
+                             eq_order=int(rng.choice([2, 3, 4])), omega=[1.0] * 5))
+    kx = torch.tensor(rng.uniform(-4, 4, 24), device=gpu)
+    ky = torch.tensor(rng.uniform(-4, 4, 24), device=gpu)
+    for tau in (1.0, 0.3):
+        g = lsa.dvbe_growth(pts, kx, ky, tau=tau).cpu().numpy()
+        worst = 0.0
+        for p, pt in enumerate(pts):
+            for q in range(24):
+                M = oracle.dvbe_matrix(pt["eq_order"], tau, pt["ux"], pt["uy"], float(kx[q]), float(ky[q]))
+                ref = float(np.max(np.linalg.eigvals(M).imag))
+                worst = max(worst, abs(g[p, q] - ref) / max(1.0, abs(ref)))
+        print(f"tau {tau}: DVBE growth vs numpy {worst:.2e}", flush=True)
+        assert worst < 1e-10
+
+
+def test_dvbe_critical_mach(gpu):
+    # Section 3c: the BGK DVBE becomes linearly unstable at Ma_c = sqrt(3) - 1 (second-order
+    # equilibrium in every direction, the extended one along a lattice axis)
+    mac = math.sqrt(3.0) - 1.0
+    machs = [round(0.01 * k, 2) for k in range(1, 100)]
+    for N, phi in ((2, 0.0), (2, math.pi / 4), (2, 0.3), (4, 0.0)):
+        got = lsa.dvbe_critical_mach(N, phi, machs, device=gpu)
+        print(f"N {N} phi {phi:.3f}: largest stable Ma {got}", flush=True)
+        assert abs(got - mac) <= 0.011, (N, phi, got)
