@@ -83,31 +83,26 @@ def measured_valu_busy(model: str, prec: str):
     return None if rec is None or rec.get("valu_busy") is None else rec["valu_busy"]
 
 
-def cpu_baseline(models, budget_s: float = 16.0):
-    """The oracle (single-threaded FP64) on a bounded sample: 256 x 256 double shear layer,
-    each model run for whole steps until its share of the time budget is used."""
+def cpu_baseline(models, n: int = 4096, rows: int = 1024, steps: int = 1):
+    """The oracle (single-threaded FP64 C) on a bounded sample of the bench workload: `rows` full
+    rows (4096 nodes wide) of the 4096 x 4096 double shear layer with the bench's rates, run as a
+    periodic band, `steps` step(s) per model (about 15 s of one core)."""
     import oracle
     from paper_2002_05265_amd import inputs
 
-    n = 256
-    rho, ux, uy = inputs.dsl_fields(n, n, 0.1)
+    rho, ux, uy = (np.ascontiguousarray(a[:rows]) for a in inputs.dsl_fields(n, n, 0.1))
     omega = inputs.rates(inputs.dsl_nu(n), "REG")
     f0 = oracle.init_eq(4, rho, ux, uy)
-    updates, elapsed, steps_done = 0, 0.0, {}
+    elapsed = 0.0
     for name in models:
         t0 = time.perf_counter()
-        f, k = f0, 0
-        while True:
-            f = oracle.step(f, oracle.MODELS[name], 4, omega, 1)
-            k += 1
-            if time.perf_counter() - t0 > budget_s / len(models):
-                break
+        f = oracle.step(f0, oracle.MODELS[name], 4, omega, steps)
         elapsed += time.perf_counter() - t0
-        updates += n * n * k
-        steps_done[name] = k
+        del f
+    updates = n * rows * steps * len(models)
     return {"value": updates / elapsed / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{n}x{n} double shear layer, FP64, steps per model {steps_done}, "
-                      f"{elapsed:.1f} s total"}
+            "sample": f"{rows} rows x {n} of the {n}x{n} double shear layer (a periodic band of the bench "
+                      f"workload), FP64, {steps} step(s) of each of {len(models)} models, {elapsed:.1f} s total"}
 
 
 def single_step_rates(sims, models, omega, cells, bpc, steps):
@@ -582,8 +577,8 @@ PROFILE_COMMANDS = {
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--prec", default="f32", choices=["f32", "f64", "f16"])
     ap.add_argument("--models", default="BGK,RM,HM,CM,CHM,K,PR,RR")
