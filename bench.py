@@ -83,10 +83,10 @@ def measured_valu_busy(model: str, prec: str):
     return None if rec is None or rec.get("valu_busy") is None else rec["valu_busy"]
 
 
-def cpu_baseline(models, n: int = 4096, rows: int = 1024, steps: int = 1):
+def cpu_baseline(models, n: int = 4096, rows: int = 2048, steps: int = 1):
     """The oracle (single-threaded FP64 C) on a bounded sample of the bench workload: `rows` full
     rows (4096 nodes wide) of the 4096 x 4096 double shear layer with the bench's rates, run as a
-    periodic band, `steps` step(s) per model (about 15 s of one core)."""
+    periodic band, `steps` step(s) per model (10-30 s of one core)."""
     import oracle
     from paper_2002_05265_amd import inputs
 
