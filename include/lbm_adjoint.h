@@ -61,6 +61,15 @@ int lbm_step_raw(lbm_ctx* ctx, int model, const double* omega, const void* src, 
 int lbm_step_raw_many(lbm_ctx* ctx, int model, const double* omega, const void* const* src,
                       void* const* dst, int count, long long step0);
 
+/* count (>= 0) pairs of raw steps in one call, in order, each as one launch of the two-step
+ * kernel (lbm_set_fusion; strips of the model's strip height, 16 rows if two steps per launch
+ * are off): pair k reads src[k] (state step0 + 2k) and writes dst[k] (state step0 + 2k + 2);
+ * when mid is non-NULL and mid[k] is non-NULL, the state step0 + 2k + 1 is also written to
+ * mid[k].  The states written are bit-identical to those of two lbm_step_raw calls.  src, mid
+ * and dst are host arrays of device pointers; the three buffers of a pair must differ. */
+int lbm_step2_raw_many(lbm_ctx* ctx, int model, const double* omega, const void* const* src,
+                       void* const* mid, void* const* dst, int count, long long step0);
+
 /* Seed of the velocity loss L = || u(f) - u_target ||_2 (sum over nodes and both
  * components) for the current state f:
  *   ux_t, uy_t  device, nx*ny FP64 [y][x]: the target velocity

@@ -6,8 +6,9 @@ L = || u(f_T) - u_target ||_2; its backward pass runs the hand-written discrete 
 and dL/domega (all five rates; the four higher-order ones are omega[1:]).
 
 The forward states needed in reverse order are rebuilt from checkpoints of the raw device
-state; steps between checkpoints run out-of-place (``lbm_step_raw``) straight into the buffer
-that keeps their result, so no state is ever copied:
+state; steps between checkpoints run out-of-place (``lbm_step_raw``, or pairs of them as one
+two-step launch, ``lbm_step2_raw_many``, when the context runs the model two steps per launch)
+straight into the buffer that keeps their result, so no state is ever copied:
   "sqrt"       ceil(sqrt(n)) evenly spaced checkpoints, each segment recomputed once into a
                ring of at most ceil(sqrt(n)) states (about n extra steps, 2 sqrt(n) states)
   "revolve"    binomial checkpointing with `slots` state buffers (Griewank's schedule: the
@@ -242,33 +243,73 @@ class _Run:
     # Fast paths: the sqrt(n) and store-all sweeps issue whole segments with two host calls
     # (lbm_step_raw_many / lbm_adjoint_many); they run exactly the kernels, in exactly the order,
     # that the generic action executor (used for "revolve") would.
+    def _two_step(self) -> bool:
+        """Whether the context runs this model two steps per launch (then pairs of forward steps
+        go through lbm_step2_raw_many; the states written are the same bit for bit)."""
+        return B.lbm_get_fusion(self.ctx, self.model)[0] > 0
+
+    def _run_chain(self, chain, step0: int):
+        """Advance along chain = [b_0, b_1, ..., b_m] (b_t receives state step0 + t; None = not
+        kept, a scratch buffer is used): pairs of steps as one two-step launch each (writing the
+        state between them only when it is kept), the rest one step per launch.  Returns the
+        buffer holding the last state."""
+        ops = []  # ("1", src, dst, step) or ("2", src, mid, dst, step)
+        cur = chain[0]
+        scratch = self._scratch
+        t, m = 1, len(chain) - 1
+        pairs = self._two_step()
+
+        def place(b):
+            if b is not None:
+                return b
+            return scratch[0] if cur is not scratch[0] else scratch[1]
+
+        while t <= m:
+            if pairs and t + 1 <= m:
+                dst = place(chain[t + 1])
+                ops.append(("2", cur, chain[t], dst, step0 + t - 1))
+                cur, t = dst, t + 2
+            else:
+                dst = place(chain[t])
+                ops.append(("1", cur, dst, step0 + t - 1))
+                cur, t = dst, t + 1
+        # issue consecutive ops of one kind with one host call
+        k = 0
+        while k < len(ops):
+            j = k
+            while j < len(ops) and ops[j][0] == ops[k][0]:
+                j += 1
+            run = ops[k:j]
+            if run[0][0] == "1":
+                B.lbm_step_raw_many(self.ctx, self.model, self.omega, [o[1].data_ptr() for o in run],
+                                    [o[2].data_ptr() for o in run], run[0][3])
+            else:
+                B.lbm_step2_raw_many(self.ctx, self.model, self.omega, [o[1].data_ptr() for o in run],
+                                     [0 if o[2] is None else o[2].data_ptr() for o in run],
+                                     [o[3].data_ptr() for o in run], run[0][4])
+            k = j
+        self.steps_run += m
+        return cur
+
     def _forward_fast(self):
         n = self.nsteps
         K = n if self.schedule == "store_all" else sqrt_interval(n)
-        keep = {}
         bufs = [self.cur]
         for t in range(1, n + 1):
             bufs.append(self._free_buffer() if (self.schedule == "store_all" or t % K == 0 or t == n)
                         else None)
-        # scratch ping-pong for states that are not kept
-        scratch = [self._free_buffer(), self._free_buffer()] if self.schedule == "sqrt" else []
-        src, dst = [], []
-        prev = bufs[0]
-        for t in range(1, n + 1):
-            b = bufs[t] if bufs[t] is not None else scratch[t % 2]
-            src.append(prev.data_ptr())
-            dst.append(b.data_ptr())
-            prev = b
-        B.lbm_step_raw_many(self.ctx, self.model, self.omega, src, dst, 0)
-        self.steps_run += n
+        # scratch for states that are not kept
+        self._scratch = [self._free_buffer(), self._free_buffer()] if self.schedule == "sqrt" else [None, None]
+        self._run_chain(bufs, 0)
+        keep = {}
         if self.schedule == "store_all":
             for t in range(n):
                 keep[("s", t)] = bufs[t]
         else:
             for t in range(0, n, K):
                 keep[("c", t)] = bufs[t]
-            self.pool.extend(scratch)
-            self.nbuf -= len(scratch)
+            self.pool.extend(self._scratch)
+            self.nbuf -= len(self._scratch)
         for k, b in keep.items():
             self._pin(k, b)
         self.cur = bufs[n]
@@ -285,13 +326,12 @@ class _Run:
             return
         K = sqrt_interval(n)
         ring = [self._free_buffer() for _ in range(K - 1)]
+        self._scratch = [None, None]
         for s0 in reversed(range(0, n, K)):
             m = min(s0 + K, n) - s0
             seg = [self.saved[("c", s0)]] + ring[:m - 1]
             if m > 1:
-                B.lbm_step_raw_many(self.ctx, self.model, self.omega, [b.data_ptr() for b in seg[:-1]],
-                                    [b.data_ptr() for b in seg[1:]], s0)
-                self.steps_run += m - 1
+                self._run_chain(seg, s0)
             states = [b.data_ptr() for b in reversed(seg)]
             ptrs = [lam[k % 2].data_ptr() for k in range(m + 1)]
             B.lbm_adjoint_many(self.ctx, self.model, self.omega, states, ptrs, None)

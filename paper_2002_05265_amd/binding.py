@@ -30,7 +30,7 @@ EXPORTS = (
     "lbm_batch_set_launch", "lbm_batch_set_fusion", "lbm_batch_get_fusion",
     "lbm_batch_autotune", "lbm_batch_destroy",
     "lbm_state_bytes", "lbm_adjoint_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_raw",
-    "lbm_step_raw_many", "lbm_adjoint_many", "lbm_adjoint_flush",
+    "lbm_step_raw_many", "lbm_step2_raw_many", "lbm_adjoint_many", "lbm_adjoint_flush",
     "lbm_adjoint_seed_velocity_l2", "lbm_adjoint_step", "lbm_eq_vjp",
     "lbm_lsa_jacobian", "lbm_lsa_eigenvalues", "lbm_lsa_radius", "lbm_lsa_dvbe_growth",
 )
@@ -101,6 +101,8 @@ def _declare(L: ctypes.CDLL):
         "lbm_load_state": (_i, [_vp, _vp, _ll]),
         "lbm_step_raw": (_i, [_vp, _i, _dp, _vp, _vp, _ll]),
         "lbm_step_raw_many": (_i, [_vp, _i, _dp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i, _ll]),
+        "lbm_step2_raw_many": (_i, [_vp, _i, _dp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i,
+                                    _ll]),
         "lbm_adjoint_many": (_i, [_vp, _i, _dp, ctypes.POINTER(_vp), _i, ctypes.POINTER(_vp), _vp]),
         "lbm_adjoint_flush": (_i, [_vp, _vp]),
         "lbm_adjoint_seed_velocity_l2": (_i, [_vp, _vp, _vp, _vp, _dp]),
@@ -319,6 +321,13 @@ def _ptrs(seq):
 def lbm_step_raw_many(ctx: int, model: int, omega, src, dst, step0: int):
     _check(lib().lbm_step_raw_many(ctx, model, _omega(omega), _ptrs(src), _ptrs(dst), len(src), step0),
            "lbm_step_raw_many")
+
+
+def lbm_step2_raw_many(ctx: int, model: int, omega, src, mid, dst, step0: int):
+    """Pairs of raw steps src[k] -> dst[k]; mid[k] (0 / None = not kept) receives the state between."""
+    mids = None if mid is None else _ptrs([m or 0 for m in mid])
+    _check(lib().lbm_step2_raw_many(ctx, model, _omega(omega), _ptrs(src), mids, _ptrs(dst), len(src), step0),
+           "lbm_step2_raw_many")
 
 
 def lbm_adjoint_many(ctx: int, model: int, omega, states, lam, domega: int | None):

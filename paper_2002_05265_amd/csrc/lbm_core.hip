@@ -152,12 +152,13 @@ int default_fusion_strip(int nx, int ny, int prec) {
     return s16 >= 256 ? 16 : 0;
 }
 
-template <int MODEL, int PREC, int RING>
+template <int MODEL, int PREC, int RING, bool MID = false>
 __global__ __launch_bounds__(256) void k_step2(const typename Store<PREC>::S* __restrict__ src,
                                                typename Store<PREC>::S* __restrict__ dst, Geom g,
                                                Coef<typename Store<PREC>::R> c,
                                                Ref<typename Store<PREC>::R> ref, int N, int step,
-                                               int* __restrict__ blowup, unsigned gsx, int hs) {
+                                               int* __restrict__ blowup, unsigned gsx, int hs,
+                                               typename Store<PREC>::S* __restrict__ mid) {
     using S = typename Store<PREC>::S;
     using R = typename Store<PREC>::R;
     __shared__ S ring[9][RING + 2][kStripW + 2];
@@ -166,8 +167,9 @@ __global__ __launch_bounds__(256) void k_step2(const typename Store<PREC>::S* __
     const unsigned sy = blockIdx.x / gsx;
     const int x0 = (int)(blockIdx.x - sy * gsx) * kStripW;
     const int ys = (int)sy * hs;
-    strip_two_steps<RING, false, true>(ring, src, dst, g, ref, x0, ys, min(ys + hs, g.ny), step, blowup,
-                                       [&](R(&h)[9], const Macro<R>& m) { collide<MODEL>(h, m, ref, c, N); });
+    strip_two_steps<RING, false, true, MID>(
+        ring, src, dst, g, ref, x0, ys, min(ys + hs, g.ny), step, blowup,
+        [&](R(&h)[9], const Macro<R>& m) { collide<MODEL>(h, m, ref, c, N); }, mid);
 }
 
 // Macroscopic fields of the state f(., n) (pulled from the post-collision copy) and per-block
@@ -317,7 +319,44 @@ void launch_step2_r(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int hs
     const unsigned gsy = (unsigned)((ctx->ny + hs - 1) / hs);
     hipLaunchKernelGGL((k_step2<MODEL, PREC, RING>), dim3(gsx * gsy), dim3(256), 0, ctx->stream, src,
                        dst, ctx->geom(), c, ref_as<typename Store<PREC>::R>(ctx->ref), ctx->eq_order,
-                       (int)ctx->step, ctx->d_flag, gsx, hs);
+                       (int)ctx->step, ctx->d_flag, gsx, hs, nullptr);
+}
+
+// Two raw steps src -> dst (ring of 8 rows, strips of hs rows); with mid != NULL the state after
+// the first step is also written there.
+template <int MODEL, int PREC>
+void launch_step2_raw_t(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int hs, const void* src, void* mid,
+                        void* dst, int step) {
+    using S = typename Store<PREC>::S;
+    const unsigned gsx = (unsigned)((ctx->nx + kStripW - 1) / kStripW);
+    const unsigned gsy = (unsigned)((ctx->ny + hs - 1) / hs);
+    if (mid)
+        hipLaunchKernelGGL((k_step2<MODEL, PREC, 8, true>), dim3(gsx * gsy), dim3(256), 0, ctx->stream,
+                           reinterpret_cast<const S*>(src), reinterpret_cast<S*>(dst), ctx->geom(), c,
+                           ref_as<typename Store<PREC>::R>(ctx->ref), ctx->eq_order, step, ctx->d_flag, gsx, hs,
+                           reinterpret_cast<S*>(mid));
+    else
+        hipLaunchKernelGGL((k_step2<MODEL, PREC, 8, false>), dim3(gsx * gsy), dim3(256), 0, ctx->stream,
+                           reinterpret_cast<const S*>(src), reinterpret_cast<S*>(dst), ctx->geom(), c,
+                           ref_as<typename Store<PREC>::R>(ctx->ref), ctx->eq_order, step, ctx->d_flag, gsx, hs,
+                           static_cast<S*>(nullptr));
+}
+
+template <int PREC>
+void launch_step2_raw_p(lbm_ctx* ctx, int model, const double* w, int hs, const void* src, void* mid, void* dst,
+                        int step) {
+    const Coef<typename Store<PREC>::R> c = make_coef<typename Store<PREC>::R>(w);
+    switch (model) {
+        case LBM_BGK: launch_step2_raw_t<kBGK, PREC>(ctx, c, hs, src, mid, dst, step); break;
+        case LBM_RM: launch_step2_raw_t<kRM, PREC>(ctx, c, hs, src, mid, dst, step); break;
+        case LBM_HM: launch_step2_raw_t<kHM, PREC>(ctx, c, hs, src, mid, dst, step); break;
+        case LBM_CM: launch_step2_raw_t<kCM, PREC>(ctx, c, hs, src, mid, dst, step); break;
+        case LBM_CHM: launch_step2_raw_t<kCHM, PREC>(ctx, c, hs, src, mid, dst, step); break;
+        case LBM_K: launch_step2_raw_t<kK, PREC>(ctx, c, hs, src, mid, dst, step); break;
+        case LBM_PR: launch_step2_raw_t<kPR, PREC>(ctx, c, hs, src, mid, dst, step); break;
+        case LBM_RR: launch_step2_raw_t<kRR, PREC>(ctx, c, hs, src, mid, dst, step); break;
+        default: launch_step2_raw_t<kStreamOnly, PREC>(ctx, c, hs, src, mid, dst, step); break;
+    }
 }
 
 template <int MODEL, int PREC>
@@ -581,6 +620,29 @@ int lbm_step_raw_many(lbm_ctx* ctx, int model, const double* omega, const void* 
     for (int k = 0; k < count; ++k)
         LBM_DISPATCH_PREC(ctx->prec, launch_step_raw_p, ctx, model, omega, sh, src[k], dst[k], (int)(step0 + k));
     return check_hip(hipGetLastError(), "raw step kernel launch");
+}
+
+int lbm_step2_raw_many(lbm_ctx* ctx, int model, const double* omega, const void* const* src, void* const* mid,
+                       void* const* dst, int count, long long step0) {
+    if (!ctx) return set_error(LBM_ESTATE, "context is NULL");
+    if (count < 0) return set_error(LBM_EINVAL, "count %d < 0", count);
+    if (count == 0) return LBM_OK;
+    if (!src || !dst) return set_error(LBM_EINVAL, "NULL pointer array");
+    if (step0 < 0 || step0 + 2LL * count >= INT_MAX) return set_error(LBM_EINVAL, "step %lld out of range", step0);
+    for (int k = 0; k < count; ++k) {
+        const void* m = mid ? mid[k] : nullptr;
+        if (!src[k] || !dst[k] || src[k] == dst[k] || (m && (m == src[k] || m == dst[k])))
+            return set_error(LBM_EINVAL, "bad state pointer at pair %d", k);
+    }
+    int rc = validate_model(model, ctx->eq_order);
+    if (rc == LBM_OK) rc = validate_omega(omega);
+    if (rc != LBM_OK) return rc;
+    const int fs = ctx->fuse_strip[lbm_ctx::slot(model)];
+    const int hs = fs > 0 ? fs : 16;
+    for (int k = 0; k < count; ++k)
+        LBM_DISPATCH_PREC(ctx->prec, launch_step2_raw_p, ctx, model, omega, hs, src[k], mid ? mid[k] : nullptr,
+                          dst[k], (int)(step0 + 2LL * k));
+    return check_hip(hipGetLastError(), "raw two-step kernel launch");
 }
 
 int lbm_moments(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* totals) {

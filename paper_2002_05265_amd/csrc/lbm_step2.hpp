@@ -60,12 +60,14 @@ __device__ __forceinline__ void pull_load_l2(const S* __restrict__ src, long lon
 // Steps `step` and `step` + 1 of the strip of columns x0 .. x0 + kStripW - 1 and rows ys .. ye - 1
 // of grid g: pulls from src, writes to dst, collides with coll(h, m).  Called by all 256 threads
 // of a workgroup (it contains block barriers); ring is the workgroup's LDS ring.  VIA_L2 selects
-// L1-bypassing loads, NT streaming stores.  Blow-up records go to *blowup (steps step and
-// step + 1).
-template <int RING, bool VIA_L2, bool NT, typename S, typename R, typename Coll>
+// L1-bypassing loads, NT streaming stores; with MID the strip's nodes after the first step are
+// also written to mid (the state a single step would have written).  Blow-up records go to
+// *blowup (steps step and step + 1).
+template <int RING, bool VIA_L2, bool NT, bool MID = false, typename S, typename R, typename Coll>
 __device__ __forceinline__ void strip_two_steps(S (&ring)[9][RING + 2][kStripW + 2], const S* __restrict__ src,
                                                 S* __restrict__ dst, const Geom& g, const Ref<R>& ref, int x0,
-                                                int ys, int ye, int step, int* __restrict__ blowup, Coll&& coll) {
+                                                int ys, int ye, int step, int* __restrict__ blowup, Coll&& coll,
+                                                S* __restrict__ mid = nullptr) {
     constexpr int NR = RING + 2;
     constexpr int W = kStripW;
     constexpr int WPR = W / 64;        // waves per row of the strip
@@ -93,13 +95,18 @@ __device__ __forceinline__ void strip_two_steps(S (&ring)[9][RING + 2][kStripW +
     // ring slot of row a is (a - ys + 1) mod NR; within a pass it is reached from the pass's slot
     // base sb = (yb - ys + 1) mod NR by an offset in [-1, NR), so one conditional wrap suffices
     auto wrap = [](int t) { return t < 0 ? t + NR : (t >= NR ? t - NR : t); };
-    auto finish = [&](int slot, int cc, R (&h)[9]) {
+    // a: the node's row (for the intermediate state, which takes the strip's own nodes only)
+    auto finish = [&](int slot, int cc, int a, R (&h)[9]) {
         double rho_d;
         const Macro<R> m = macro_of<S>(h, ref, rho_d);
         flag_bad(!(rho_d > 0.0), blowup, step);
         coll(h, m);
 #pragma unroll
         for (int i = 0; i < 9; ++i) ring[i][slot][cc] = to_store<S>(h[i]);
+        if constexpr (MID) {
+            if (cc >= 1 && cc <= w && a >= ys && a < ye)
+                store_cell<S, R, NT>(mid, g.plane, (unsigned)a * (unsigned)g.nx + (unsigned)(x0 + cc - 1), h);
+        }
     };
     // Rows of a pass starting at yb: wave v takes rows yb + 1 + rl + RPW k of its column group,
     // and wave 3 also the halo columns of rows yb + 1 .. (two lanes per row).  The loads of the
@@ -132,7 +139,7 @@ __device__ __forceinline__ void strip_two_steps(S (&ring)[9][RING + 2][kStripW +
         const bool act = wave < 2 ? in1 : (wave == 2 && lane < 4);
         if (act) load(ys - 1 + r, cc, h);
         prefetch(ys);
-        if (act) finish(r, cc, h);
+        if (act) finish(r, cc, ys - 1 + r, h);
     } else {
         R h[9], hp[9];
         const bool act = rl < 2 && in1;
@@ -141,8 +148,8 @@ __device__ __forceinline__ void strip_two_steps(S (&ring)[9][RING + 2][kStripW +
         if (act) load(ys - 1 + rl, lc, h);
         if (acth) load(ys - 1 + rh, ch, hp);
         prefetch(ys);
-        if (act) finish(rl, lc, h);
-        if (acth) finish(rh, ch, hp);
+        if (act) finish(rl, lc, ys - 1 + rl, h);
+        if (acth) finish(rh, ch, ys - 1 + rh, hp);
     }
     for (int yb = ys; yb < ye; yb += RING) {
         const int top = min(yb + RING, ye);   // first step of rows yb + 1 .. top
@@ -150,11 +157,11 @@ __device__ __forceinline__ void strip_two_steps(S (&ring)[9][RING + 2][kStripW +
 #pragma unroll
         for (int k = 0; k < KR; ++k) {
             const int a = yb + 1 + rl + RPW * k;
-            if (a <= top && in1) finish(wrap(sb + 1 + rl + RPW * k), lc, hn[k]);
+            if (a <= top && in1) finish(wrap(sb + 1 + rl + RPW * k), lc, a, hn[k]);
         }
         if (wave == 3) {
             const int a = yb + 1 + (lane >> 1);
-            if (a <= top) finish(wrap(sb + 1 + (lane >> 1)), (lane & 1) ? w + 1 : 0, hh);
+            if (a <= top) finish(wrap(sb + 1 + (lane >> 1)), (lane & 1) ? w + 1 : 0, a, hh);
         }
         __syncthreads();
         if (yb + RING < ye) prefetch(yb + RING);
