@@ -574,6 +574,21 @@ PROFILE_COMMANDS = {
 }
 
 
+def profile_commands(prec: str) -> dict:
+    """The rocprofv3 commands whose csv output `--profile-summary` reads, for one precision (FP32:
+    PROFILE_COMMANDS; others under gpurun_out/p_<prec>/, with the FP32 run's copy calibration)."""
+    if prec == "f32":
+        return PROFILE_COMMANDS
+    args = f"{PROFILE_ARGS} --prec {prec}"
+    d = f"gpurun_out/p_{prec}"
+    out = {k: f"rocprofv3 --pmc {c} --output-format csv -d {d}/rp_{k} -o bench -- python bench.py {args}"
+           for k, c in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE"), ("valu", "VALUBusy"))}
+    out["trace"] = (f"rocprofv3 --kernel-trace --stats --output-format csv -d {d}/rp_trace -o bench -- "
+                    f"python bench.py {args}")
+    out["copy_fetch"], out["copy_write"] = PROFILE_COMMANDS["copy_fetch"], PROFILE_COMMANDS["copy_write"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -596,8 +611,9 @@ def main():
                          "into profiles/ (no GPU use)")
     args = ap.parse_args()
     if args.profile_summary:
-        profile_summary(args.profile_summary, args.prec, args.n, PROFILE_COMMANDS)
-        extras_trace_summary(args.profile_summary, EXTRAS_PROFILE_COMMAND)
+        profile_summary(args.profile_summary, args.prec, args.n, profile_commands(args.prec))
+        if args.prec == "f32":
+            extras_trace_summary(args.profile_summary, EXTRAS_PROFILE_COMMAND)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
