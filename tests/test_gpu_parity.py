@@ -246,3 +246,39 @@ def test_argument_errors_on_gpu(gpu):
         s.step(42, [1.0] * 5, 1)
     assert s.status() == (0, -1)
     s.close()
+
+
+def test_argument_errors_of_two_step_and_dvbe_entry_points(gpu):
+    import torch
+
+    import paper_2002_05265_amd.binding as B
+    from paper_2002_05265_amd import lsa
+
+    rho, ux, uy = inputs.vortex_fields(16, 16, 0.1)
+    s = Sim(rho, ux, uy, prec="f64", device=gpu)
+    n = B.lbm_state_bytes(s.ctx)
+    a, b, c = (torch.empty(n, dtype=torch.uint8, device=gpu) for _ in range(3))
+    w = [1.5] * 5
+    # a pair's three buffers must differ; counts and steps in range
+    for src, mid, dst in ((a, None, a), (a, a, b), (a, b, b)):
+        with pytest.raises(B.LbmError) as e:
+            B.lbm_step2_raw_many(s.ctx, 0, w, [src.data_ptr()], None if mid is None else [mid.data_ptr()],
+                                 [dst.data_ptr()], 0)
+        assert e.value.code == -1
+    with pytest.raises(B.LbmError):
+        B.lbm_step2_raw_many(s.ctx, 0, w, [a.data_ptr()], None, [b.data_ptr()], -1)
+    with pytest.raises(B.LbmError):
+        B.lbm_step2_raw_many(s.ctx, 42, w, [a.data_ptr()], None, [b.data_ptr()], 0)  # unknown model
+    B.lbm_save_state(s.ctx, a.data_ptr())
+    B.lbm_step2_raw_many(s.ctx, 0, w, [], None, [], 0)  # an empty call does nothing
+    B.lbm_step2_raw_many(s.ctx, 0, w, [a.data_ptr()], [c.data_ptr()], [b.data_ptr()], 0)
+    s.close()
+    # DVBE: tau must be positive; the points are checked
+    kx = torch.zeros(4, dtype=torch.float64, device=gpu)
+    pt = lsa.point("BGK", 0.0, 0.1, eq_order=2, omega=[1.0] * 5)
+    for tau in (0.0, -1.0, float("nan")):
+        with pytest.raises(B.LbmError):
+            lsa.dvbe_growth([pt], kx, kx, tau=tau)
+    bad = dict(pt, eq_order=5)
+    with pytest.raises(B.LbmError):
+        lsa.dvbe_growth([bad], kx, kx)
