@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kTileThreads) void k_batch2(
             const int sy = e.y / gsx;
             const int x0 = (e.y - sy * gsx) * kStripW, ys = sy * hs;
             const Geom g{d.nx, d.ny, d.plane};
-            strip_two_steps<RING, true, false>(ring, src + d.off, dst + d.off, g, d.ref, x0, ys, min(ys + hs, d.ny),
+            strip_two_steps<RING, kStripW, true, false>(ring, src + d.off, dst + d.off, g, d.ref, x0, ys, min(ys + hs, d.ny),
                                                (int)n, blowup + j, [&](R(&h)[9], const Macro<R>& m) {
                                                    collide_model(d.model, h, m, d.ref, d.c, d.N);
                                                });

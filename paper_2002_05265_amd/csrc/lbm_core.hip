@@ -152,6 +152,21 @@ int default_fusion_strip(int nx, int ny, int prec) {
     return s16 >= 256 ? 16 : 0;
 }
 
+// Strip width of the two-step kernel for a model and precision.  Measured at 4096^2: in FP32 the
+// models whose two-step kernel is not ALU-bound (BGK, RM, HM, PR, RR, the pure pull) gain 5% from
+// strips of 128 columns (two waves per row: half the edge lines and halo nodes per column) with a
+// ring of 4 rows; CM, CHM and K (vector ALU saturated), FP64 and FP16 do not, and keep 64.
+constexpr bool wide_strips(int model, int prec) {
+    return prec == LBM_F32_SHIFTED && model != LBM_CM && model != LBM_CHM && model != LBM_K;
+}
+
+template <int MODEL, int PREC>
+constexpr int strip_width() {
+    return wide_strips(MODEL, PREC == kF32 ? LBM_F32_SHIFTED : (PREC == kF64 ? LBM_F64 : LBM_F16_SHIFTED))
+               ? 2 * kStripW
+               : kStripW;
+}
+
 template <int MODEL, int PREC, int RING, bool MID = false>
 __global__ __launch_bounds__(256) void k_step2(const typename Store<PREC>::S* __restrict__ src,
                                                typename Store<PREC>::S* __restrict__ dst, Geom g,
@@ -161,13 +176,14 @@ __global__ __launch_bounds__(256) void k_step2(const typename Store<PREC>::S* __
                                                typename Store<PREC>::S* __restrict__ mid) {
     using S = typename Store<PREC>::S;
     using R = typename Store<PREC>::R;
-    __shared__ S ring[9][RING + 2][kStripW + 2];
+    constexpr int W = strip_width<MODEL, PREC>();
+    __shared__ S ring[9][RING + 2][W + 2];
     // strips in hardware order (an XCD-banded order measured no faster: the strips' edge lines
     // are not what limits this kernel)
     const unsigned sy = blockIdx.x / gsx;
-    const int x0 = (int)(blockIdx.x - sy * gsx) * kStripW;
+    const int x0 = (int)(blockIdx.x - sy * gsx) * W;
     const int ys = (int)sy * hs;
-    strip_two_steps<RING, false, true, MID>(
+    strip_two_steps<RING, W, false, true, MID>(
         ring, src, dst, g, ref, x0, ys, min(ys + hs, g.ny), step, blowup,
         [&](R(&h)[9], const Macro<R>& m) { collide<MODEL>(h, m, ref, c, N); }, mid);
 }
@@ -315,7 +331,8 @@ void launch_step2_r(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int hs
     using S = typename Store<PREC>::S;
     const S* src = reinterpret_cast<const S*>(ctx->copy(src_copy));
     S* dst = reinterpret_cast<S*>(ctx->copy(src_copy ^ 1));
-    const unsigned gsx = (unsigned)((ctx->nx + kStripW - 1) / kStripW);
+    constexpr int W = strip_width<MODEL, PREC>();
+    const unsigned gsx = (unsigned)((ctx->nx + W - 1) / W);
     const unsigned gsy = (unsigned)((ctx->ny + hs - 1) / hs);
     hipLaunchKernelGGL((k_step2<MODEL, PREC, RING>), dim3(gsx * gsy), dim3(256), 0, ctx->stream, src,
                        dst, ctx->geom(), c, ref_as<typename Store<PREC>::R>(ctx->ref), ctx->eq_order,
@@ -328,7 +345,8 @@ template <int MODEL, int PREC>
 void launch_step2_raw_t(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int hs, const void* src, void* mid,
                         void* dst, int step) {
     using S = typename Store<PREC>::S;
-    const unsigned gsx = (unsigned)((ctx->nx + kStripW - 1) / kStripW);
+    constexpr int W = strip_width<MODEL, PREC>();
+    const unsigned gsx = (unsigned)((ctx->nx + W - 1) / W);
     const unsigned gsy = (unsigned)((ctx->ny + hs - 1) / hs);
     if (mid)
         hipLaunchKernelGGL((k_step2<MODEL, PREC, 8, true>), dim3(gsx * gsy), dim3(256), 0, ctx->stream,
@@ -365,7 +383,7 @@ void launch_step2_t(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int ri
         case 4: launch_step2_r<MODEL, PREC, 4>(ctx, c, hs, src_copy); break;
         case 16:
             // the ring must fit in the 160 KiB of LDS a workgroup can have
-            if constexpr (9 * 18 * (kStripW + 2) * sizeof(typename Store<PREC>::S) <= 160 * 1024)
+            if constexpr (9 * 18 * (strip_width<MODEL, PREC>() + 2) * sizeof(typename Store<PREC>::S) <= 160 * 1024)
                 launch_step2_r<MODEL, PREC, 16>(ctx, c, hs, src_copy);
             else
                 launch_step2_r<MODEL, PREC, 8>(ctx, c, hs, src_copy);
@@ -543,7 +561,8 @@ int lbm_init_shifted(lbm_ctx** out, int nx, int ny, int prec, int eq_order, doub
     const int fstrip = default_fusion_strip(nx, ny, prec);
     if (fstrip > 0)
         for (int k = 0; k < 9; ++k) {
-            ctx->fuse_ring[k] = 8;
+            // slot k is model k (slot 8: the pure pull); a ring of 4 rows with wide strips
+            ctx->fuse_ring[k] = wide_strips(k < 8 ? k : LBM_STREAM_ONLY, prec) ? 4 : 8;
             ctx->fuse_strip[k] = fstrip;
         }
     int rc = check_hip(hipGetDevice(&ctx->device), "hipGetDevice");
@@ -766,9 +785,9 @@ int lbm_autotune(lbm_ctx* ctx, int model, const double* omega, int trials, int* 
             }
         }
     // two-step shapes, per step
-    const int fuse_c[5][2] = {{8, 16}, {8, 32}, {8, 64}, {16, 16}, {4, 64}};
+    const int fuse_c[6][2] = {{8, 16}, {8, 32}, {8, 64}, {16, 16}, {4, 16}, {4, 64}};
     int best_ring = 0, best_strip = 0;
-    for (int k = 0; k < 5 && rc == LBM_OK; ++k) {
+    for (int k = 0; k < 6 && rc == LBM_OK; ++k) {
         const int ring = fuse_c[k][0], hs = fuse_c[k][1];
         const float ms = 0.5f * timed([&] { LBM_DISPATCH_PREC(ctx->prec, launch_step2_p, ctx, model, omega, ring, hs, ctx->cur); });
         if (rc == LBM_OK && ms < best) {

@@ -18,14 +18,12 @@ namespace lbm {
 // node is computed by the same arithmetic as in k_step and the ring holds the values in the
 // storage type, so the result is bit-identical to two launches of k_step.
 //
-// A strip is 64 columns wide, so every output row segment is whole 256-byte lines; lane l takes
-// column x0 + l, and one wave collides the two halo columns of the pass's rows in an extra pass.
+// Strips are 64 columns wide (128 for some models, see strip_width in lbm_core.hip), so every
+// output row segment is whole 256-byte lines; lane l of a wave takes column x0 + 64 c + l of its
+// column group c, and one wave collides the two halo columns of the pass's rows in an extra pass.
 // (A 62-column strip with the halo columns in lanes 0 and 63 saves that pass, but its stores
 // start mid-line and two strips write parts of the same lines: measured 0.6x as fast.)
-#ifndef LBM_STRIP_W
-#define LBM_STRIP_W 64
-#endif
-constexpr int kStripW = LBM_STRIP_W;
+constexpr int kStripW = 64;
 
 // Loads that bypass the CU's L1 (agent scope) and are served by the XCD's L2: what the batched
 // kernel's workgroups read was written by other workgroups of the same XCD during the launch.
@@ -57,19 +55,18 @@ __device__ __forceinline__ void pull_load_l2(const S* __restrict__ src, long lon
     h[8] = R(ld_l2(plane_at(src, plane, 8, rp + xm)));
 }
 
-// Steps `step` and `step` + 1 of the strip of columns x0 .. x0 + kStripW - 1 and rows ys .. ye - 1
+// Steps `step` and `step` + 1 of the strip of columns x0 .. x0 + W - 1 and rows ys .. ye - 1
 // of grid g: pulls from src, writes to dst, collides with coll(h, m).  Called by all 256 threads
 // of a workgroup (it contains block barriers); ring is the workgroup's LDS ring.  VIA_L2 selects
 // L1-bypassing loads, NT streaming stores; with MID the strip's nodes after the first step are
 // also written to mid (the state a single step would have written).  Blow-up records go to
 // *blowup (steps step and step + 1).
-template <int RING, bool VIA_L2, bool NT, bool MID = false, typename S, typename R, typename Coll>
-__device__ __forceinline__ void strip_two_steps(S (&ring)[9][RING + 2][kStripW + 2], const S* __restrict__ src,
+template <int RING, int W, bool VIA_L2, bool NT, bool MID = false, typename S, typename R, typename Coll>
+__device__ __forceinline__ void strip_two_steps(S (&ring)[9][RING + 2][W + 2], const S* __restrict__ src,
                                                 S* __restrict__ dst, const Geom& g, const Ref<R>& ref, int x0,
                                                 int ys, int ye, int step, int* __restrict__ blowup, Coll&& coll,
                                                 S* __restrict__ mid = nullptr) {
     constexpr int NR = RING + 2;
-    constexpr int W = kStripW;
     constexpr int WPR = W / 64;        // waves per row of the strip
     constexpr int RPW = 4 / WPR;       // rows the block covers at once
     constexpr int KR = RING / RPW;     // rows per wave and pass

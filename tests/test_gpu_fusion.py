@@ -122,7 +122,10 @@ def test_defaults_and_autotune(gpu):
         s = Sim(rho, ux, uy, prec=prec, device=gpu)
         got = [s.fusion(m) for m in MODELS]
         s.close()
-        assert all(g == want for g in got), (nx, ny, prec, got)
+        # FP32: the models with 128-column strips start with a ring of 4 rows
+        wide = [prec == "f32" and m not in ("CM", "CHM", "K") for m in MODELS]
+        exp = [(4, want[1]) if wd and want[0] else want for wd in wide]
+        assert got == exp, (nx, ny, prec, got)
     # autotune leaves state and counter alone, keeps a valid choice, and results do not change
     nx, ny = 1024, 512
     rho, ux, uy = perturbed(nx, ny, 8)
@@ -136,7 +139,7 @@ def test_defaults_and_autotune(gpu):
     ring, strip = a.fusion("RR")
     print(f"autotune 1024x512 RR: rows {rows} xcd {xcd} ring {ring} strip {strip} {us:.1f} us/step", flush=True)
     assert rows in (1, 2, 4) and xcd in (0, 1) and us > 0
-    assert (ring, strip) in ((0, 0), (8, 16), (8, 32), (8, 64), (16, 16), (4, 64))
+    assert (ring, strip) in ((0, 0), (8, 16), (8, 32), (8, 64), (16, 16), (4, 16), (4, 64))
     np.testing.assert_array_equal(a.state().cpu().numpy(), before)
     assert a.status() == (3, -1)
     a.step("RR", omega, 9)
