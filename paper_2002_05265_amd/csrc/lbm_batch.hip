@@ -984,10 +984,13 @@ int lbm_batch_set_fusion(lbm_batch* b, int strip_rows) {
     }
     b->fuse = 1;
     if (strip_rows == b->hs) return LBM_OK;
-    b->hs = strip_rows;
-    int rc = alloc_strips(b);
+    // live_set synchronises the stream first: no launch still reads the strip table when it is
+    // reallocated and rewritten
     std::vector<char> live;
-    if (rc == LBM_OK) rc = live_set(b, live);
+    int rc = live_set(b, live);
+    if (rc != LBM_OK) return rc;
+    b->hs = strip_rows;
+    rc = alloc_strips(b);
     return rc != LBM_OK ? rc : deal_tables(b, live);
 }
 
