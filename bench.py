@@ -127,6 +127,22 @@ def single_step_rates(sims, models, omega, cells, bpc, steps):
     return out
 
 
+def cache_resident_rates(models, sizes=(1024, 512), precs=("f32", "f64"), steps: int = 200):
+    """MLUPS on grids whose two copies fit the 256 MB last-level cache (the double shear layer at
+    1024^2 and 512^2, the bench's default launch settings): labelled cache-resident, not compared
+    with the HBM roofline."""
+    from paper_2002_05265_amd import inputs
+
+    out = {}
+    for n in sizes:
+        fields = inputs.dsl_fields(n, n, 0.1)
+        omega = inputs.rates(inputs.dsl_nu(n), "REG")
+        for prec in precs:
+            r = time_models(prec, n, models, steps, 10, omega, fields)
+            out[f"{prec}-{n}"] = {m: v["mlups"] for m, v in r.items()}
+    return {"cache_resident": True, "steps": steps, "mlups": out}
+
+
 def time_models(prec: str, n: int, models, steps: int, warmup: int, omega, fields):
     """Per-model timing of `steps` launches on an n x n grid (HIP events on the launch stream)."""
     import torch
@@ -734,6 +750,7 @@ def main():
         fields = (rho, ux, uy)
         extra_steps = max(20, args.steps // 2)
         line["precisions"] = {p: time_models(p, n, models, extra_steps, 5, omega, fields) for p in ("f64", "f16")}
+        line["small_grids"] = cache_resident_rates(models)
         f64_mlups = min(v["mlups"] for v in line["precisions"]["f64"].values())
         line["batched"] = batched_sweep(args.batch_steps, f64_mlups)
         line["adjoint"] = adjoint_run()

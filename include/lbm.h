@@ -147,12 +147,13 @@ int lbm_set_launch(lbm_ctx* ctx, int model, int rows, int xcd);
  * LBM_STREAM_ONLY): lbm_step then advances two steps per launch, reading and writing each
  * population once per pair of steps instead of twice; an odd last step uses the single-step
  * kernel.  A workgroup owns a strip of columns (128 for the FP32 context's BGK, RM, HM, PR, RR and
- * LBM_STREAM_ONLY, 64 otherwise) and strip_rows rows and walks down it
+ * LBM_STREAM_ONLY when that still gives at least 1024 strips, 64 otherwise) and strip_rows rows and
+ * walks down it
  * ring_rows rows at a time, keeping the first step's values of ring_rows + 2 rows (and one halo
  * column each side) in LDS; the halo nodes are collided by both strips that need them.
  *   ring_rows   0 (off), 4, 8 or 16
  *   strip_rows  positive multiple of ring_rows (ignored when ring_rows is 0)
- * A new context starts, for every model, with ring_rows 8 (4 for the FP32 models with 128-column
+ * A new context starts, for every model, with ring_rows 8 (4 for the FP32 models that get 128-column
  * strips) and strip_rows
  *   FP32: 16 if that gives at least 256 strips, else off;
  *   FP64: 64 if that gives at least 1024 strips, else as FP32;

@@ -160,6 +160,10 @@ constexpr bool wide_strips(int model, int prec) {
     return prec == LBM_F32_SHIFTED && model != LBM_CM && model != LBM_CHM && model != LBM_K;
 }
 
+// Widest strip for a model and precision; the launch uses it only while it still gives at least
+// kWideMinStrips strips (otherwise 64 columns keep enough workgroups in flight on small grids).
+constexpr long long kWideMinStrips = 1024;
+
 template <int MODEL, int PREC>
 constexpr int strip_width() {
     return wide_strips(MODEL, PREC == kF32 ? LBM_F32_SHIFTED : (PREC == kF64 ? LBM_F64 : LBM_F16_SHIFTED))
@@ -167,7 +171,7 @@ constexpr int strip_width() {
                : kStripW;
 }
 
-template <int MODEL, int PREC, int RING, bool MID = false>
+template <int MODEL, int PREC, int RING, int W, bool MID = false>
 __global__ __launch_bounds__(256) void k_step2(const typename Store<PREC>::S* __restrict__ src,
                                                typename Store<PREC>::S* __restrict__ dst, Geom g,
                                                Coef<typename Store<PREC>::R> c,
@@ -176,7 +180,6 @@ __global__ __launch_bounds__(256) void k_step2(const typename Store<PREC>::S* __
                                                typename Store<PREC>::S* __restrict__ mid) {
     using S = typename Store<PREC>::S;
     using R = typename Store<PREC>::R;
-    constexpr int W = strip_width<MODEL, PREC>();
     __shared__ S ring[9][RING + 2][W + 2];
     // strips in hardware order (an XCD-banded order measured no faster: the strips' edge lines
     // are not what limits this kernel)
@@ -326,17 +329,38 @@ void launch_step_raw_p(lbm_ctx* ctx, int model, const double* w, const StepShape
     }
 }
 
-template <int MODEL, int PREC, int RING>
-void launch_step2_r(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int hs, int src_copy) {
+// One launch of k_step2 with strips of W columns.
+template <int MODEL, int PREC, int RING, int W, bool MID>
+void launch_step2_w(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int hs, const void* src, void* mid,
+                    void* dst, int step) {
     using S = typename Store<PREC>::S;
-    const S* src = reinterpret_cast<const S*>(ctx->copy(src_copy));
-    S* dst = reinterpret_cast<S*>(ctx->copy(src_copy ^ 1));
-    constexpr int W = strip_width<MODEL, PREC>();
     const unsigned gsx = (unsigned)((ctx->nx + W - 1) / W);
     const unsigned gsy = (unsigned)((ctx->ny + hs - 1) / hs);
-    hipLaunchKernelGGL((k_step2<MODEL, PREC, RING>), dim3(gsx * gsy), dim3(256), 0, ctx->stream, src,
-                       dst, ctx->geom(), c, ref_as<typename Store<PREC>::R>(ctx->ref), ctx->eq_order,
-                       (int)ctx->step, ctx->d_flag, gsx, hs, nullptr);
+    hipLaunchKernelGGL((k_step2<MODEL, PREC, RING, W, MID>), dim3(gsx * gsy), dim3(256), 0, ctx->stream,
+                       reinterpret_cast<const S*>(src), reinterpret_cast<S*>(dst), ctx->geom(), c,
+                       ref_as<typename Store<PREC>::R>(ctx->ref), ctx->eq_order, step, ctx->d_flag, gsx, hs,
+                       reinterpret_cast<S*>(mid));
+}
+
+// The model's widest strips while they give kWideMinStrips strips, else 64 columns.
+template <int MODEL, int PREC, int RING, bool MID>
+void launch_step2_any(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int hs, const void* src, void* mid,
+                      void* dst, int step) {
+    constexpr int WW = strip_width<MODEL, PREC>();
+    if constexpr (WW != kStripW) {
+        const long long strips = (long long)((ctx->nx + WW - 1) / WW) * ((ctx->ny + hs - 1) / hs);
+        if (strips >= kWideMinStrips) {
+            launch_step2_w<MODEL, PREC, RING, WW, MID>(ctx, c, hs, src, mid, dst, step);
+            return;
+        }
+    }
+    launch_step2_w<MODEL, PREC, RING, kStripW, MID>(ctx, c, hs, src, mid, dst, step);
+}
+
+template <int MODEL, int PREC, int RING>
+void launch_step2_r(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int hs, int src_copy) {
+    launch_step2_any<MODEL, PREC, RING, false>(ctx, c, hs, ctx->copy(src_copy), nullptr, ctx->copy(src_copy ^ 1),
+                                               (int)ctx->step);
 }
 
 // Two raw steps src -> dst (ring of 8 rows, strips of hs rows); with mid != NULL the state after
@@ -344,20 +368,10 @@ void launch_step2_r(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int hs
 template <int MODEL, int PREC>
 void launch_step2_raw_t(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int hs, const void* src, void* mid,
                         void* dst, int step) {
-    using S = typename Store<PREC>::S;
-    constexpr int W = strip_width<MODEL, PREC>();
-    const unsigned gsx = (unsigned)((ctx->nx + W - 1) / W);
-    const unsigned gsy = (unsigned)((ctx->ny + hs - 1) / hs);
     if (mid)
-        hipLaunchKernelGGL((k_step2<MODEL, PREC, 8, true>), dim3(gsx * gsy), dim3(256), 0, ctx->stream,
-                           reinterpret_cast<const S*>(src), reinterpret_cast<S*>(dst), ctx->geom(), c,
-                           ref_as<typename Store<PREC>::R>(ctx->ref), ctx->eq_order, step, ctx->d_flag, gsx, hs,
-                           reinterpret_cast<S*>(mid));
+        launch_step2_any<MODEL, PREC, 8, true>(ctx, c, hs, src, mid, dst, step);
     else
-        hipLaunchKernelGGL((k_step2<MODEL, PREC, 8, false>), dim3(gsx * gsy), dim3(256), 0, ctx->stream,
-                           reinterpret_cast<const S*>(src), reinterpret_cast<S*>(dst), ctx->geom(), c,
-                           ref_as<typename Store<PREC>::R>(ctx->ref), ctx->eq_order, step, ctx->d_flag, gsx, hs,
-                           static_cast<S*>(nullptr));
+        launch_step2_any<MODEL, PREC, 8, false>(ctx, c, hs, src, nullptr, dst, step);
 }
 
 template <int PREC>
@@ -559,10 +573,13 @@ int lbm_init_shifted(lbm_ctx** out, int nx, int ny, int prec, int eq_order, doub
     // flight (measured on MI355X; lbm_autotune can revise it)
     for (int k = 0; k < 9; ++k) ctx->rows[k] = prec == LBM_F16_SHIFTED ? 2 : 1;
     const int fstrip = default_fusion_strip(nx, ny, prec);
+    const bool wide_fit = fstrip > 0 && (long long)((nx + 2 * kStripW - 1) / (2 * kStripW)) *
+                                            ((ny + fstrip - 1) / fstrip) >= kWideMinStrips;
     if (fstrip > 0)
         for (int k = 0; k < 9; ++k) {
-            // slot k is model k (slot 8: the pure pull); a ring of 4 rows with wide strips
-            ctx->fuse_ring[k] = wide_strips(k < 8 ? k : LBM_STREAM_ONLY, prec) ? 4 : 8;
+            // slot k is model k (slot 8: the pure pull); a ring of 4 rows where the launch takes
+            // 128-column strips
+            ctx->fuse_ring[k] = (wide_fit && wide_strips(k < 8 ? k : LBM_STREAM_ONLY, prec)) ? 4 : 8;
             ctx->fuse_strip[k] = fstrip;
         }
     int rc = check_hip(hipGetDevice(&ctx->device), "hipGetDevice");

@@ -122,8 +122,10 @@ def test_defaults_and_autotune(gpu):
         s = Sim(rho, ux, uy, prec=prec, device=gpu)
         got = [s.fusion(m) for m in MODELS]
         s.close()
-        # FP32: the models with 128-column strips start with a ring of 4 rows
-        wide = [prec == "f32" and m not in ("CM", "CHM", "K") for m in MODELS]
+        # FP32: the models that get 128-column strips (while these give >= 1024 strips) start with a
+        # ring of 4 rows
+        wide = [prec == "f32" and m not in ("CM", "CHM", "K") and (nx + 127) // 128 * (-(-ny // 16)) >= 1024
+                for m in MODELS]
         exp = [(4, want[1]) if wd and want[0] else want for wd in wide]
         assert got == exp, (nx, ny, prec, got)
     # autotune leaves state and counter alone, keeps a valid choice, and results do not change
@@ -165,3 +167,35 @@ def test_single_step_shapes_agree(gpu):
             if ref is None:
                 ref = st
             np.testing.assert_array_equal(st, ref)
+
+
+def test_wide_strips_bit_identical(gpu):
+    """FP32 BGK-class models take 128-column strips once these give >= 1024 strips: a grid ragged
+    against 128 columns and the strip height, every ring, plain and raw (with the state between)
+    two-step launches against single steps."""
+    import torch
+
+    from paper_2002_05265_amd import binding as B
+
+    nx, ny = 1030, 1100  # 9 x 138 strips of 128 x 8
+    omega = np.array([1.93, 1.2, 1.05, 0.9, 1.4])
+    for model in ("BGK", "RR", "STREAM_ONLY"):
+        for ring, strip, h in ((4, 4, ny), (4, 8, ny), (8, 8, ny), (16, 16, 2 * ny)):
+            assert (nx + 127) // 128 * (-(-h // strip)) >= 1024
+            print(f"wide strips f32 {model} ring {ring} strip {strip} {nx}x{h}", flush=True)
+            sa, sb, (ta, tb) = run_pair(gpu, "f32", model, nx, h, ring, strip, 5, omega, seed=13)
+            np.testing.assert_array_equal(sa, sb)
+            assert ta == tb
+    rho, ux, uy = perturbed(nx, ny, 14)
+    s = Sim(rho, ux, uy, prec="f32", device=gpu)
+    n = B.lbm_state_bytes(s.ctx)
+    # zeroed: the plane padding is never written and must compare equal
+    a, m1, b, c, d = (torch.zeros(n, dtype=torch.uint8, device=gpu) for _ in range(5))
+    B.lbm_save_state(s.ctx, a.data_ptr())
+    code = inputs.MODEL_CODES["PR"]
+    B.lbm_set_fusion(s.ctx, code, 4, 8)
+    B.lbm_step_raw_many(s.ctx, code, omega, [a.data_ptr(), c.data_ptr()], [c.data_ptr(), d.data_ptr()], 0)
+    B.lbm_step2_raw_many(s.ctx, code, omega, [a.data_ptr()], [m1.data_ptr()], [b.data_ptr()], 0)
+    torch.cuda.synchronize()
+    assert torch.equal(m1, c) and torch.equal(b, d)
+    s.close()
