@@ -100,7 +100,13 @@ def cpu_baseline(models, n: int = 4096, rows: int = 2048, steps: int = 1):
         elapsed += time.perf_counter() - t0
         del f
     updates = n * rows * steps * len(models)
-    return {"value": updates / elapsed / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), cpu)
+    except OSError:
+        pass
+    return {"value": updates / elapsed / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle", "host_cpu": cpu,
             "sample": f"{rows} rows x {n} of the {n}x{n} double shear layer (a periodic band of the bench "
                       f"workload), FP64, {steps} step(s) of each of {len(models)} models, {elapsed:.1f} s total"}
 
@@ -751,6 +757,11 @@ def main():
         extra_steps = max(20, args.steps // 2)
         line["precisions"] = {p: time_models(p, n, models, extra_steps, 5, omega, fields) for p in ("f64", "f16")}
         line["small_grids"] = cache_resident_rates(models)
+        # the same grids under the SRT preset (one rate for every non-conserved moment)
+        srt = inputs.rates(nu, "SRT")
+        line["srt_preset"] = {"omega": [round(w, 6) for w in srt],
+                              "mlups": {m: v["mlups"] for m, v in
+                                        time_models(args.prec, n, models, extra_steps, 5, srt, fields).items()}}
         f64_mlups = min(v["mlups"] for v in line["precisions"]["f64"].values())
         line["batched"] = batched_sweep(args.batch_steps, f64_mlups)
         line["adjoint"] = adjoint_run()
