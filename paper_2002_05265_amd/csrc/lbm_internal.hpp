@@ -187,7 +187,13 @@ __device__ __forceinline__ Macro<R> macro_of(const R (&h)[9], const Ref<R>& ref,
     }
     m.jx = ((h[1] + h[5]) + h[8]) - ((h[3] + h[6]) + h[7]);
     m.jy = ((h[2] + h[5]) + h[6]) - ((h[4] + h[7]) + h[8]);
-    m.inv_rho = R(1) / m.rho;
+    // FP32 arithmetic takes the hardware reciprocal (1 ulp; the correctly rounded quotient costs
+    // nine more instructions per node): it scales O(u) quantities only, and every kernel that
+    // collides (plain, batched, adjoint) shares this function, so they stay bit-identical
+    if constexpr (std::is_same<R, float>::value)
+        m.inv_rho = __builtin_amdgcn_rcpf(m.rho);
+    else
+        m.inv_rho = R(1) / m.rho;
     m.dux = (m.jx - m.drho * ref.ux) * m.inv_rho;
     m.duy = (m.jy - m.drho * ref.uy) * m.inv_rho;
     m.ux = ref.ux + m.dux;

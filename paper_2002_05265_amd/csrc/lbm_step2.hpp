@@ -55,6 +55,24 @@ __device__ __forceinline__ void pull_load_l2(const S* __restrict__ src, long lon
     h[8] = R(ld_l2(plane_at(src, plane, 8, rp + xm)));
 }
 
+// A pointer that is the same on every lane of the wave, made explicit (scalar registers, global
+// address space), and an access at a per-lane 32-bit byte offset from it: the global load /
+// store then takes its scalar-base form and needs no per-lane 64-bit address arithmetic.
+template <typename T> struct Global { typedef __attribute__((address_space(1))) T type; };
+
+template <typename T>
+__device__ __forceinline__ T* wave_uniform(T* p) {
+    const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return (T*)(typename Global<T>::type*)(((unsigned long long)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ T* byte_off(T* p, unsigned off) {
+    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return reinterpret_cast<T*>(reinterpret_cast<B*>(p) + off);
+}
+
 // Steps `step` and `step` + 1 of the strip of columns x0 .. x0 + W - 1 and rows ys .. ye - 1
 // of grid g: pulls from src, writes to dst, collides with coll(h, m).  Called by all 256 threads
 // of a workgroup (it contains block barriers); ring is the workgroup's LDS ring.  VIA_L2 selects
@@ -71,12 +89,24 @@ __device__ __forceinline__ void strip_two_steps(S (&ring)[9][RING + 2][W + 2], c
     constexpr int RPW = 4 / WPR;       // rows the block covers at once
     constexpr int KR = RING / RPW;     // rows per wave and pass
     const int lane = (int)(threadIdx.x & 63u);
-    const int wave = (int)(threadIdx.x >> 6);
+    // the wave index is the same on every lane: read it as such, so that rows, ring slots and
+    // row offsets below are scalar arithmetic and not repeated per lane
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int cg = wave % WPR, rl = wave / WPR;
     const int w = min(W, g.nx - x0);           // output columns of this strip
     const int col = cg * 64 + lane;            // this lane's column in the strip
     const int lc = col + 1;                    // and in the ring
     const bool in1 = col < w;
+    // byte offsets of the lane's column and its two neighbours (wrapped), fixed for the strip
+    constexpr unsigned E = sizeof(S);
+    unsigned xo0, xom, xop;
+    {
+        int x = x0 + col;
+        x = x >= g.nx ? x - g.nx : x;
+        xo0 = (unsigned)x * E;
+        xom = (unsigned)(x == 0 ? g.nx - 1 : x - 1) * E;
+        xop = (unsigned)(x == g.nx - 1 ? 0 : x + 1) * E;
+    }
 
     // first step at row a (ys - 1 <= a <= ye, unwrapped) and ring column cc (column
     // x0 - 1 + cc, wrapped): the pull loads, then the collision into the ring
@@ -88,6 +118,31 @@ __device__ __forceinline__ void strip_two_steps(S (&ring)[9][RING + 2][W + 2], c
             pull_load_l2(src, g.plane, neighbours(xw, yw, g.nx, g.ny), h);
         else
             pull_load(src, g.plane, neighbours(xw, yw, g.nx, g.ny), h);
+    };
+    // first step at the lane's own column of row a (the same row on the whole wave): the row
+    // part of each address is a scalar pointer, the column part the lane's fixed offset
+    auto load_own = [&](int a, R (&h)[9]) {
+        const int yw = a < 0 ? a + g.ny : (a >= g.ny ? a - g.ny : a);
+        const long long r0 = (long long)yw * g.nx;
+        const long long rm = yw == 0 ? (long long)(g.ny - 1) * g.nx : r0 - g.nx;
+        const long long rp = yw == g.ny - 1 ? 0 : r0 + g.nx;
+        // the lane offsets are taken afresh here (an empty asm) so that their widening to 64 bits
+        // is not hoisted out of the loop, which would cost a 64-bit vector add per load
+        unsigned o0 = xo0, om = xom, op = xop;
+        asm("" : "+v"(o0), "+v"(om), "+v"(op));
+        auto at = [&](int q, long long r, unsigned xo) { return byte_off(wave_uniform(src + q * g.plane + r), xo); };
+        auto get = [&](const S* p) {
+            if constexpr (VIA_L2) return ld_l2(p); else return ld(p);
+        };
+        h[0] = R(get(at(0, r0, o0)));
+        h[1] = R(get(at(1, r0, om)));
+        h[2] = R(get(at(2, rm, o0)));
+        h[3] = R(get(at(3, r0, op)));
+        h[4] = R(get(at(4, rp, o0)));
+        h[5] = R(get(at(5, rm, om)));
+        h[6] = R(get(at(6, rm, op)));
+        h[7] = R(get(at(7, rp, op)));
+        h[8] = R(get(at(8, rp, om)));
     };
     // ring slot of row a is (a - ys + 1) mod NR; within a pass it is reached from the pass's slot
     // base sb = (yb - ys + 1) mod NR by an offset in [-1, NR), so one conditional wrap suffices
@@ -116,7 +171,7 @@ __device__ __forceinline__ void strip_two_steps(S (&ring)[9][RING + 2][W + 2], c
 #pragma unroll
         for (int k = 0; k < KR; ++k) {
             const int a = yb + 1 + rl + RPW * k;
-            if (a <= top && in1) load(a, lc, hn[k]);
+            if (a <= top && in1) load_own(a, hn[k]);
         }
         if (wave == 3) {
             const int a = yb + 1 + (lane >> 1);
@@ -174,7 +229,12 @@ __device__ __forceinline__ void strip_two_steps(S (&ring)[9][RING + 2][W + 2], c
                 const Macro<R> m = macro_of<S>(h, ref, rho_d);
                 flag_bad(!(rho_d > 0.0), blowup, step + 1);
                 coll(h, m);
-                store_cell<S, R, NT>(dst, g.plane, (unsigned)y * (unsigned)g.nx + (unsigned)(x0 + col), h);
+                const long long r = (long long)y * g.nx + x0;
+                unsigned o = (unsigned)col * E;
+                asm("" : "+v"(o));  // as in load_own
+#pragma unroll
+                for (int i = 0; i < 9; ++i)
+                    st<S, NT>(byte_off(wave_uniform(dst + i * g.plane + r), o), to_store<S>(h[i]));
             }
         }
         __syncthreads();
