@@ -146,21 +146,20 @@ int lbm_set_launch(lbm_ctx* ctx, int model, int rows, int xcd);
 /* Two steps per pass over memory (temporal blocking) for one model (model code, or
  * LBM_STREAM_ONLY): lbm_step then advances two steps per launch, reading and writing each
  * population once per pair of steps instead of twice; an odd last step uses the single-step
- * kernel.  A workgroup owns a strip of columns (128 for the FP32 context's BGK, RM, HM, PR, RR and
- * LBM_STREAM_ONLY when that still gives at least 1024 strips, 64 otherwise) and strip_rows rows and
- * walks down it
- * ring_rows rows at a time, keeping the first step's values of ring_rows + 2 rows (and one halo
- * column each side) in LDS; the halo nodes are collided by both strips that need them.
+ * kernel.  A workgroup owns a strip of columns (128 for an FP32 context when that still gives at
+ * least 1024 strips, 64 otherwise) and strip_rows rows and walks down it ring_rows rows at a time,
+ * keeping the first step's values of ring_rows + 2 rows (and one halo column each side) in LDS;
+ * the halo nodes are collided by both strips that need them.
  *   ring_rows   0 (off), 4, 8 or 16
  *   strip_rows  positive multiple of ring_rows (ignored when ring_rows is 0)
- * A new context starts, for every model, with ring_rows 8 (4 for the FP32 models that get 128-column
- * strips) and strip_rows
+ * A new context starts with ring_rows 8 and strip_rows
  *   FP32: 16 if that gives at least 256 strips, else off;
  *   FP64: 64 if that gives at least 1024 strips, else as FP32;
- *   FP16: 64 if that gives at least 1024 strips, else off.
- * Results are bit-identical
- * to single steps (same arithmetic per node; the LDS ring holds the stored type).  Returns
- * LBM_EINVAL for other values. */
+ *   FP16: 40 if that gives at least 1024 strips, else off;
+ * except where an FP32 model's measured best setting on 128-column strips, (ring_rows, strip_rows)
+ * = (8, 8) for BGK and (4, 20) for the others, gives at least 1024 such strips: it starts with that.
+ * Results are bit-identical to single steps (same arithmetic per node; the LDS ring holds the
+ * stored type).  Returns LBM_EINVAL for other values. */
 int lbm_set_fusion(lbm_ctx* ctx, int model, int ring_rows, int strip_rows);
 
 /* The two-step setting of `model` (host pointers, either may be NULL; ring_rows 0 = off). */
@@ -168,8 +167,8 @@ int lbm_get_fusion(lbm_ctx* ctx, int model, int* ring_rows, int* strip_rows);
 
 /* Autotune the launches of `model` on this context's grid: every single-step shape
  * (rows in {1, 2, 4} x xcd in {0, 1}) and the two-step shapes (ring_rows, strip_rows) in
- * {(8, 16), (8, 32), (8, 64), (16, 16), (4, 16), (4, 64)} are timed with HIP events over `trials` (>= 1)
- * launches that recompute from the same input copy, so the state and the step counter are
+ * {(8, 8), (8, 16), (8, 40), (8, 64), (16, 16), (4, 16), (4, 20), (4, 64)} are timed with HIP events
+ * over `trials` (>= 1) launches that recompute from the same input copy, so the state and the step counter are
  * unchanged.  The fastest single-step shape is kept (it also takes an odd last step) and
  * returned through rows_out / xcd_out; two steps per launch are kept (lbm_get_fusion) when a
  * two-step shape beats it per step, and switched off otherwise.  us_per_step is the best time

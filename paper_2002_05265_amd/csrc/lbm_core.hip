@@ -142,23 +142,32 @@ __global__ __launch_bounds__(256) void k_step(const typename Store<PREC>::S* __r
 // Strip height a new context starts with (ring of 8 rows), 0 for single steps.  Measured on
 // MI355X (CM, double shear layer): two steps per launch win in FP32 and FP64 from 512^2 up
 // (strips of 16 rows: 256 blocks at 512^2), and in FP16, whose step is bound by arithmetic
-// rather than bytes, only once strips of 64 rows still give 1024 blocks (2048^2 and up); FP64
-// takes strips of 64 rows when they give 1024 blocks.
+// rather than bytes, only once strips of 40 rows still give 1024 blocks (2048^2 and up); FP64
+// takes strips of 64 rows when they give 1024 blocks.  (At 4096^2 FP16 runs 1-5% faster on
+// 40-row strips than on 32 or 64: strip starts a power-of-two number of rows apart put the
+// concurrently running strips at addresses a large power of two apart.)
 int default_fusion_strip(int nx, int ny, int prec) {
     const long long sx = (nx + kStripW - 1) / kStripW;
-    const long long s16 = sx * ((ny + 15) / 16), s64 = sx * ((ny + 63) / 64);
-    if (prec == LBM_F16_SHIFTED) return s64 >= 1024 ? 64 : 0;
+    const long long s16 = sx * ((ny + 15) / 16), s40 = sx * ((ny + 39) / 40), s64 = sx * ((ny + 63) / 64);
+    if (prec == LBM_F16_SHIFTED) return s40 >= 1024 ? 40 : 0;
     if (prec == LBM_F64 && s64 >= 1024) return 64;
     return s16 >= 256 ? 16 : 0;
 }
 
-// Strip width of the two-step kernel for a model and precision.  Measured at 4096^2: in FP32 the
-// models whose two-step kernel is not ALU-bound (BGK, RM, HM, PR, RR, the pure pull) gain 5% from
-// strips of 128 columns (two waves per row: half the edge lines and halo nodes per column) with a
-// ring of 4 rows; CM, CHM and K (vector ALU saturated), FP64 and FP16 do not, and keep 64.
-constexpr bool wide_strips(int model, int prec) {
-    return prec == LBM_F32_SHIFTED && model != LBM_CM && model != LBM_CHM && model != LBM_K;
-}
+// Strip width of the two-step kernel for a model and precision.  Measured at 4096^2: in FP32 every
+// model gains from strips of 128 columns (two waves per row: half the edge lines and halo nodes
+// per column), 2-5% over 64 columns; FP64 (bandwidth-bound on 64-row strips) and FP16 (bound by
+// arithmetic) do not, and keep 64.
+constexpr bool wide_strips(int /*model*/, int prec) { return prec == LBM_F32_SHIFTED; }
+
+// (ring rows, strip rows) a new context starts with on 128-column strips, measured at 4096^2 in
+// FP32: a ring of 4 rows on 20-row strips for every model but BGK, whose light collision gains
+// most from one pass of a ring of 8 rows per 8-row strip (1-2% over 16-row strips, which start a
+// power of two apart; see default_fusion_strip).
+struct FusionPick {
+    int ring, strip;
+};
+constexpr FusionPick wide_default(int model) { return model == LBM_BGK ? FusionPick{8, 8} : FusionPick{4, 20}; }
 
 // Widest strip for a model and precision; the launch uses it only while it still gives at least
 // kWideMinStrips strips (otherwise 64 columns keep enough workgroups in flight on small grids).
@@ -573,14 +582,16 @@ int lbm_init_shifted(lbm_ctx** out, int nx, int ny, int prec, int eq_order, doub
     // flight (measured on MI355X; lbm_autotune can revise it)
     for (int k = 0; k < 9; ++k) ctx->rows[k] = prec == LBM_F16_SHIFTED ? 2 : 1;
     const int fstrip = default_fusion_strip(nx, ny, prec);
-    const bool wide_fit = fstrip > 0 && (long long)((nx + 2 * kStripW - 1) / (2 * kStripW)) *
-                                            ((ny + fstrip - 1) / fstrip) >= kWideMinStrips;
     if (fstrip > 0)
         for (int k = 0; k < 9; ++k) {
-            // slot k is model k (slot 8: the pure pull); a ring of 4 rows where the launch takes
-            // 128-column strips
-            ctx->fuse_ring[k] = (wide_fit && wide_strips(k < 8 ? k : LBM_STREAM_ONLY, prec)) ? 4 : 8;
-            ctx->fuse_strip[k] = fstrip;
+            // slot k is model k (slot 8: the pure pull); 128-column strips where they give at
+            // least kWideMinStrips strips (the launch takes them then)
+            const int model = k < 8 ? k : LBM_STREAM_ONLY;
+            const FusionPick w = wide_default(model);
+            const bool wide = wide_strips(model, prec) && (long long)((nx + 2 * kStripW - 1) / (2 * kStripW)) *
+                                                                  ((ny + w.strip - 1) / w.strip) >= kWideMinStrips;
+            ctx->fuse_ring[k] = wide ? w.ring : 8;
+            ctx->fuse_strip[k] = wide ? w.strip : fstrip;
         }
     int rc = check_hip(hipGetDevice(&ctx->device), "hipGetDevice");
     if (rc == LBM_OK) rc = check_hip(hipMalloc(&ctx->d_flag, sizeof(int)), "hipMalloc(flag)");
@@ -802,9 +813,9 @@ int lbm_autotune(lbm_ctx* ctx, int model, const double* omega, int trials, int* 
             }
         }
     // two-step shapes, per step
-    const int fuse_c[6][2] = {{8, 16}, {8, 32}, {8, 64}, {16, 16}, {4, 16}, {4, 64}};
+    const int fuse_c[8][2] = {{8, 8}, {8, 16}, {8, 40}, {8, 64}, {16, 16}, {4, 16}, {4, 20}, {4, 64}};
     int best_ring = 0, best_strip = 0;
-    for (int k = 0; k < 6 && rc == LBM_OK; ++k) {
+    for (int k = 0; k < 8 && rc == LBM_OK; ++k) {
         const int ring = fuse_c[k][0], hs = fuse_c[k][1];
         const float ms = 0.5f * timed([&] { LBM_DISPATCH_PREC(ctx->prec, launch_step2_p, ctx, model, omega, ring, hs, ctx->cur); });
         if (rc == LBM_OK && ms < best) {

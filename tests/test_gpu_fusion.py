@@ -115,18 +115,20 @@ def test_rejects_bad_shapes(gpu):
 def test_defaults_and_autotune(gpu):
     # a new context's two-step setting follows the strip counts (include/lbm.h)
     for (nx, ny, prec), want in {(2048, 2048, "f32"): (8, 16), (2048, 2048, "f64"): (8, 64),
-                                 (4096, 1024, "f16"): (8, 64), (512, 512, "f32"): (8, 16),
+                                 (4096, 1024, "f16"): (8, 40), (512, 512, "f32"): (8, 16),
                                  (256, 256, "f32"): (0, 0), (2048, 1000, "f64"): (8, 16),
-                                 (512, 512, "f16"): (0, 0), (448, 512, "f64"): (0, 0)}.items():
+                                 (512, 512, "f16"): (0, 0), (448, 512, "f64"): (0, 0),
+                                 (2048, 1024, "f32"): (8, 16), (1024, 2048, "f32"): (8, 16)}.items():
         rho, ux, uy = np.ones((ny, nx)), np.zeros((ny, nx)), np.zeros((ny, nx))
         s = Sim(rho, ux, uy, prec=prec, device=gpu)
         got = [s.fusion(m) for m in MODELS]
         s.close()
-        # FP32: the models that get 128-column strips (while these give >= 1024 strips) start with a
-        # ring of 4 rows
-        wide = [prec == "f32" and m not in ("CM", "CHM", "K") and (nx + 127) // 128 * (-(-ny // 16)) >= 1024
-                for m in MODELS]
-        exp = [(4, want[1]) if wd and want[0] else want for wd in wide]
+        # FP32 models start with their 128-column setting where it gives >= 1024 strips
+        exp = []
+        for m in MODELS:
+            wr, ws = (8, 8) if m == "BGK" else (4, 20)
+            wide = prec == "f32" and want[0] and (nx + 127) // 128 * (-(-ny // ws)) >= 1024
+            exp.append((wr, ws) if wide else want)
         assert got == exp, (nx, ny, prec, got)
     # autotune leaves state and counter alone, keeps a valid choice, and results do not change
     nx, ny = 1024, 512
@@ -141,7 +143,7 @@ def test_defaults_and_autotune(gpu):
     ring, strip = a.fusion("RR")
     print(f"autotune 1024x512 RR: rows {rows} xcd {xcd} ring {ring} strip {strip} {us:.1f} us/step", flush=True)
     assert rows in (1, 2, 4) and xcd in (0, 1) and us > 0
-    assert (ring, strip) in ((0, 0), (8, 16), (8, 32), (8, 64), (16, 16), (4, 16), (4, 64))
+    assert (ring, strip) in ((0, 0), (8, 8), (8, 16), (8, 40), (8, 64), (16, 16), (4, 16), (4, 20), (4, 64))
     np.testing.assert_array_equal(a.state().cpu().numpy(), before)
     assert a.status() == (3, -1)
     a.step("RR", omega, 9)
@@ -170,7 +172,7 @@ def test_single_step_shapes_agree(gpu):
 
 
 def test_wide_strips_bit_identical(gpu):
-    """FP32 BGK-class models take 128-column strips once these give >= 1024 strips: a grid ragged
+    """FP32 models take 128-column strips once these give >= 1024 strips: a grid ragged
     against 128 columns and the strip height, every ring, plain and raw (with the state between)
     two-step launches against single steps."""
     import torch
@@ -179,7 +181,7 @@ def test_wide_strips_bit_identical(gpu):
 
     nx, ny = 1030, 1100  # 9 x 138 strips of 128 x 8
     omega = np.array([1.93, 1.2, 1.05, 0.9, 1.4])
-    for model in ("BGK", "RR", "STREAM_ONLY"):
+    for model in ("BGK", "K", "RR", "STREAM_ONLY"):
         for ring, strip, h in ((4, 4, ny), (4, 8, ny), (8, 8, ny), (16, 16, 2 * ny)):
             assert (nx + 127) // 128 * (-(-h // strip)) >= 1024
             print(f"wide strips f32 {model} ring {ring} strip {strip} {nx}x{h}", flush=True)
