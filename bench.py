@@ -25,7 +25,7 @@ PROFILE_DIR = os.path.join(ROOT, "profiles")
 # while these are unchanged since the counters were taken
 STEP_SOURCES = ("paper_2002_05265_amd/csrc/lbm_core.hip", "paper_2002_05265_amd/csrc/lbm_cell.hpp",
                 "paper_2002_05265_amd/csrc/lbm_internal.hpp", "paper_2002_05265_amd/csrc/lbm_step2.hpp",
-                "paper_2002_05265_amd/build.py")
+                "paper_2002_05265_amd/csrc/lbm_step3.hpp", "paper_2002_05265_amd/build.py")
 MODEL_ORDER = ("BGK", "RM", "HM", "CM", "CHM", "K", "PR", "RR")
 PREC_CODE = {"f64": 0, "f32": 1, "f16": 2}
 
@@ -45,15 +45,27 @@ def step_source_hash() -> str:
 
 
 def step_kernel_keys(model: str, prec: str):
-    """(label, name prefix in a kernel trace) of the two-step and the single-step kernel."""
+    """(label, name prefix in a kernel trace) of the three-, two- and single-step kernel."""
     args = f"{MODEL_ORDER.index(model)}, {PREC_CODE[prec]}, "
-    return [("k_step2", f"k_step2<{args}"), ("k_step", f"k_step<{args}")]
+    return [("k_step3", f"k_step3<{args}"), ("k_step2", f"k_step2<{args}"), ("k_step", f"k_step<{args}")]
+
+
+def launch_steps(sim, model: str) -> int:
+    """Steps one launch of `model` advances on `sim`: 3, 2 or 1."""
+    ring = sim.fusion(model)[0]
+    if not ring:
+        return 1
+    return 3 if sim.fusion_depth(model) == 3 and ring in (4, 8) else 2
+
+
+def profile_path(prec: str, kind: str) -> str:
+    return os.path.join(PROFILE_DIR, f"step_kernels_{prec}_dsl4096_{kind}.md")
 
 
 def measured_traffic(model: str, prec: str):
     """HBM bytes per launch of the step kernel from the committed counter summary, or None when
     there is none for this kernel or its sources changed since it was taken."""
-    path = os.path.join(PROFILE_DIR, f"k_step2_{prec}_dsl4096_counters.md")
+    path = profile_path(prec, "counters")
     try:
         with open(path) as fh:
             text = fh.read()
@@ -70,7 +82,7 @@ def measured_valu_busy(model: str, prec: str):
     """Fraction of the vector-ALU issue capacity the step kernel used (rocprofv3 VALUBusy) from the
     committed counter summary, or None when there is none for this kernel or its sources changed
     since it was taken."""
-    path = os.path.join(PROFILE_DIR, f"k_step2_{prec}_dsl4096_counters.md")
+    path = profile_path(prec, "counters")
     try:
         with open(path) as fh:
             text = fh.read()
@@ -166,7 +178,7 @@ def time_models(prec: str, n: int, models, steps: int, warmup: int, omega, field
         e1.record()
         torch.cuda.synchronize()
         us = e0.elapsed_time(e1) * 1e3 / steps
-        spl = 2 if s.fusion(m)[0] else 1
+        spl = launch_steps(s, m)
         mlups = n * n / us
         gbs = mlups * 1e6 * bytes_per_cell(prec) / spl / 1e9
         out[m] = {"mlups": round(mlups, 1), "us_per_step": round(us, 2), "steps_per_launch": spl,
@@ -485,11 +497,12 @@ def profile_summary(out_root: str, prec: str, n: int, commands: dict):
     stats = _csv_rows(_find_csv(os.path.join(out_root, "rp_trace"), "kernel_stats.csv"))
     cells = n * n
     alg = cells * bytes_per_cell(prec)
-    lines = [f"# k_step2 / k_step ({prec}, {n}x{n} double shear layer): kernel trace", "",
+    lines = [f"# k_step3 / k_step2 / k_step ({prec}, {n}x{n} double shear layer): kernel trace", "",
              "Command (from the repository root, with `cd /tmp && export TMPDIR=/tmp` semantics for",
              "the profiler's scratch files):", "", "```", commands["trace"], "```", "",
              f"Algorithmic bytes per launch: {n}*{n} nodes * 18 * {bytes_per_cell(prec) // 18} B = {alg} B "
-             "(every population read and written once; k_step2 advances two steps per launch, k_step one).",
+             "(every population read and written once; k_step3 advances three steps per launch, k_step2 "
+             "two, k_step one).",
              "", "| kernel | calls | average us | min us | max us | GB/s at algorithmic bytes |",
              "|---|---|---|---|---|---|"]
     for r in stats:
@@ -504,7 +517,7 @@ def profile_summary(out_root: str, prec: str, n: int, commands: dict):
                     short = f"{label}<{m}, {prec}>"
         lines.append(f"| {short} | {r['Calls']} | {avg:.2f} | {float(r['MinNs']) * 1e-3:.2f} | "
                      f"{float(r['MaxNs']) * 1e-3:.2f} | {gbs} |")
-    with open(os.path.join(PROFILE_DIR, f"k_step2_{prec}_dsl4096_trace.md"), "w") as fh:
+    with open(profile_path(prec, "trace"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
     fetch = _csv_rows(_find_csv(os.path.join(out_root, "rp_fetch"), "counter_collection.csv"))
@@ -522,7 +535,8 @@ def profile_summary(out_root: str, prec: str, n: int, commands: dict):
     rows = ["| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) | / algorithmic | VALUBusy % |",
             "|---|---|---|---|---|---|---|"]
     for m in MODEL_ORDER:
-        # the first kernel of the model found (two-step before single-step) is the one reported
+        # the first kernel of the model found (three-step, then two-step, then single-step) is the
+        # one reported
         for label, key in step_kernel_keys(m, prec):
             f_kib, nf = _per_dispatch(fetch, key)
             w_kib, _ = _per_dispatch(write, key)
@@ -538,7 +552,7 @@ def profile_summary(out_root: str, prec: str, n: int, commands: dict):
     blob = {"step_source_hash": step_source_hash(), "prec": prec, "n": n, "algorithmic_bytes": alg,
             "copy_probe_kib": {"fetch": round(cf, 1), "write": round(cw, 1), "true": gib_kib},
             "scale": {"fetch": round(fscale, 4), "write": round(wscale, 4)}, "per_launch": per_launch}
-    text = [f"# k_step2 / k_step ({prec}, {n}x{n} double shear layer): HBM counters", "",
+    text = [f"# k_step3 / k_step2 / k_step ({prec}, {n}x{n} double shear layer): HBM counters", "",
             "Commands (each counter in a run of its own):", "", "```", commands["fetch"], commands["write"],
             commands["copy_fetch"], commands["copy_write"], commands["valu"], "```", "",
             "VALUBusy is rocprofv3's derived counter 100 * SQ_ACTIVE_INST_VALU / CUs / GRBM_GUI_ACTIVE: the "
@@ -550,7 +564,7 @@ def profile_summary(out_root: str, prec: str, n: int, commands: dict):
             f"WRITE_SIZE by {wscale:.4f}.", "", *rows, "",
             "Machine-readable (bench.py reports `roofline.traffic` from this block while the step "
             "kernel's sources hash to `step_source_hash`):", "", "```json", json.dumps(blob, indent=1), "```", ""]
-    with open(os.path.join(PROFILE_DIR, f"k_step2_{prec}_dsl4096_counters.md"), "w") as fh:
+    with open(profile_path(prec, "counters"), "w") as fh:
         fh.write("\n".join(text))
     print(json.dumps(blob), flush=True)
 
@@ -690,7 +704,7 @@ def main():
     for m in models:
         ms = ev[m][0].elapsed_time(ev[m][1])
         ring, strip = sims[m].fusion(m)
-        spl = 2 if ring else 1
+        spl = launch_steps(sims[m], m)
         mlups = cells * args.steps / (ms * 1e-3) / 1e6
         gbs = mlups * 1e6 * bpc / spl / 1e9
         per_model[m] = {"mlups": round(mlups, 1), "us_per_step": round(ms * 1e3 / args.steps, 2),
@@ -704,7 +718,7 @@ def main():
     ref_sim.step("STREAM_ONLY", omega, args.steps)
     ev1.record()
     torch.cuda.synchronize()
-    stream_launch_us = ev0.elapsed_time(ev1) * 1e3 / args.steps * (2 if ref_sim.fusion("STREAM_ONLY")[0] else 1)
+    stream_launch_us = ev0.elapsed_time(ev1) * 1e3 / args.steps * launch_steps(ref_sim, "STREAM_ONLY")
     single = single_step_rates(sims, models, omega, cells, bpc, max(10, args.steps // 10))
     value = cells * args.steps * len(models) / wall / 1e6
     dominant = max(models, key=lambda m: per_model[m]["us_per_step"])
@@ -713,7 +727,7 @@ def main():
     achieved = cells * bpc / (launch_us * 1e-6) / 1e9
     traffic = measured_traffic(dominant, args.prec) if n == 4096 else None
     valu_busy = measured_valu_busy(dominant, args.prec) if n == 4096 else None
-    kname = "k_step2" if spl == 2 else "k_step"
+    kname = {3: "k_step3", 2: "k_step2", 1: "k_step"}[spl]
     line = {
         "metric": "MLUPS per collision model at 4096^2 FP32 + % HBM roofline; adjoint/batched vs plain",
         "value": round(value, 1),

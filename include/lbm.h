@@ -157,7 +157,9 @@ int lbm_set_launch(lbm_ctx* ctx, int model, int rows, int xcd);
  *   FP64: 64 if that gives at least 1024 strips, else as FP32;
  *   FP16: 40 if that gives at least 1024 strips, else off;
  * except where an FP32 model's measured best setting on 128-column strips, (ring_rows, strip_rows)
- * = (8, 8) for BGK and (4, 20) for the others, gives at least 1024 such strips: it starts with that.
+ * = (8, 8) for BGK and (4, 20) for the others, gives at least 1024 such strips: it starts with that;
+ * and an FP32 or FP64 context whose 64-column strips of 60 rows number at least 2048 starts every
+ * model with three steps per launch (lbm_set_fusion_depth), ring_rows 4 and strip_rows 60.
  * Results are bit-identical to single steps (same arithmetic per node; the LDS ring holds the
  * stored type).  Returns LBM_EINVAL for other values. */
 int lbm_set_fusion(lbm_ctx* ctx, int model, int ring_rows, int strip_rows);
@@ -165,14 +167,27 @@ int lbm_set_fusion(lbm_ctx* ctx, int model, int ring_rows, int strip_rows);
 /* The two-step setting of `model` (host pointers, either may be NULL; ring_rows 0 = off). */
 int lbm_get_fusion(lbm_ctx* ctx, int model, int* ring_rows, int* strip_rows);
 
+/* Steps per fused launch of `model`: 2 (the default) or 3.  With 3, and ring_rows 4 or 8 set by
+ * lbm_set_fusion, lbm_step advances three steps per launch (then pairs, then single steps): a
+ * second LDS ring holds the second step's values, so each population is read and written once per
+ * three steps; the first step covers two halo rows and columns on each side of the strip, the
+ * second one.  Strips are 64 columns wide.  Bit-identical to single steps.  LBM_EUNSUPPORTED for 3 on an FP16 context or on a grid
+ * narrower or lower than 2; LBM_EINVAL for other values. */
+int lbm_set_fusion_depth(lbm_ctx* ctx, int model, int steps);
+
+/* Steps per fused launch of `model` (host pointer, may be NULL). */
+int lbm_get_fusion_depth(lbm_ctx* ctx, int model, int* steps);
+
 /* Autotune the launches of `model` on this context's grid: every single-step shape
- * (rows in {1, 2, 4} x xcd in {0, 1}) and the two-step shapes (ring_rows, strip_rows) in
- * {(8, 8), (8, 16), (8, 40), (8, 64), (16, 16), (4, 16), (4, 20), (4, 64)} are timed with HIP events
- * over `trials` (>= 1) launches that recompute from the same input copy, so the state and the step counter are
- * unchanged.  The fastest single-step shape is kept (it also takes an odd last step) and
- * returned through rows_out / xcd_out; two steps per launch are kept (lbm_get_fusion) when a
- * two-step shape beats it per step, and switched off otherwise.  us_per_step is the best time
- * per step.  Host pointers, each may be NULL.  Synchronises. */
+ * (rows in {1, 2, 4} x xcd in {0, 1}), the two-step shapes (ring_rows, strip_rows) in
+ * {(8, 8), (8, 16), (8, 40), (8, 64), (16, 16), (4, 16), (4, 20), (4, 64)} and, except for FP16,
+ * the three-step shapes {(4, 20), (4, 40), (4, 60), (4, 80), (8, 40), (8, 64)} are timed with HIP
+ * events over `trials` (>= 1) launches that recompute from the same input copy, so the state, the
+ * step counter and the blow-up record are unchanged.  The fastest single-step shape is kept (it
+ * also takes the last steps that do not fill a fused launch) and returned through rows_out /
+ * xcd_out; the fastest fused shape per step is kept (lbm_get_fusion, lbm_get_fusion_depth) when it
+ * beats it, and fusion is switched off otherwise.  us_per_step is the best time per step.  Host
+ * pointers, each may be NULL.  Synchronises. */
 int lbm_autotune(lbm_ctx* ctx, int model, const double* omega, int trials, int* rows_out,
                  int* xcd_out, double* us_per_step);
 

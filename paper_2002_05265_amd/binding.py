@@ -23,8 +23,8 @@ STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_EUNSUPPORTED", -3: "LBM_EHIP",
 # every symbol declared in include/*.h
 EXPORTS = (
     "lbm_population_bytes", "lbm_init", "lbm_init_shifted", "lbm_step", "lbm_moments", "lbm_status",
-    "lbm_get_state", "lbm_set_state", "lbm_set_launch", "lbm_set_fusion", "lbm_get_fusion", "lbm_autotune", "lbm_destroy",
-    "lbm_last_error",
+    "lbm_get_state", "lbm_set_state", "lbm_set_launch", "lbm_set_fusion", "lbm_get_fusion",
+    "lbm_set_fusion_depth", "lbm_get_fusion_depth", "lbm_autotune", "lbm_destroy", "lbm_last_error",
     "lbm_batch_population_bytes", "lbm_batch_create", "lbm_batch_run", "lbm_batch_status",
     "lbm_batch_get_state", "lbm_batch_mean_u2", "lbm_batch_set_active", "lbm_batch_rebalance",
     "lbm_batch_set_launch", "lbm_batch_set_fusion", "lbm_batch_get_fusion",
@@ -74,6 +74,8 @@ def _declare(L: ctypes.CDLL):
         "lbm_set_launch": (_i, [_vp, _i, _i, _i]),
         "lbm_set_fusion": (_i, [_vp, _i, _i, _i]),
         "lbm_get_fusion": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
+        "lbm_set_fusion_depth": (_i, [_vp, _i, _i]),
+        "lbm_get_fusion_depth": (_i, [_vp, _i, ctypes.POINTER(_i)]),
         "lbm_autotune": (_i, [_vp, _i, _dp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), _dp]),
         "lbm_destroy": (None, [_vp]),
         "lbm_last_error": (ctypes.c_char_p, []),
@@ -198,6 +200,16 @@ def lbm_set_launch(ctx: int, model: int, rows: int, xcd: int):
 
 def lbm_set_fusion(ctx: int, model: int, ring_rows: int, strip_rows: int):
     _check(lib().lbm_set_fusion(ctx, model, ring_rows, strip_rows), "lbm_set_fusion")
+
+
+def lbm_set_fusion_depth(ctx: int, model: int, steps: int):
+    _check(lib().lbm_set_fusion_depth(ctx, model, steps), "lbm_set_fusion_depth")
+
+
+def lbm_get_fusion_depth(ctx: int, model: int) -> int:
+    steps = _i(0)
+    _check(lib().lbm_get_fusion_depth(ctx, model, ctypes.byref(steps)), "lbm_get_fusion_depth")
+    return steps.value
 
 
 def lbm_get_fusion(ctx: int, model: int):

@@ -328,6 +328,7 @@ struct lbm_ctx {
 
     int fuse_ring[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // two steps per pass: ring rows (0 = off)
     int fuse_strip[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // and strip height, per model
+    int fuse_depth[9] = {2, 2, 2, 2, 2, 2, 2, 2, 2};  // steps per fused launch (2 or 3)
 
     static int slot(int model) { return (model >= 0 && model < 8) ? model : 8; }
     lbm::StepShape shape_of(int model) const {

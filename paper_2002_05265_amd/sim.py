@@ -56,6 +56,13 @@ class Sim:
         """Two steps per launch (ring_rows 4, 8 or 16, strip_rows a multiple of it); 0 turns it off."""
         B.lbm_set_fusion(self.ctx, _model_code(model), ring_rows, strip_rows)
 
+    def set_fusion_depth(self, model, steps: int):
+        """Steps per fused launch of `model`: 2 or 3 (FP32, FP64; with ring_rows 4 or 8)."""
+        B.lbm_set_fusion_depth(self.ctx, _model_code(model), steps)
+
+    def fusion_depth(self, model) -> int:
+        return B.lbm_get_fusion_depth(self.ctx, _model_code(model))
+
     def fusion(self, model):
         """(ring_rows, strip_rows) of `model`'s two-step launches, (0, 0) when off."""
         return B.lbm_get_fusion(self.ctx, _model_code(model))

@@ -1,6 +1,6 @@
 """Parity at the benchmark's full size and launch configuration (4096 x 4096 double shear
-layer, the same Sim / lbm_step path bench.py times: a new context's default of two steps per
-launch, then one single step), on sampled nodes.
+layer, the same Sim / lbm_step path bench.py times: a new context's default of three steps per
+launch in FP32 and FP64, here one such launch and then a two-step one), on sampled nodes.
 
 After k steps a node depends only on nodes within distance k (one lattice link per step), so
 the oracle recomputes a sampled node exactly from a (2k + 3)^2 patch of the analytic initial
@@ -51,7 +51,8 @@ def test_fullsize_sampled(gpu, prec, tol):
     for model in inputs.MODEL_NAMES:
         print(f"full size {prec} {model}", flush=True)
         sim = Sim(*fields, prec=prec, eq_order=4, device=gpu)
-        assert sim.fusion(model)[0] > 0  # the two-step kernel is the one timed at this size
+        # the three-step kernel is the one timed at this size
+        assert sim.fusion(model)[0] > 0 and sim.fusion_depth(model) == 3
         t0 = sim.totals()
         sim.step(model, omega, STEPS)
         state = sim.state()

@@ -122,6 +122,7 @@ def test_defaults_and_autotune(gpu):
         rho, ux, uy = np.ones((ny, nx)), np.zeros((ny, nx)), np.zeros((ny, nx))
         s = Sim(rho, ux, uy, prec=prec, device=gpu)
         got = [s.fusion(m) for m in MODELS]
+        assert all(s.fusion_depth(m) == 2 for m in MODELS)  # below 2048 strips of 64 x 60
         s.close()
         # FP32 models start with their 128-column setting where it gives >= 1024 strips
         exp = []
@@ -130,6 +131,13 @@ def test_defaults_and_autotune(gpu):
             wide = prec == "f32" and want[0] and (nx + 127) // 128 * (-(-ny // ws)) >= 1024
             exp.append((wr, ws) if wide else want)
         assert got == exp, (nx, ny, prec, got)
+    # three steps per launch from 2048 strips of 64 x 60 on (FP32, FP64; not FP16)
+    for (nx, ny, prec), deep in {(4096, 4096, "f32"): True, (4096, 1920, "f64"): True, (4096, 1860, "f32"): False,
+                                 (4096, 4096, "f16"): False}.items():
+        s = Sim(np.ones((ny, nx)), np.zeros((ny, nx)), np.zeros((ny, nx)), prec=prec, device=gpu)
+        for m in MODELS:
+            assert (s.fusion_depth(m), s.fusion(m)) == ((3, (4, 60)) if deep else (2, s.fusion(m))), (nx, ny, prec, m)
+        s.close()
     # autotune leaves state and counter alone, keeps a valid choice, and results do not change
     nx, ny = 1024, 512
     rho, ux, uy = perturbed(nx, ny, 8)
@@ -143,7 +151,11 @@ def test_defaults_and_autotune(gpu):
     ring, strip = a.fusion("RR")
     print(f"autotune 1024x512 RR: rows {rows} xcd {xcd} ring {ring} strip {strip} {us:.1f} us/step", flush=True)
     assert rows in (1, 2, 4) and xcd in (0, 1) and us > 0
-    assert (ring, strip) in ((0, 0), (8, 8), (8, 16), (8, 40), (8, 64), (16, 16), (4, 16), (4, 20), (4, 64))
+    depth = a.fusion_depth("RR")
+    if depth == 2:
+        assert (ring, strip) in ((0, 0), (8, 8), (8, 16), (8, 40), (8, 64), (16, 16), (4, 16), (4, 20), (4, 64))
+    else:
+        assert depth == 3 and (ring, strip) in ((4, 20), (4, 40), (4, 60), (4, 80), (8, 40), (8, 64))
     np.testing.assert_array_equal(a.state().cpu().numpy(), before)
     assert a.status() == (3, -1)
     a.step("RR", omega, 9)
