@@ -652,8 +652,8 @@ def main():
             extras_trace_summary(args.profile_summary, EXTRAS_PROFILE_COMMAND)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the grid would shard as y-slabs with a one-row halo; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the grid would shard as y-slabs with a one-row halo)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -131,6 +131,26 @@ def test_three_steps_against_oracle(gpu, prec, tol):
     assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) < tol
 
 
+def test_three_steps_need_ring_4_or_8(gpu):
+    # with a ring of 16 rows (or fusion off) a depth of 3 falls back to pairs (or single steps)
+    nx, ny = 100, 90
+    omega = inputs.rates(1e-4, "REG")
+    for ring, strip in ((16, 32), (0, 0)):
+        print(f"depth 3 with ring {ring}", flush=True)
+        rho, ux, uy = perturbed(nx, ny, 5)
+        a = Sim(rho, ux, uy, prec="f32", device=gpu)
+        a.set_fusion("HM", 0)
+        b = Sim(rho, ux, uy, prec="f32", device=gpu)
+        b.set_fusion("HM", ring, strip)
+        b.set_fusion_depth("HM", 3)
+        a.step("HM", omega, 7)
+        b.step("HM", omega, 7)
+        np.testing.assert_array_equal(a.state().cpu().numpy(), b.state().cpu().numpy())
+        assert a.status() == b.status() == (7, -1)
+        a.close()
+        b.close()
+
+
 def test_fusion_depth_errors(gpu):
     rho, ux, uy = perturbed(32, 32, 1)
     s = Sim(rho, ux, uy, prec="f32", device=gpu)
