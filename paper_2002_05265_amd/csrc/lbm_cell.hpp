@@ -122,30 +122,41 @@ __host__ __device__ __forceinline__ Eq<R> hermite_eq(const Macro<R>& m, const Re
     return e;
 }
 
+// Fused multiply-add, rounded once: written out where a product feeds a sum in another
+// statement, so that every kernel (and the host) computes it the same way.
+template <typename R>
+__host__ __device__ __forceinline__ R fmadd(R a, R b, R c) {
+    if constexpr (sizeof(R) == 4)
+        return fmaf(a, b, c);
+    else
+        return fma(a, b, c);
+}
+
 // Post-collision Hermite moments minus the reference's (equilibrium difference + relaxed
 // non-equilibrium part) -> raw-moment differences (eq. HM2RM_Q9, which is linear) -> stored
-// deviations (eq. Q9postCollVDF_RM; the density difference contributes drho w_i).
+// deviations (eq. Q9postCollVDF_RM; the density difference contributes drho w_i).  The pairs of
+// opposite populations share their sums and differences.
 template <typename R>
 __host__ __device__ __forceinline__ void hermite_to_pop(const Macro<R>& m, R a20, R a02, R a11, R a21,
                                                R a12, R a22, R (&h)[9]) {
     using L = Lat<R>;
-    const R M20 = a20, M02 = a02, M11 = a11;
+    const R tr = a20 + a02;
     const R M21 = a21 + L::cs2 * m.jy;
     const R M12 = a12 + L::cs2 * m.jx;
-    const R M22 = a22 + L::cs2 * (a20 + a02);
-    const R r0 = m.drho * L::w0, r1 = m.drho * L::w1, r5 = m.drho * L::w5;
-    const R hx = R(0.5) * (M20 - M22), hy = R(0.5) * (M02 - M22);
-    const R px = R(0.5) * (m.jx - M12), py = R(0.5) * (m.jy - M21);
-    h[0] = r0 + (M22 - (M20 + M02));
-    h[1] = r1 + hx + px;
-    h[3] = r1 + hx - px;
-    h[2] = r1 + hy + py;
-    h[4] = r1 + hy - py;
-    const R q = R(0.25) * M22, s11 = R(0.25) * M11, s12 = R(0.25) * M12, s21 = R(0.25) * M21;
-    h[5] = r5 + (q + s11) + (s12 + s21);
-    h[6] = r5 + (q - s11) + (s21 - s12);
-    h[7] = r5 + (q + s11) - (s12 + s21);
-    h[8] = r5 + (q - s11) + (s12 - s21);
+    const R M22 = a22 + L::cs2 * tr;
+    const R r1 = m.drho * L::w1, r5 = m.drho * L::w5;
+    h[0] = fmadd(m.drho, L::w0, M22 - tr);
+    const R u = a20 - M22, v = m.jx - M12;  // 2 (h1 - r1), 2 (h3 - r1) = u + v, u - v
+    const R p = a02 - M22, q = m.jy - M21;
+    h[1] = fmadd(R(0.5), u + v, r1);
+    h[3] = fmadd(R(0.5), u - v, r1);
+    h[2] = fmadd(R(0.5), p + q, r1);
+    h[4] = fmadd(R(0.5), p - q, r1);
+    const R A = M22 + a11, B = M22 - a11, C = M12 + M21, D = M12 - M21;
+    h[5] = fmadd(R(0.25), A + C, r5);
+    h[6] = fmadd(R(0.25), B - D, r5);
+    h[7] = fmadd(R(0.25), A - C, r5);
+    h[8] = fmadd(R(0.25), B + D, r5);
 }
 
 // Hermite non-equilibrium moments d_pq = A_pq - A^eq_pq of the shifted populations.
