@@ -170,12 +170,12 @@ struct FusionPick {
 };
 constexpr FusionPick wide_default(int model) { return model == LBM_BGK ? FusionPick{8, 8} : FusionPick{4, 20}; }
 
-// Three steps per launch for a new FP32 or FP64 context while 64-column strips of 60 rows (ring of
-// 4 rows) give at least kDeepMinStrips strips, measured at 4096^2: FP32 +21% (BGK) and +15% (K)
-// over the best two-step launch, FP64 +11%.  Taller strips leave too few workgroups to balance the
-// tail; 60 rows are not a power of two apart (see default_fusion_strip).
+// Three steps per launch for a new FP32 or FP64 context while 64-column strips of 80 rows (ring of
+// 4 rows) give at least kDeepMinStrips strips, measured at 4096^2: FP32 +27% (BGK) and +22% (K)
+// over the best two-step launch, FP64 +10%.  80-row strips measured 1-2% faster than 60-row ones
+// in FP32 (the same in FP64); taller ones leave too few workgroups to balance the tail.
 constexpr long long kDeepMinStrips = 2048;
-constexpr int kDeepRing = 4, kDeepStrip = 60;
+constexpr int kDeepRing = 4, kDeepStrip = 80;
 
 // Widest strip for a model and precision; the launch uses it only while it still gives at least
 // kWideMinStrips strips (otherwise 64 columns keep enough workgroups in flight on small grids).

@@ -122,7 +122,7 @@ def test_defaults_and_autotune(gpu):
         rho, ux, uy = np.ones((ny, nx)), np.zeros((ny, nx)), np.zeros((ny, nx))
         s = Sim(rho, ux, uy, prec=prec, device=gpu)
         got = [s.fusion(m) for m in MODELS]
-        assert all(s.fusion_depth(m) == 2 for m in MODELS)  # below 2048 strips of 64 x 60
+        assert all(s.fusion_depth(m) == 2 for m in MODELS)  # below 2048 strips of 64 x 80
         s.close()
         # FP32 models start with their 128-column setting where it gives >= 1024 strips
         exp = []
@@ -131,12 +131,12 @@ def test_defaults_and_autotune(gpu):
             wide = prec == "f32" and want[0] and (nx + 127) // 128 * (-(-ny // ws)) >= 1024
             exp.append((wr, ws) if wide else want)
         assert got == exp, (nx, ny, prec, got)
-    # three steps per launch from 2048 strips of 64 x 60 on (FP32, FP64; not FP16)
-    for (nx, ny, prec), deep in {(4096, 4096, "f32"): True, (4096, 1920, "f64"): True, (4096, 1860, "f32"): False,
+    # three steps per launch from 2048 strips of 64 x 80 on (FP32, FP64; not FP16)
+    for (nx, ny, prec), deep in {(4096, 4096, "f32"): True, (4096, 2560, "f64"): True, (4096, 2480, "f32"): False,
                                  (4096, 4096, "f16"): False}.items():
         s = Sim(np.ones((ny, nx)), np.zeros((ny, nx)), np.zeros((ny, nx)), prec=prec, device=gpu)
         for m in MODELS:
-            assert (s.fusion_depth(m), s.fusion(m)) == ((3, (4, 60)) if deep else (2, s.fusion(m))), (nx, ny, prec, m)
+            assert (s.fusion_depth(m), s.fusion(m)) == ((3, (4, 80)) if deep else (2, s.fusion(m))), (nx, ny, prec, m)
         s.close()
     # autotune leaves state and counter alone, keeps a valid choice, and results do not change
     nx, ny = 1024, 512
