@@ -168,11 +168,12 @@ int lbm_set_fusion(lbm_ctx* ctx, int model, int ring_rows, int strip_rows);
 int lbm_get_fusion(lbm_ctx* ctx, int model, int* ring_rows, int* strip_rows);
 
 /* Steps per fused launch of `model`: 2 (the default) or 3.  With 3, and ring_rows 4 or 8 set by
- * lbm_set_fusion, lbm_step advances three steps per launch (then pairs, then single steps): a
- * second LDS ring holds the second step's values, so each population is read and written once per
- * three steps; the first step covers two halo rows and columns on each side of the strip, the
- * second one.  Strips are 64 columns wide.  Bit-identical to single steps.  LBM_EUNSUPPORTED for 3 on an FP16 context or on a grid
- * narrower or lower than 2; LBM_EINVAL for other values. */
+ * lbm_set_fusion, lbm_step advances three steps per launch (then pairs, then single steps), each
+ * the step of eq. StreamCollide: a second LDS ring holds the second step's values, so each
+ * population is read and written once per three steps; the first step covers two halo rows and
+ * columns on each side of the strip, the second one.  Strips are 64 columns wide.  Bit-identical
+ * to single steps.  LBM_EUNSUPPORTED for 3 on an FP16 context or on a grid narrower or lower than
+ * 2; LBM_EINVAL for other values. */
 int lbm_set_fusion_depth(lbm_ctx* ctx, int model, int steps);
 
 /* Steps per fused launch of `model` (host pointer, may be NULL). */
