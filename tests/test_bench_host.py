@@ -1,0 +1,93 @@
+"""Host logic of bench.py (no GPU): the one-GPU contract, the steps a launch advances, the
+kernel-name keys, and the rocprofv3 summary it writes and reads back (counter scaling by the
+copy calibration, bytes per launch against the algorithmic ones)."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_multi_gpu_request_exits_with_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+class FakeSim:
+    def __init__(self, ring, depth):
+        self.ring, self.depth = ring, depth
+
+    def fusion(self, model):
+        return (self.ring, 16 if self.ring else 0)
+
+    def fusion_depth(self, model):
+        return self.depth
+
+
+@pytest.mark.parametrize("ring,depth,want", [(0, 2, 1), (0, 3, 1), (8, 2, 2), (4, 3, 3), (8, 3, 3), (16, 3, 2)])
+def test_launch_steps(ring, depth, want):
+    # three steps per launch only with a ring of 4 or 8 rows (lbm_set_fusion_depth)
+    assert bench.launch_steps(FakeSim(ring, depth), "K") == want
+
+
+def test_step_kernel_keys_prefer_the_fused_kernels():
+    keys = bench.step_kernel_keys("K", "f32")
+    assert [k for k, _ in keys] == ["k_step3", "k_step2", "k_step"]
+    assert keys[0][1] == "k_step3<5, 1, "
+    assert bench.step_kernel_keys("BGK", "f64")[2][1] == "k_step<0, 0, "
+
+
+def _write_csv(path, header, rows):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as fh:
+        fh.write(",".join(header) + "\n")
+        for r in rows:
+            fh.write(",".join(str(v) for v in r) + "\n")
+
+
+def test_profile_summary_round_trip(tmp_path, monkeypatch):
+    out = tmp_path / "run"
+    prof = tmp_path / "profiles"
+    monkeypatch.setattr(bench, "PROFILE_DIR", str(prof))
+    n = 64
+    k3 = "void (anonymous namespace)::k_step3<5, 1, 4, 64>(float const*, ...)"
+    k1 = "void (anonymous namespace)::k_step<0, 1, 1>(float const*, ...)"
+    _write_csv(str(out / "rp_trace" / "b_kernel_stats.csv"), ["Name", "Calls", "AverageNs", "MinNs", "MaxNs"],
+               [[f'"{k3}"', 4, 3000.0, 2900.0, 3100.0], [f'"{k1}"', 2, 1000.0, 990.0, 1010.0]])
+    cc = ["Kernel_Name", "Counter_Value"]
+    # the calibration copy moves 1 GiB each way; FETCH_SIZE reads half of it, WRITE_SIZE all
+    _write_csv(str(out / "rp_copy_fetch" / "c_counter_collection.csv"), cc, [["copyBuffer", 524288.0]])
+    _write_csv(str(out / "rp_copy_write" / "c_counter_collection.csv"), cc, [["copyBuffer", 1048576.0]])
+    _write_csv(str(out / "rp_fetch" / "b_counter_collection.csv"), cc,
+               [[f'"{k3}"', 100.0], [f'"{k3}"', 110.0], [f'"{k1}"', 40.0]])
+    _write_csv(str(out / "rp_write" / "b_counter_collection.csv"), cc, [[f'"{k3}"', 50.0], [f'"{k1}"', 30.0]])
+    _write_csv(str(out / "rp_valu" / "b_counter_collection.csv"), cc, [[f'"{k3}"', 97.0]])
+    bench.profile_summary(str(out), "f32", n, bench.profile_commands("f32"))
+    counters = (prof / "step_kernels_f32_dsl4096_counters.md").read_text()
+    blob = json.loads(counters.split("```json", 1)[1].split("```", 1)[0])
+    alg = n * n * 72
+    assert blob["algorithmic_bytes"] == alg
+    assert blob["scale"] == {"fetch": 2.0, "write": 1.0}
+    rec = blob["per_launch"]["K"]
+    assert rec["kernel"] == "k_step3"  # the three-step kernel is reported before the others
+    assert rec["hbm_bytes"] == int(round(105.0 * 1024 * 2.0 + 50.0 * 1024))
+    assert rec["vs_algorithmic"] == round(rec["hbm_bytes"] / alg, 4)
+    assert rec["valu_busy"] == 0.97
+    assert blob["per_launch"]["BGK"]["kernel"] == "k_step"
+    # read back through the bench's own reader while the step sources hash as recorded
+    assert bench.measured_traffic("K", "f32") == rec["hbm_bytes"]
+    assert bench.measured_valu_busy("K", "f32") == 0.97
+    trace = (prof / "step_kernels_f32_dsl4096_trace.md").read_text()
+    assert "| k_step3<K, f32> | 4 | 3.00 |" in trace
+    # a summary taken from other sources is not used
+    (prof / "step_kernels_f32_dsl4096_counters.md").write_text(counters.replace(blob["step_source_hash"], "0" * 16))
+    assert bench.measured_traffic("K", "f32") is None
