@@ -209,6 +209,7 @@ def batched_sweep(steps: int, plain_f64_mlups: float, n_inst: int = 512):
     b = Batch(insts, fields, prec="f64", device="cuda:0")
     tuned = b.autotune(3)
     fused_rows = b.fusion()  # 0: one step per pass won the autotuning
+    per_pass = b.fusion_depth() if fused_rows else 1
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
@@ -245,7 +246,7 @@ def batched_sweep(steps: int, plain_f64_mlups: float, n_inst: int = 512):
             "blown_up": int(sum(1 for bl in blow if bl >= 0)),
             "blowup_steps_first10": blow[:10],
             "autotuned": {"nodes_per_thread": tuned[0], "groups_per_cu": tuned[1],
-                          "two_step_strip_rows": fused_rows},
+                          "steps_per_pass": per_pass, "strip_rows": fused_rows},
             "rebalance_every": 500, "precision": "f64"}
 
 

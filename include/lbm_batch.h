@@ -61,7 +61,9 @@ int lbm_batch_create(lbm_batch** out, const lbm_instance_desc* desc, int n, int 
 
 /* Advance every live instance by nsteps >= 0 steps in one cooperative persistent launch (with
  * two steps per pass on, lbm_batch_set_fusion: the first 4 * (nsteps / 4) steps in a launch of
- * the two-step kernel, the rest in one of the single-step kernel).
+ * the two-step kernel, the rest in one of the single-step kernel; with three steps per pass,
+ * lbm_batch_set_fusion_depth: the first 3 * (nsteps / 3) steps in a launch of the three-step
+ * kernel, the rest one step per pass).
  * Asynchronous, except that the first run of each launch shape first probes how many workgroups
  * per CU really stay co-resident (the runtime's occupancy figure can be one too high): two
  * non-advancing steps with a 250 ms barrier bound per candidate, from the occupancy figure
@@ -121,13 +123,25 @@ int lbm_batch_set_fusion(lbm_batch* b, int strip_rows);
 /* The current strip height of two steps per pass (0 = off); strip_rows is a host pointer. */
 int lbm_batch_get_fusion(lbm_batch* b, int* strip_rows);
 
-/* Autotune the persistent launch: each candidate (nodes per thread in {1, 2, 4}, or two steps per
- * pass at the current strip height (16 rows unless set), x groups per CU in {limit, limit/2},
- * limit = the probed residency limit of that shape) runs `trials` (>= 1) steps or pairs that all
- * recompute from the same input copy, so states, counters and blow-up records are unchanged.
- * Keeps the fastest per step: it sets nodes per thread, groups per CU and whether two steps per
- * pass are used (lbm_batch_get_fusion), and returns the first two and the time per step.
- * Synchronises. */
+/* Steps per fused pass (with lbm_batch_set_fusion on): 2 (the default) or 3.  With 3 a workgroup
+ * advances a strip three steps (eq. StreamCollide each) with the first and second steps' values in
+ * two LDS rings of 6 rows (as lbm_set_fusion_depth for a single grid), and the workgroups of an XCD
+ * meet at one barrier per three steps; any number of triples keeps the states in the copy of their
+ * step's parity.  Bit-identical to single steps, blow-up steps included.  LBM_EUNSUPPORTED for 3 on
+ * an FP16 batch; LBM_EINVAL for other values. */
+int lbm_batch_set_fusion_depth(lbm_batch* b, int steps);
+
+/* Steps per fused pass (host pointer, may be NULL). */
+int lbm_batch_get_fusion_depth(lbm_batch* b, int* steps);
+
+/* Autotune the persistent launch: each candidate (nodes per thread in {1, 2, 4}, or two or, for
+ * FP64 and FP32, three steps per pass at the current strip height (32 rows unless set), x groups
+ * per CU in {limit, limit/2}, limit = the probed residency limit of that shape) runs `trials`
+ * (>= 1) steps, pairs or triples that all recompute from the same input copy, so states and
+ * counters are unchanged, and the blow-up records are restored afterwards.  Keeps the fastest per
+ * step: it sets nodes per thread, groups per CU and whether two or three steps per pass are used
+ * (lbm_batch_get_fusion, lbm_batch_get_fusion_depth), and returns the first two and the time per
+ * step.  Synchronises. */
 int lbm_batch_autotune(lbm_batch* b, int trials, int* nodes_per_thread, int* groups_per_cu,
                        double* us_per_step);
 

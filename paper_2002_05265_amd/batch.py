@@ -90,9 +90,16 @@ class Batch:
         """Strip height of two steps per pass, 0 when off."""
         return B.lbm_batch_get_fusion(self.handle)
 
+    def set_fusion_depth(self, steps: int):
+        """Steps per fused pass: 2 or 3 (FP64, FP32)."""
+        B.lbm_batch_set_fusion_depth(self.handle, steps)
+
+    def fusion_depth(self) -> int:
+        return B.lbm_batch_get_fusion_depth(self.handle)
+
     def autotune(self, trials: int = 5):
         """Fastest launch shape (nodes per thread, groups per CU, us per step); also decides
-        whether two steps per pass are used (see fusion())."""
+        whether two or three steps per pass are used (see fusion(), fusion_depth())."""
         return B.lbm_batch_autotune(self.handle, trials)
 
     def close(self):

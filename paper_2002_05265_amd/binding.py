@@ -28,6 +28,7 @@ EXPORTS = (
     "lbm_batch_population_bytes", "lbm_batch_create", "lbm_batch_run", "lbm_batch_status",
     "lbm_batch_get_state", "lbm_batch_mean_u2", "lbm_batch_set_active", "lbm_batch_rebalance",
     "lbm_batch_set_launch", "lbm_batch_set_fusion", "lbm_batch_get_fusion",
+    "lbm_batch_set_fusion_depth", "lbm_batch_get_fusion_depth",
     "lbm_batch_autotune", "lbm_batch_destroy",
     "lbm_state_bytes", "lbm_adjoint_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_raw",
     "lbm_step_raw_many", "lbm_step2_raw_many", "lbm_adjoint_many", "lbm_adjoint_flush",
@@ -95,6 +96,8 @@ def _declare(L: ctypes.CDLL):
         "lbm_batch_set_launch": (_i, [_vp, _i, _i]),
         "lbm_batch_set_fusion": (_i, [_vp, _i]),
         "lbm_batch_get_fusion": (_i, [_vp, ctypes.POINTER(_i)]),
+        "lbm_batch_set_fusion_depth": (_i, [_vp, _i]),
+        "lbm_batch_get_fusion_depth": (_i, [_vp, ctypes.POINTER(_i)]),
         "lbm_batch_autotune": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), _dp]),
         "lbm_batch_destroy": (None, [_vp]),
         "lbm_state_bytes": (_sz, [_vp]),
@@ -287,6 +290,16 @@ def lbm_batch_set_launch(b: int, nodes_per_thread: int, groups_per_cu: int):
 
 def lbm_batch_set_fusion(b: int, strip_rows: int):
     _check(lib().lbm_batch_set_fusion(b, strip_rows), "lbm_batch_set_fusion")
+
+
+def lbm_batch_set_fusion_depth(b: int, steps: int):
+    _check(lib().lbm_batch_set_fusion_depth(b, steps), "lbm_batch_set_fusion_depth")
+
+
+def lbm_batch_get_fusion_depth(b: int) -> int:
+    v = _i(0)
+    _check(lib().lbm_batch_get_fusion_depth(b, ctypes.byref(v)), "lbm_batch_get_fusion_depth")
+    return v.value
 
 
 def lbm_batch_get_fusion(b: int) -> int:

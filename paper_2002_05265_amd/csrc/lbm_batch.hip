@@ -22,6 +22,7 @@
 #include "lbm_cell.hpp"
 #include "lbm_internal.hpp"
 #include "lbm_step2.hpp"
+#include "lbm_step3.hpp"
 
 using namespace lbm;
 
@@ -257,6 +258,61 @@ __global__ __launch_bounds__(kTileThreads) void k_batch2(
     if (advance && blockIdx.x == 0 && tid == 0) *step_ctr = n0 + 2LL * npairs;
 }
 
+// Three steps per pass: the same persistent grid, XCD-local barriers and strips as k_batch2, with
+// the strip body of the plain three-step kernel (two LDS rings of RING + 2 rows).  A triple
+// changes both the step's parity and the copy, so triple p of a launch reads the copy of its
+// first step's parity (the copy of the launch start, flipped p times) and any number of triples
+// keeps every live state in the copy of its step's parity.
+template <int PREC, int RING>
+__global__ __launch_bounds__(kTileThreads) void k_batch3(
+    typename Store<PREC>::S* __restrict__ base, long long copy_elems,
+    const BDesc<typename Store<PREC>::R>* __restrict__ desc, const int2* __restrict__ run,
+    const int* __restrict__ xtab, int* __restrict__ blowup, const int* __restrict__ active,
+    int* __restrict__ lastcopy, unsigned* __restrict__ bar, int* __restrict__ err,
+    long long* __restrict__ step_ctr, int ntriples, int advance, long long timeout_ticks, int hs) {
+    using S = typename Store<PREC>::S;
+    using R = typename Store<PREC>::R;
+    __shared__ S ring1[9][RING + 2][kStripW + 4];
+    __shared__ S ring2[9][RING + 2][kStripW + 2];
+    __shared__ int s_skip;
+    const int tid = threadIdx.x;
+    const unsigned xcc = xcc_id();
+    unsigned rank, count;
+    if (!register_group(bar, xtab, err, timeout_ticks, xcc, rank, count)) return;
+    const int first_strip = xtab[2 * xcc], nstrips = xtab[2 * xcc + 1];
+    unsigned* xbar = bar + kLine * (1 + kMaxXcc + xcc);
+    const long long n0 = *step_ctr;
+    for (int p = 0; p < ntriples; ++p) {
+        const long long n = n0 + (advance ? 3 * p : 0);
+        const int sc = (int)(n0 & 1) ^ (advance ? (p & 1) : 0);
+        const S* src = base + sc * copy_elems;
+        S* dst = base + (sc ^ 1) * copy_elems;
+        for (int t = (int)rank; t < nstrips; t += (int)count) {
+            const int2 e = run[first_strip + t];  // (instance, strip within the instance)
+            const int j = e.x;
+            const BDesc<R>& d = desc[j];
+            if (tid == 0) {
+                const int frozen = __hip_atomic_load(blowup + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_skip = ((long long)frozen < n || !active[j]) ? 1 : 0;  // blew up earlier, or retired
+                if (!s_skip && advance && e.y == 0) lastcopy[j] = sc ^ 1;
+            }
+            __syncthreads();
+            const bool skip = s_skip != 0;
+            __syncthreads();  // s_skip is rewritten for the next strip only after every thread read it
+            if (skip) continue;
+            const int gsx = (d.nx + kStripW - 1) / kStripW;
+            const int sy = e.y / gsx;
+            const int x0 = (e.y - sy * gsx) * kStripW, ys = sy * hs;
+            const Geom g{d.nx, d.ny, d.plane};
+            strip_three_steps<RING, kStripW, true, false>(
+                ring1, ring2, src + d.off, dst + d.off, g, d.ref, x0, ys, min(ys + hs, d.ny), (int)n, blowup + j,
+                [&](R(&h)[9], const Macro<R>& m) { collide_model(d.model, h, m, d.ref, d.c, d.N); });
+        }
+        if (!xcd_barrier(xbar, p, count, err, timeout_ticks)) return;
+    }
+    if (advance && blockIdx.x == 0 && tid == 0) *step_ctr = n0 + 3LL * ntriples;
+}
+
 // XCD of each workgroup of a small probe launch (which XCC ids the device dispatches to).
 __global__ void k_xcc_probe(int* __restrict__ out) {
     if (threadIdx.x == 0) out[blockIdx.x] = (int)xcc_id();
@@ -373,11 +429,15 @@ struct lbm_batch {
     size_t bytes = 0;
     hipStream_t stream = nullptr;      // caller's stream
     // launch shapes k: 0, 1, 2 = one step per pass with 1, 2, 4 nodes per thread; 3 = two
-    // steps per pass over strips
-    int cus = 0, occ[4] = {0, 0, 0, 0};        // CUs, occupancy limit per shape (runtime query)
-    int resident[4] = {0, 0, 0, 0};            // groups per CU confirmed co-resident (0 = not probed)
+    // steps per pass over strips; 4 = three steps per pass over the same strips (shape 3's run
+    // table)
+    int cus = 0, occ[5] = {0, 0, 0, 0, 0};     // CUs, occupancy limit per shape (runtime query)
+    int resident[5] = {0, 0, 0, 0, 0};         // groups per CU confirmed co-resident (0 = not probed)
     int npt = 1, gpc = 0;              // launch shape (gpc 0 = occupancy limit)
-    int fuse = 0, hs = 16;             // two steps per pass (strip height hs) for runs of 4 steps
+    // fused passes over strips of hs rows (32: on the 512-instance FP64 sweep 4% faster than 16 with
+    // two steps per pass, 10% with three)
+    int fuse = 0, hs = 32;
+    int depth = 2;                     // steps per fused pass: 2 (runs of 4 steps) or 3
     long long step = 0;                // host mirror of the step counter
     void* d_desc[3] = {nullptr, nullptr, nullptr};  // descriptors per NPT (tile0 differs)
     int* d_tiles[3] = {nullptr, nullptr, nullptr};  // every tile of every instance, instance order
@@ -478,6 +538,40 @@ const void* batch2_kernel_p(int prec) {
     }
 }
 
+constexpr int kBatch3Ring = 4;
+
+template <int PREC>
+hipError_t launch_batch3_t(lbm_batch* b, hipStream_t s, int G, int ntriples, int advance) {
+    using S = typename Store<PREC>::S;
+    using R = typename Store<PREC>::R;
+    S* base = reinterpret_cast<S*>(b->buf);
+    long long copy_elems = b->copy_elems;
+    const BDesc<R>* desc = reinterpret_cast<const BDesc<R>*>(b->d_desc[0]);
+    const int2* strips = b->d_run[3];
+    const int* xtab = b->d_xtab[3];
+    int* blowup = b->d_blowup;
+    const int* active = b->d_active;
+    int* lastcopy = b->d_lastcopy;
+    unsigned* bar = b->d_bar;
+    int* err = b->d_err;
+    long long* step = b->d_step;
+    long long timeout = b->timeout_ticks;
+    int hs = b->hs;
+    void* args[] = {&base, &copy_elems, &desc, &strips, &xtab, &blowup, &active, &lastcopy, &bar, &err, &step,
+                    &ntriples, &advance, &timeout, &hs};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_batch3<PREC, kBatch3Ring>), dim3(G),
+                                      dim3(kTileThreads), args, 0, s);
+}
+
+// The three-step kernel exists for FP64 and FP32 (nullptr for FP16).
+const void* batch3_kernel_p(int prec) {
+    switch (prec) {
+        case LBM_F64: return reinterpret_cast<const void*>(&k_batch3<kF64, kBatch3Ring>);
+        case LBM_F32_SHIFTED: return reinterpret_cast<const void*>(&k_batch3<kF32, kBatch3Ring>);
+        default: return nullptr;
+    }
+}
+
 long long strips_of(const lbm_instance_desc& d, int hs) {
     return (long long)((d.nx + kStripW - 1) / kStripW) * ((d.ny + hs - 1) / hs);
 }
@@ -538,7 +632,7 @@ int deal_tables(lbm_batch* b, const std::vector<char>& live) {
     return LBM_OK;
 }
 
-int shape_of(const lbm_batch* b, bool fused) { return fused ? 3 : npt_index(b->npt); }
+int shape_of(const lbm_batch* b, bool fused) { return fused ? (b->depth == 3 ? 4 : 3) : npt_index(b->npt); }
 
 int groups_limit(lbm_batch* b, int k) { return b->resident[k] > 0 ? b->resident[k] : b->occ[k]; }
 
@@ -549,7 +643,7 @@ int grid_size(lbm_batch* b, int k) {
 }
 
 // Reset the barrier counter, then one cooperative launch of the persistent kernel of shape k on
-// G groups: `units` steps (shapes 0-2) or pairs of steps (shape 3).
+// G groups: `units` steps (shapes 0-2), pairs of steps (shape 3) or triples (shape 4).
 int run_persistent_on(lbm_batch* b, int k, int G, int units, int advance, long long ticks) {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, b->stream, b->d_bar);
     int rc = check_hip(hipGetLastError(), "barrier reset launch");
@@ -557,7 +651,13 @@ int run_persistent_on(lbm_batch* b, int k, int G, int units, int advance, long l
     const long long keep = b->timeout_ticks;
     b->timeout_ticks = ticks;
     hipError_t e;
-    if (k == 3) {
+    if (k == 4) {
+        switch (b->prec) {
+            case LBM_F64: e = launch_batch3_t<kF64>(b, b->stream, G, units, advance); break;
+            case LBM_F32_SHIFTED: e = launch_batch3_t<kF32>(b, b->stream, G, units, advance); break;
+            default: e = hipErrorInvalidValue; break;
+        }
+    } else if (k == 3) {
         switch (b->prec) {
             case LBM_F64: e = launch_batch2_t<kF64>(b, b->stream, G, units, advance); break;
             case LBM_F32_SHIFTED: e = launch_batch2_t<kF32>(b, b->stream, G, units, advance); break;
@@ -605,8 +705,8 @@ int ensure_resident(lbm_batch* b, int k) {
     return set_error(LBM_EHIP, "no persistent grid of this shape stays co-resident");
 }
 
-// Advance every live instance by `units` steps (k < 3) or pairs (k = 3), in launches short
-// enough that the barrier counter G * units stays below 2^31.
+// Advance every live instance by `units` steps (k < 3), pairs (k = 3) or triples (k = 4), in
+// launches short enough that the barrier counter G * units stays below 2^31.
 int run_units(lbm_batch* b, int k, int units) {
     if (units <= 0) return LBM_OK;
     int rc = ensure_resident(b, k);
@@ -619,7 +719,7 @@ int run_units(lbm_batch* b, int k, int units) {
         rc = run_persistent(b, k, u, 1);
         if (rc != LBM_OK) return rc;
         left -= u;
-        b->step += k == 3 ? 2LL * u : (long long)u;
+        b->step += k == 4 ? 3LL * u : (k == 3 ? 2LL * u : (long long)u);
     }
     return LBM_OK;
 }
@@ -806,6 +906,11 @@ int lbm_batch_create(lbm_batch** out, const lbm_instance_desc* desc, int n, int 
         rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[3], batch2_kernel_p(prec), kTileThreads, 0),
                        "occupancy");
     if (rc == LBM_OK && b->occ[3] < 1) rc = set_error(LBM_EHIP, "persistent two-step kernel does not fit a CU");
+    if (rc == LBM_OK && batch3_kernel_p(prec))
+        rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[4], batch3_kernel_p(prec), kTileThreads, 0),
+                       "occupancy");
+    if (rc == LBM_OK && batch3_kernel_p(prec) && b->occ[4] < 1)
+        rc = set_error(LBM_EHIP, "persistent three-step kernel does not fit a CU");
     if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_xtab[3], sizeof(int) * 2 * kMaxXcc), "hipMalloc(xtab)");
     if (rc == LBM_OK) rc = alloc_strips(b);
     if (rc == LBM_OK) rc = deal_tables(b, std::vector<char>((size_t)n, 1));
@@ -861,8 +966,15 @@ int lbm_batch_run(lbm_batch* b, int nsteps) {
     if (nsteps < 0) return set_error(LBM_EINVAL, "nsteps %d < 0", nsteps);
     if (b->step + nsteps >= INT_MAX) return set_error(LBM_EINVAL, "step counter would overflow");
     if (nsteps == 0) return LBM_OK;
-    // two steps per pass in runs of 4 steps (an even number of pairs leaves every live state in
-    // the copy of its step's parity), the rest one step per pass
+    // three steps per pass (any number of triples leaves every live state in the copy of its
+    // step's parity), or two in runs of 4 steps (an even number of pairs does); the rest one step
+    // per pass
+    if (b->fuse && b->depth == 3) {
+        const int triples = nsteps / 3;
+        int rc = run_units(b, 4, triples);
+        if (rc == LBM_OK) rc = run_units(b, npt_index(b->npt), nsteps - 3 * triples);
+        return rc;
+    }
     const int pairs = b->fuse ? 2 * (nsteps / 4) : 0;
     int rc = run_units(b, 3, pairs);
     if (rc == LBM_OK) rc = run_units(b, npt_index(b->npt), nsteps - 2 * pairs);
@@ -994,6 +1106,21 @@ int lbm_batch_set_fusion(lbm_batch* b, int strip_rows) {
     return rc != LBM_OK ? rc : deal_tables(b, live);
 }
 
+int lbm_batch_set_fusion_depth(lbm_batch* b, int steps) {
+    if (!b) return set_error(LBM_ESTATE, "batch is NULL");
+    if (steps != 2 && steps != 3) return set_error(LBM_EINVAL, "steps per fused pass %d not in {2, 3}", steps);
+    if (steps == 3 && !batch3_kernel_p(b->prec))
+        return set_error(LBM_EUNSUPPORTED, "three steps per pass need an FP64 or FP32 batch");
+    b->depth = steps;
+    return LBM_OK;
+}
+
+int lbm_batch_get_fusion_depth(lbm_batch* b, int* steps) {
+    if (!b) return set_error(LBM_ESTATE, "batch is NULL");
+    if (steps) *steps = b->depth;
+    return LBM_OK;
+}
+
 int lbm_batch_get_fusion(lbm_batch* b, int* strip_rows) {
     if (!b) return set_error(LBM_ESTATE, "batch is NULL");
     if (strip_rows) *strip_rows = b->fuse ? b->hs : 0;
@@ -1018,12 +1145,20 @@ int lbm_batch_autotune(lbm_batch* b, int trials, int* nodes_per_thread, int* gro
     int rc = check_hip(hipEventCreate(&e0), "hipEventCreate");
     if (rc == LBM_OK) rc = check_hip(hipEventCreate(&e1), "hipEventCreate");
     const int npts[3] = {1, 2, 4};
-    const int keep_npt = b->npt, keep_gpc = b->gpc, keep_fuse = b->fuse;
+    const int keep_npt = b->npt, keep_gpc = b->gpc, keep_fuse = b->fuse, keep_depth = b->depth;
     float best = 0.f;
-    int best_npt = keep_npt, best_gpc = keep_gpc, best_fuse = keep_fuse;
-    // candidates: one step per pass (1, 2, 4 nodes per thread), then two steps per pass; each at
-    // the residency limit and at half of it; times per step
-    for (int k = 0; k < 4 && rc == LBM_OK; ++k)
+    int best_npt = keep_npt, best_gpc = keep_gpc, best_fuse = keep_fuse, best_depth = keep_depth;
+    // the timed passes run ahead of the step counter and may record a blow-up of a step not taken
+    // yet: the records are restored afterwards
+    std::vector<int> flags0((size_t)b->n);
+    if (rc == LBM_OK) rc = check_hip(hipStreamSynchronize(b->stream), "synchronise");
+    if (rc == LBM_OK)
+        rc = check_hip(hipMemcpy(flags0.data(), b->d_blowup, sizeof(int) * flags0.size(), hipMemcpyDeviceToHost),
+                       "copy blow-up steps");
+    // candidates: one step per pass (1, 2, 4 nodes per thread), then two and (FP64, FP32) three
+    // steps per pass; each at the residency limit and at half of it; times per step
+    const int nshapes = batch3_kernel_p(b->prec) ? 5 : 4;
+    for (int k = 0; k < nshapes && rc == LBM_OK; ++k)
         for (int half = 0; half < 2 && rc == LBM_OK; ++half) {
             if (k < 3) b->npt = npts[k];
             rc = ensure_resident(b, k);
@@ -1039,6 +1174,7 @@ int lbm_batch_autotune(lbm_batch* b, int trials, int* nodes_per_thread, int* gro
             float ms = 0.f;
             if (rc == LBM_OK) rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
             if (k == 3) ms *= 0.5f;
+            if (k == 4) ms /= 3.f;
             int err = 0;
             if (rc == LBM_OK) rc = check_hip(hipMemcpy(&err, b->d_err, sizeof(int), hipMemcpyDeviceToHost), "copy err");
             if (rc == LBM_OK && err) rc = set_error(LBM_EHIP, "persistent launch stopped: a barrier timed out");
@@ -1046,7 +1182,8 @@ int lbm_batch_autotune(lbm_batch* b, int trials, int* nodes_per_thread, int* gro
                 best = ms;
                 best_npt = b->npt;
                 best_gpc = b->gpc;
-                best_fuse = k == 3 ? 1 : 0;
+                best_fuse = k >= 3 ? 1 : 0;
+                best_depth = k == 4 ? 3 : 2;
             }
         }
     if (e0) (void)hipEventDestroy(e0);
@@ -1054,6 +1191,10 @@ int lbm_batch_autotune(lbm_batch* b, int trials, int* nodes_per_thread, int* gro
     b->npt = rc == LBM_OK ? best_npt : keep_npt;
     b->gpc = rc == LBM_OK ? best_gpc : keep_gpc;
     b->fuse = rc == LBM_OK ? best_fuse : keep_fuse;
+    b->depth = rc == LBM_OK ? best_depth : keep_depth;
+    if (rc == LBM_OK)
+        rc = check_hip(hipMemcpy(b->d_blowup, flags0.data(), sizeof(int) * flags0.size(), hipMemcpyHostToDevice),
+                       "restore blow-up steps");
     if (rc != LBM_OK) return rc;
     if (nodes_per_thread) *nodes_per_thread = best_npt;
     if (groups_per_cu) *groups_per_cu = best_gpc == 0 ? b->resident[shape_of(b, best_fuse)] : best_gpc;

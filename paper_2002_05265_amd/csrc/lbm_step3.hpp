@@ -1,5 +1,5 @@
-// Three time steps per pass over one strip of a grid (temporal blocking with two LDS rings), for
-// the plain kernel.
+// Three time steps per pass over one strip of a grid (temporal blocking with two LDS rings), shared
+// by the plain three-step kernel and the batched one.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,10 +19,11 @@ namespace lbm {
 // pass the three steps work on rows two, one and zero rows ahead of the pass base yb (each needs
 // the rows above and below from the step before), so a pass has two block barriers, as the
 // two-step pass.  Every node is computed by the same arithmetic as in k_step and the rings hold the
-// values in the storage type, so the result is bit-identical to three launches of k_step.
-// Requires nx, ny >= 2 (one conditional wrap of rows and columns) and strip rows >= 1.  Called by
-// all 256 threads of a workgroup.
-template <int RING, int W, typename S, typename R, typename Coll>
+// values in the storage type, so the result is bit-identical to three launches of k_step.  VIA_L2
+// selects L1-bypassing loads, NT streaming stores (as in strip_two_steps).  Requires nx, ny >= 2
+// (one conditional wrap of rows and columns) and strip rows >= 1.  Called by all 256 threads of a
+// workgroup.
+template <int RING, int W, bool VIA_L2 = false, bool NT = true, typename S, typename R, typename Coll>
 __device__ __forceinline__ void strip_three_steps(S (&ring1)[9][RING + 2][W + 4], S (&ring2)[9][RING + 2][W + 2],
                                                   const S* __restrict__ src, S* __restrict__ dst, const Geom& g,
                                                   const Ref<R>& ref, int x0, int ys, int ye, int step,
@@ -60,21 +61,27 @@ __device__ __forceinline__ void strip_three_steps(S (&ring1)[9][RING + 2][W + 4]
         unsigned o0 = xo0, om = xom, op = xop;
         asm("" : "+v"(o0), "+v"(om), "+v"(op));
         auto at = [&](int q, long long r, unsigned xo) { return byte_off(wave_uniform(src + q * g.plane + r), xo); };
-        h[0] = R(ld(at(0, r0, o0)));
-        h[1] = R(ld(at(1, r0, om)));
-        h[2] = R(ld(at(2, rm, o0)));
-        h[3] = R(ld(at(3, r0, op)));
-        h[4] = R(ld(at(4, rp, o0)));
-        h[5] = R(ld(at(5, rm, om)));
-        h[6] = R(ld(at(6, rm, op)));
-        h[7] = R(ld(at(7, rp, op)));
-        h[8] = R(ld(at(8, rp, om)));
+        auto get = [&](const S* p) {
+            if constexpr (VIA_L2) return ld_l2(p); else return ld(p);
+        };
+        h[0] = R(get(at(0, r0, o0)));
+        h[1] = R(get(at(1, r0, om)));
+        h[2] = R(get(at(2, rm, o0)));
+        h[3] = R(get(at(3, r0, op)));
+        h[4] = R(get(at(4, rp, o0)));
+        h[5] = R(get(at(5, rm, om)));
+        h[6] = R(get(at(6, rm, op)));
+        h[7] = R(get(at(7, rp, op)));
+        h[8] = R(get(at(8, rp, om)));
     };
     // first-step pull loads of row a (per lane) at ring1 column c1 (grid column x0 - 2 + c1)
     auto load_any = [&](int a, int c1, R (&h)[9]) {
         const int x = x0 - 2 + c1;
         const int xw = x < 0 ? x + g.nx : (x >= g.nx ? x - g.nx : x);
-        pull_load(src, g.plane, neighbours(xw, wrap_row(a), g.nx, g.ny), h);
+        if constexpr (VIA_L2)
+            pull_load_l2(src, g.plane, neighbours(xw, wrap_row(a), g.nx, g.ny), h);
+        else
+            pull_load(src, g.plane, neighbours(xw, wrap_row(a), g.nx, g.ny), h);
     };
     // ring1 column of halo lane code k (0..3): grid columns x0 - 2, x0 - 1, x0 + w, x0 + w + 1
     auto halo1_col = [&](int k) { return k < 2 ? k : w + k; };
@@ -186,7 +193,7 @@ __device__ __forceinline__ void strip_three_steps(S (&ring1)[9][RING + 2][W + 4]
                 asm("" : "+v"(o));
 #pragma unroll
                 for (int i = 0; i < 9; ++i)
-                    st<S, true>(byte_off(wave_uniform(dst + i * g.plane + r), o), to_store<S>(h[i]));
+                    st<S, NT>(byte_off(wave_uniform(dst + i * g.plane + r), o), to_store<S>(h[i]));
             }
         }
     }
