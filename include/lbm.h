@@ -158,8 +158,10 @@ int lbm_set_launch(lbm_ctx* ctx, int model, int rows, int xcd);
  *   FP16: 40 if that gives at least 1024 strips, else off;
  * except where an FP32 model's measured best setting on 128-column strips, (ring_rows, strip_rows)
  * = (8, 8) for BGK and (4, 20) for the others, gives at least 1024 such strips: it starts with that;
- * and an FP32 or FP64 context whose 64-column strips of 80 rows number at least 2048 starts every
- * model with three steps per launch (lbm_set_fusion_depth), ring_rows 4 and strip_rows 80.
+ * and an FP32 or FP64 context starts every model with three steps per launch
+ * (lbm_set_fusion_depth) and ring_rows 4 when its 64-column strips of strip_rows rows number at
+ * least 512, strip_rows being ceil(nx / 64) ny / sqrt(nx ny) rounded to a multiple of 8 and
+ * clamped to [8, 64] (n / 64 on an n x n grid), and 80 instead of 64 in FP32.
  * Results are bit-identical to single steps (same arithmetic per node; the LDS ring holds the
  * stored type).  Returns LBM_EINVAL for other values. */
 int lbm_set_fusion(lbm_ctx* ctx, int model, int ring_rows, int strip_rows);

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <string>
@@ -170,12 +171,22 @@ struct FusionPick {
 };
 constexpr FusionPick wide_default(int model) { return model == LBM_BGK ? FusionPick{8, 8} : FusionPick{4, 20}; }
 
-// Three steps per launch for a new FP32 or FP64 context while 64-column strips of 80 rows (ring of
-// 4 rows) give at least kDeepMinStrips strips, measured at 4096^2: FP32 +27% (BGK) and +22% (K)
-// over the best two-step launch, FP64 +10%.  80-row strips measured 1-2% faster than 60-row ones
-// in FP32 (the same in FP64); taller ones leave too few workgroups to balance the tail.
-constexpr long long kDeepMinStrips = 2048;
-constexpr int kDeepRing = 4, kDeepStrip = 80;
+// Three steps per launch for a new FP32 or FP64 context (ring of 4 rows, 64-column strips) while
+// its strips number at least kDeepMinStrips.  The strip height is about gsx ny / sqrt(nx ny) rows
+// (n / 64 on an n x n grid: as many strips as columns), a multiple of 8 in [8, 64], and 80 in FP32
+// from 64 on.  Measured on MI355X (double shear layer, BGK / K): FP32 512^2 hs 8 77 / 66k MLUPS
+// (two steps per launch 59 / 54k), 1024^2 hs 16 129 / 118k (97 / 91k), 2048^2 hs 32 161 / 146k
+// (118 / 117k), 3072^2 hs 48 180 / 162k, 4096^2 hs 80 186 / 169k (hs 64: 1.5% less; two steps:
+// 145 / 138k); FP64 2048^2 75 / 72k (61 / 62k), 4096^2 hs 64 86 / 83k (75 / 74k).
+constexpr long long kDeepMinStrips = 512;
+constexpr int kDeepRing = 4;
+
+int deep_strip(int nx, int ny, int prec) {
+    const double gsx = (double)((nx + kStripW - 1) / kStripW);
+    const int h = 8 * (int)(gsx * ny / std::sqrt((double)nx * ny) / 8.0 + 0.5);
+    const int hs = h < 8 ? 8 : (h > 64 ? 64 : h);
+    return (prec == LBM_F32_SHIFTED && hs == 64) ? 80 : hs;
+}
 
 // Widest strip for a model and precision; the launch uses it only while it still gives at least
 // kWideMinStrips strips (otherwise 64 columns keep enough workgroups in flight on small grids).
@@ -655,13 +666,14 @@ int lbm_init_shifted(lbm_ctx** out, int nx, int ny, int prec, int eq_order, doub
     // flight (measured on MI355X; lbm_autotune can revise it)
     for (int k = 0; k < 9; ++k) ctx->rows[k] = prec == LBM_F16_SHIFTED ? 2 : 1;
     const int fstrip = default_fusion_strip(nx, ny, prec);
+    const int dstrip = deep_strip(nx, ny, prec);
     const bool deep = prec != LBM_F16_SHIFTED && nx >= 2 && ny >= 2 &&
-                      (long long)((nx + kStripW - 1) / kStripW) * ((ny + kDeepStrip - 1) / kDeepStrip) >= kDeepMinStrips;
+                      (long long)((nx + kStripW - 1) / kStripW) * ((ny + dstrip - 1) / dstrip) >= kDeepMinStrips;
     if (deep)
         for (int k = 0; k < 9; ++k) {
             ctx->fuse_depth[k] = 3;
             ctx->fuse_ring[k] = kDeepRing;
-            ctx->fuse_strip[k] = kDeepStrip;
+            ctx->fuse_strip[k] = dstrip;
         }
     else if (fstrip > 0)
         for (int k = 0; k < 9; ++k) {
