@@ -124,7 +124,7 @@ def cpu_baseline(models, n: int = 4096, rows: int = 2048, steps: int = 1):
 
 
 def single_step_rates(sims, models, omega, cells, bpc, steps):
-    """The same grids with one step per launch (two-step launches switched off), for comparison;
+    """The same grids with one step per launch (fused launches switched off), for comparison;
     each sim's own setting is restored afterwards."""
     import torch
 

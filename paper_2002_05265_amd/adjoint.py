@@ -7,8 +7,8 @@ and dL/domega (all five rates; the four higher-order ones are omega[1:]).
 
 The forward states needed in reverse order are rebuilt from checkpoints of the raw device
 state; steps between checkpoints run out-of-place (``lbm_step_raw``, or pairs of them as one
-two-step launch, ``lbm_step2_raw_many``, when the context runs the model two steps per launch)
-straight into the buffer that keeps their result, so no state is ever copied:
+two-step launch, ``lbm_step2_raw_many``, when the context runs the model two or three steps per
+launch) straight into the buffer that keeps their result, so no state is ever copied:
   "sqrt"       ceil(sqrt(n)) evenly spaced checkpoints, each segment recomputed once into a
                ring of at most ceil(sqrt(n)) states (about n extra steps, 2 sqrt(n) states)
   "revolve"    binomial checkpointing with `slots` state buffers (Griewank's schedule: the
@@ -244,8 +244,8 @@ class _Run:
     # (lbm_step_raw_many / lbm_adjoint_many); they run exactly the kernels, in exactly the order,
     # that the generic action executor (used for "revolve") would.
     def _two_step(self) -> bool:
-        """Whether the context runs this model two steps per launch (then pairs of forward steps
-        go through lbm_step2_raw_many; the states written are the same bit for bit)."""
+        """Whether the context runs this model fused, two or three steps per launch (then pairs of
+        forward steps go through lbm_step2_raw_many; the states written are the same bit for bit)."""
         return B.lbm_get_fusion(self.ctx, self.model)[0] > 0
 
     def _run_chain(self, chain, step0: int):

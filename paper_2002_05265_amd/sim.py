@@ -64,12 +64,14 @@ class Sim:
         return B.lbm_get_fusion_depth(self.ctx, _model_code(model))
 
     def fusion(self, model):
-        """(ring_rows, strip_rows) of `model`'s two-step launches, (0, 0) when off."""
+        """(ring_rows, strip_rows) of `model`'s fused launches, (0, 0) when off (fusion_depth() gives
+        the steps per launch)."""
         return B.lbm_get_fusion(self.ctx, _model_code(model))
 
     def autotune(self, model, omega, trials: int = 10):
         """Pick the fastest launches for `model` (state unchanged); returns the single-step shape
-        (rows, xcd) and the best microseconds per step; fusion() gives the two-step choice."""
+        (rows, xcd) and the best microseconds per step; fusion() and fusion_depth() give the fused
+        choice."""
         return B.lbm_autotune(self.ctx, _model_code(model), omega, trials)
 
     def moments(self):
