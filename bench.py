@@ -45,9 +45,11 @@ def step_source_hash() -> str:
 
 
 def step_kernel_keys(model: str, prec: str):
-    """(label, name prefix in a kernel trace) of the three-, two- and single-step kernel."""
+    """(label, name prefix in a kernel trace) of the three-step kernels (64-column and narrow
+    strips), the two-step and the single-step kernel."""
     args = f"{MODEL_ORDER.index(model)}, {PREC_CODE[prec]}, "
-    return [("k_step3", f"k_step3<{args}"), ("k_step2", f"k_step2<{args}"), ("k_step", f"k_step<{args}")]
+    return [("k_step3", f"k_step3<{args}"), ("k_step3n", f"k_step3n<{args}"), ("k_step2", f"k_step2<{args}"),
+            ("k_step", f"k_step<{args}")]
 
 
 def launch_steps(sim, model: str) -> int:
@@ -502,8 +504,8 @@ def profile_summary(out_root: str, prec: str, n: int, commands: dict):
              "Command (from the repository root, with `cd /tmp && export TMPDIR=/tmp` semantics for",
              "the profiler's scratch files):", "", "```", commands["trace"], "```", "",
              f"Algorithmic bytes per launch: {n}*{n} nodes * 18 * {bytes_per_cell(prec) // 18} B = {alg} B "
-             "(every population read and written once; k_step3 advances three steps per launch, k_step2 "
-             "two, k_step one).",
+             "(every population read and written once; k_step3 and k_step3n advance three steps per "
+             "launch, k_step2 two, k_step one).",
              "", "| kernel | calls | average us | min us | max us | GB/s at algorithmic bytes |",
              "|---|---|---|---|---|---|"]
     for r in stats:
@@ -728,7 +730,8 @@ def main():
     achieved = cells * bpc / (launch_us * 1e-6) / 1e9
     traffic = measured_traffic(dominant, args.prec) if n == 4096 else None
     valu_busy = measured_valu_busy(dominant, args.prec) if n == 4096 else None
-    kname = {3: "k_step3", 2: "k_step2", 1: "k_step"}[spl]
+    kname = {3: "k_step3n" if args.prec == "f64" and per_model[dominant]["ring_rows"] == 4 else "k_step3",
+             2: "k_step2", 1: "k_step"}[spl]
     line = {
         "metric": "MLUPS per collision model at 4096^2 FP32 + % HBM roofline; adjoint/batched vs plain",
         "value": round(value, 1),

@@ -173,8 +173,9 @@ int lbm_get_fusion(lbm_ctx* ctx, int model, int* ring_rows, int* strip_rows);
  * lbm_set_fusion, lbm_step advances three steps per launch (then pairs, then single steps), each
  * the step of eq. StreamCollide: a second LDS ring holds the second step's values, so each
  * population is read and written once per three steps; the first step covers two halo rows and
- * columns on each side of the strip, the second one.  Strips are 64 columns wide.  Bit-identical
- * to single steps.  LBM_EUNSUPPORTED for 3 on an FP16 context or on a grid narrower or lower than
+ * columns on each side of the strip, the second one.  Strips are 64 columns wide, except FP64 with
+ * ring_rows 4: 48, so that the strip and its halo columns fit one wave.  Bit-identical to single
+ * steps.  LBM_EUNSUPPORTED for 3 on an FP16 context or on a grid narrower or lower than
  * 2; LBM_EINVAL for other values. */
 int lbm_set_fusion_depth(lbm_ctx* ctx, int model, int steps);
 

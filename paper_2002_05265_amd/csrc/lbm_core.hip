@@ -243,6 +243,27 @@ __global__ __launch_bounds__(256) void k_step3(const typename Store<PREC>::S* __
                                [&](R(&h)[9], const Macro<R>& m) { collide<MODEL>(h, m, ref, c, N); });
 }
 
+// Three steps per launch on strips of WP columns whose halo columns fit the wave (FP64: WP = 48;
+// measured at 4096^2 against 64-column strips: BGK 96 against 86k MLUPS, K 82 against 80k).
+template <int MODEL, int PREC, int RING, int WP>
+__global__ __launch_bounds__(256) void k_step3n(const typename Store<PREC>::S* __restrict__ src,
+                                                typename Store<PREC>::S* __restrict__ dst, Geom g,
+                                                Coef<typename Store<PREC>::R> c,
+                                                Ref<typename Store<PREC>::R> ref, int N, int step,
+                                                int* __restrict__ blowup, unsigned gsx, int hs) {
+    using S = typename Store<PREC>::S;
+    using R = typename Store<PREC>::R;
+    __shared__ S ring1[9][RING + 2][WP + 4];
+    __shared__ S ring2[9][RING + 2][WP + 3];
+    // strips dealt to the XCDs in contiguous bands (measured 1-4% faster than hardware order here)
+    unsigned sx, sy;
+    tile_of_block(blockIdx.x, gsx, gridDim.x, 1, sx, sy);
+    const int x0 = (int)sx * WP;
+    const int ys = (int)sy * hs;
+    strip_three_steps_narrow<RING, WP>(ring1, ring2, src, dst, g, ref, x0, ys, min(ys + hs, g.ny), step, blowup,
+                                       [&](R(&h)[9], const Macro<R>& m) { collide<MODEL>(h, m, ref, c, N); });
+}
+
 // Macroscopic fields of the state f(., n) (pulled from the post-collision copy) and per-block
 // partial sums of {rho, rho ux, rho uy, rho |u|^2 / 2, |u|^2} in FP64.
 template <int PREC>
@@ -486,11 +507,33 @@ void launch_step3_w(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int hs
                        ctx->d_flag, gsx, hs);
 }
 
-// Three steps per launch (FP32 and FP64), 64-column strips: the two rings of 128-column strips
-// take 56 KiB of LDS in FP32 with a ring of 4 rows, two workgroups per CU, and measured 10-25%
-// slower.
+// FP64 three-step strips with a ring of 4 rows: 48 columns, the halo columns inside the wave (no halo
+// passes, 44 KiB of LDS: three workgroups per CU), each row segment three whole 128-byte lines.
+constexpr int kNarrowW = 48;
+
+// One launch of k_step3n (FP64 narrow strips) from copy src_copy to the other.
+template <int MODEL, int PREC, int RING, int WP>
+void launch_step3n_w(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int hs, int src_copy) {
+    using S = typename Store<PREC>::S;
+    const unsigned gsx = (unsigned)((ctx->nx + WP - 1) / WP);
+    const unsigned gsy = (unsigned)((ctx->ny + hs - 1) / hs);
+    hipLaunchKernelGGL((k_step3n<MODEL, PREC, RING, WP>), dim3(gsx * gsy), dim3(256), 0, ctx->stream,
+                       reinterpret_cast<const S*>(ctx->copy(src_copy)), reinterpret_cast<S*>(ctx->copy(src_copy ^ 1)),
+                       ctx->geom(), c, ref_as<typename Store<PREC>::R>(ctx->ref), ctx->eq_order, (int)ctx->step,
+                       ctx->d_flag, gsx, hs);
+}
+
+// Three steps per launch (FP32 and FP64), 64-column strips, except FP64 with a ring of 4 rows
+// (48-column narrow strips): the two rings of 128-column strips take 56 KiB of LDS in FP32 with a
+// ring of 4 rows, two workgroups per CU, and measured 10-25% slower.
 template <int MODEL, int PREC>
 void launch_step3_t(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int ring, int hs, int src_copy) {
+    if constexpr (PREC == kF64) {
+        if (ring == 4) {
+            launch_step3n_w<MODEL, PREC, 4, kNarrowW>(ctx, c, hs, src_copy);
+            return;
+        }
+    }
     if constexpr (PREC != kF16) {
         if (ring == 4)
             launch_step3_w<MODEL, PREC, 4, kStripW>(ctx, c, hs, src_copy);

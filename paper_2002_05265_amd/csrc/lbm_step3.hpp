@@ -200,3 +200,136 @@ __device__ __forceinline__ void strip_three_steps(S (&ring1)[9][RING + 2][W + 4]
 }
 
 }  // namespace lbm
+
+namespace lbm {
+
+// Three steps per pass over a strip of WP output columns whose halo columns fit the wave: lane l
+// takes column x0 - 2 + l in all three steps, the first step on lanes 0 .. WP + 3 (the strip and two
+// halo columns each side), the second on lanes 1 .. WP + 2, the third on lanes 2 .. WP + 1, which
+// write; there are no halo passes.  With WP = 48 in FP64 an output row segment is three whole
+// 128-byte lines and the rings take 44 KiB (three workgroups per CU against two for 64 columns).
+// Same rows, ring slots and barriers as strip_three_steps; one wave per row.
+template <int RING, int WP, typename S, typename R, typename Coll>
+__device__ __forceinline__ void strip_three_steps_narrow(S (&ring1)[9][RING + 2][WP + 4],
+                                                         S (&ring2)[9][RING + 2][WP + 3],
+                                                         const S* __restrict__ src, S* __restrict__ dst,
+                                                         const Geom& g, const Ref<R>& ref, int x0, int ys, int ye,
+                                                         int step, int* __restrict__ blowup, Coll&& coll) {
+    constexpr int NR = RING + 2;
+    constexpr int KR = RING / 4;  // rows per wave and pass
+    static_assert(RING % 4 == 0 && WP + 4 <= 64, "ring rows: a multiple of 4; the strip and its halo fit a wave");
+    const int lane = (int)(threadIdx.x & 63u);
+    const int rl = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int w = min(WP, g.nx - x0);            // output columns of this strip
+    const bool on1 = lane < w + 4;               // first step: columns x0 - 2 .. x0 + w + 1
+    const bool on2 = lane >= 1 && lane <= w + 2;  // second step: x0 - 1 .. x0 + w
+    const bool on3 = lane >= 2 && lane <= w + 1;  // third step: x0 .. x0 + w - 1
+    constexpr unsigned E = sizeof(S);
+    unsigned xo0, xom, xop;
+    {
+        int x = x0 - 2 + lane;
+        x = x < 0 ? x + g.nx : (x >= g.nx ? x - g.nx : x);
+        xo0 = (unsigned)x * E;
+        xom = (unsigned)(x == 0 ? g.nx - 1 : x - 1) * E;
+        xop = (unsigned)(x == g.nx - 1 ? 0 : x + 1) * E;
+    }
+    auto wrap_row = [&](int a) { return a < 0 ? a + g.ny : (a >= g.ny ? a - g.ny : a); };
+    auto load_own = [&](int a, R (&h)[9]) {
+        const int yw = wrap_row(a);
+        const long long r0 = (long long)yw * g.nx;
+        const long long rm = yw == 0 ? (long long)(g.ny - 1) * g.nx : r0 - g.nx;
+        const long long rp = yw == g.ny - 1 ? 0 : r0 + g.nx;
+        unsigned o0 = xo0, om = xom, op = xop;
+        asm("" : "+v"(o0), "+v"(om), "+v"(op));
+        auto at = [&](int q, long long r, unsigned xo) { return byte_off(wave_uniform(src + q * g.plane + r), xo); };
+        h[0] = R(ld(at(0, r0, o0)));
+        h[1] = R(ld(at(1, r0, om)));
+        h[2] = R(ld(at(2, rm, o0)));
+        h[3] = R(ld(at(3, r0, op)));
+        h[4] = R(ld(at(4, rp, o0)));
+        h[5] = R(ld(at(5, rm, om)));
+        h[6] = R(ld(at(6, rm, op)));
+        h[7] = R(ld(at(7, rp, op)));
+        h[8] = R(ld(at(8, rp, om)));
+    };
+    auto wrap = [](int t) { return t < 0 ? t + NR : (t >= NR ? t - NR : t); };
+    auto finish1 = [&](int slot, R (&h)[9]) {
+        double rho_d;
+        const Macro<R> m = macro_of<S>(h, ref, rho_d);
+        flag_bad(!(rho_d > 0.0), blowup, step);
+        coll(h, m);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) ring1[i][slot][lane] = to_store<S>(h[i]);
+    };
+    auto second = [&](int s1, int s2) {
+        R h[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) h[i] = R(ring1[i][wrap(s1 - cy(i))][lane - cx(i)]);
+        double rho_d;
+        const Macro<R> m = macro_of<S>(h, ref, rho_d);
+        flag_bad(!(rho_d > 0.0), blowup, step + 1);
+        coll(h, m);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) ring2[i][s2][lane] = to_store<S>(h[i]);
+    };
+    R hn[KR][9];
+    auto prefetch = [&](int yb) {
+        const int top = min(yb + RING + 1, ye + 1);
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+            const int a = yb + 2 + rl + 4 * k;
+            if (a <= top && on1) load_own(a, hn[k]);
+        }
+    };
+    // prologue: first step on rows ys - 2 .. ys + 1 (ring1 slots 0..3), second on ys - 1, ys
+    {
+        R hp[9];
+        if (on1) load_own(ys - 2 + rl, hp);
+        prefetch(ys);
+        if (on1) finish1(rl, hp);
+    }
+    __syncthreads();
+    if (rl < 2 && on2) second(1 + rl, rl);
+    __syncthreads();
+    for (int yb = ys; yb < ye; yb += RING) {
+        const int top1 = min(yb + RING + 1, ye + 1);
+        const int top2 = min(yb + RING, ye);
+        const int sb1 = (yb - ys + 2) % NR;
+        const int sb2 = (yb - ys + 1) % NR;
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+            const int a = yb + 2 + rl + 4 * k;
+            if (a <= top1 && on1) finish1(wrap(sb1 + 2 + rl + 4 * k), hn[k]);
+        }
+        __syncthreads();
+        if (yb + RING < ye) prefetch(yb + RING);
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+            const int off = 1 + rl + 4 * k;
+            if (yb + off <= top2 && on2) second(sb1 + off, wrap(sb2 + off));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+            const int y = yb + rl + 4 * k;
+            if (y < ye && on3) {
+                const int s0 = sb2 + rl + 4 * k;
+                R h[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) h[i] = R(ring2[i][wrap(s0 - cy(i))][lane - cx(i)]);
+                double rho_d;
+                const Macro<R> m = macro_of<S>(h, ref, rho_d);
+                flag_bad(!(rho_d > 0.0), blowup, step + 2);
+                coll(h, m);
+                const long long r = (long long)y * g.nx;
+                unsigned o = xo0;
+                asm("" : "+v"(o));
+#pragma unroll
+                for (int i = 0; i < 9; ++i)
+                    st<S, true>(byte_off(wave_uniform(dst + i * g.plane + r), o), to_store<S>(h[i]));
+            }
+        }
+    }
+}
+
+}  // namespace lbm

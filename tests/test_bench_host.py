@@ -41,9 +41,10 @@ def test_launch_steps(ring, depth, want):
 
 def test_step_kernel_keys_prefer_the_fused_kernels():
     keys = bench.step_kernel_keys("K", "f32")
-    assert [k for k, _ in keys] == ["k_step3", "k_step2", "k_step"]
+    assert [k for k, _ in keys] == ["k_step3", "k_step3n", "k_step2", "k_step"]
     assert keys[0][1] == "k_step3<5, 1, "
-    assert bench.step_kernel_keys("BGK", "f64")[2][1] == "k_step<0, 0, "
+    assert bench.step_kernel_keys("BGK", "f64")[1][1] == "k_step3n<0, 0, "
+    assert bench.step_kernel_keys("BGK", "f64")[3][1] == "k_step<0, 0, "
 
 
 def _write_csv(path, header, rows):
