@@ -258,9 +258,13 @@ __global__ __launch_bounds__(kTileThreads) void k_batch2(
     if (advance && blockIdx.x == 0 && tid == 0) *step_ctr = n0 + 2LL * npairs;
 }
 
-// Three steps per pass: the same persistent grid, XCD-local barriers and strips as k_batch2, with
-// the strip body of the plain three-step kernel (two LDS rings of RING + 2 rows).  A triple
-// changes both the step's parity and the copy, so triple p of a launch reads the copy of its
+// Strip width of the FP64 three-step batched kernel: the strip and its halo fit one wave.
+constexpr int kBatchNarrowW = 48;
+
+// Three steps per pass: the same persistent grid and XCD-local barriers as k_batch2, with the strip
+// body of the plain three-step kernels (two LDS rings of RING + 2 rows): in FP64 the narrow strips
+// of 48 columns whose halo fits the wave, in FP32 strips of 64 columns (its own strip table).  A
+// triple changes both the step's parity and the copy, so triple p of a launch reads the copy of its
 // first step's parity (the copy of the launch start, flipped p times) and any number of triples
 // keeps every live state in the copy of its step's parity.
 template <int PREC, int RING>
@@ -272,8 +276,10 @@ __global__ __launch_bounds__(kTileThreads) void k_batch3(
     long long* __restrict__ step_ctr, int ntriples, int advance, long long timeout_ticks, int hs) {
     using S = typename Store<PREC>::S;
     using R = typename Store<PREC>::R;
-    __shared__ S ring1[9][RING + 2][kStripW + 4];
-    __shared__ S ring2[9][RING + 2][kStripW + 2];
+    constexpr bool NARROW = PREC == kF64;
+    constexpr int SW = NARROW ? kBatchNarrowW : kStripW;  // strip width
+    __shared__ S ring1[9][RING + 2][SW + 4];
+    __shared__ S ring2[9][RING + 2][NARROW ? SW + 3 : SW + 2];
     __shared__ int s_skip;
     const int tid = threadIdx.x;
     const unsigned xcc = xcc_id();
@@ -300,13 +306,17 @@ __global__ __launch_bounds__(kTileThreads) void k_batch3(
             const bool skip = s_skip != 0;
             __syncthreads();  // s_skip is rewritten for the next strip only after every thread read it
             if (skip) continue;
-            const int gsx = (d.nx + kStripW - 1) / kStripW;
+            const int gsx = (d.nx + SW - 1) / SW;
             const int sy = e.y / gsx;
-            const int x0 = (e.y - sy * gsx) * kStripW, ys = sy * hs;
+            const int x0 = (e.y - sy * gsx) * SW, ys = sy * hs;
             const Geom g{d.nx, d.ny, d.plane};
-            strip_three_steps<RING, kStripW, true, false>(
-                ring1, ring2, src + d.off, dst + d.off, g, d.ref, x0, ys, min(ys + hs, d.ny), (int)n, blowup + j,
-                [&](R(&h)[9], const Macro<R>& m) { collide_model(d.model, h, m, d.ref, d.c, d.N); });
+            auto coll = [&](R(&h)[9], const Macro<R>& m) { collide_model(d.model, h, m, d.ref, d.c, d.N); };
+            if constexpr (NARROW)
+                strip_three_steps_narrow<RING, SW, true, false>(ring1, ring2, src + d.off, dst + d.off, g, d.ref, x0, ys,
+                                                                min(ys + hs, d.ny), (int)n, blowup + j, coll);
+            else
+                strip_three_steps<RING, kStripW, true, false>(ring1, ring2, src + d.off, dst + d.off, g, d.ref, x0, ys,
+                                                              min(ys + hs, d.ny), (int)n, blowup + j, coll);
         }
         if (!xcd_barrier(xbar, p, count, err, timeout_ticks)) return;
     }
@@ -442,9 +452,11 @@ struct lbm_batch {
     void* d_desc[3] = {nullptr, nullptr, nullptr};  // descriptors per NPT (tile0 differs)
     int* d_tiles[3] = {nullptr, nullptr, nullptr};  // every tile of every instance, instance order
     int ntiles[3] = {0, 0, 0};
-    int2* d_run[4] = {nullptr, nullptr, nullptr, nullptr};  // tiles / strips of live instances, one list per XCD
-    int* d_xtab[4] = {nullptr, nullptr, nullptr, nullptr};  // per XCC id: first run entry, entry count
-    long long run_cap[4] = {0, 0, 0, 0};                    // entries d_run[k] can hold
+    // tiles / strips of live instances per launch shape, one list per XCD (shape 4: the strips of the
+    // three-step kernel, 48 columns wide in FP64)
+    int2* d_run[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    int* d_xtab[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // per XCC id: first run entry, entry count
+    long long run_cap[5] = {0, 0, 0, 0, 0};                          // entries d_run[k] can hold
     std::vector<int> xccs;                          // XCC ids the device dispatches to
     int* d_blowup = nullptr;
     int* d_active = nullptr;           // per instance: nonzero = advanced by lbm_batch_run
@@ -547,8 +559,8 @@ hipError_t launch_batch3_t(lbm_batch* b, hipStream_t s, int G, int ntriples, int
     S* base = reinterpret_cast<S*>(b->buf);
     long long copy_elems = b->copy_elems;
     const BDesc<R>* desc = reinterpret_cast<const BDesc<R>*>(b->d_desc[0]);
-    const int2* strips = b->d_run[3];
-    const int* xtab = b->d_xtab[3];
+    const int2* strips = b->d_run[4];
+    const int* xtab = b->d_xtab[4];
     int* blowup = b->d_blowup;
     const int* active = b->d_active;
     int* lastcopy = b->d_lastcopy;
@@ -572,9 +584,12 @@ const void* batch3_kernel_p(int prec) {
     }
 }
 
-long long strips_of(const lbm_instance_desc& d, int hs) {
-    return (long long)((d.nx + kStripW - 1) / kStripW) * ((d.ny + hs - 1) / hs);
+long long strips_of(const lbm_instance_desc& d, int hs, int width = kStripW) {
+    return (long long)((d.nx + width - 1) / width) * ((d.ny + hs - 1) / hs);
 }
+
+// Strip width of the three-step batched kernel (launch shape 4).
+int batch3_width(int prec) { return prec == LBM_F64 ? kBatchNarrowW : kStripW; }
 
 template <int PREC>
 hipError_t launch_batch_p(lbm_batch* b, hipStream_t s, int G, int nsteps, int advance) {
@@ -605,7 +620,8 @@ int deal_tables(lbm_batch* b, const std::vector<char>& live) {
         owner[j] = b->xccs[best];
     }
     const int npts[3] = {1, 2, 4};
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 5; ++k) {
+        if (k == 4 && !b->d_run[4]) continue;  // no three-step kernel (FP16)
         std::vector<int2> run;
         std::vector<int> xtab(2 * kMaxXcc, 0);
         for (int x : b->xccs) {
@@ -614,7 +630,7 @@ int deal_tables(lbm_batch* b, const std::vector<char>& live) {
                 if (owner[j] != x) continue;
                 const long long nt = k < 3 ? (cells(j) + (long long)kTileThreads * npts[k] - 1) /
                                                  ((long long)kTileThreads * npts[k])
-                                           : strips_of(b->hdesc[j], b->hs);
+                                           : strips_of(b->hdesc[j], b->hs, k == 4 ? batch3_width(b->prec) : kStripW);
                 for (int t = 0; t < (int)nt; ++t) run.push_back(make_int2(j, t));
             }
             xtab[2 * x + 1] = (int)run.size() - xtab[2 * x];
@@ -740,17 +756,27 @@ int live_set(lbm_batch* b, std::vector<char>& live) {
     return LBM_OK;
 }
 
-// (Re)allocate the strip table for the current strip height.
-int alloc_strips(lbm_batch* b) {
-    long long total = 0;
-    for (int j = 0; j < b->n; ++j) total += strips_of(b->hdesc[j], b->hs);
+// (Re)allocate strip table k to hold `total` strips.
+int alloc_table(lbm_batch* b, int k, long long total) {
     if (total >= INT_MAX) return set_error(LBM_EINVAL, "too many strips (%lld)", total);
-    if (total <= b->run_cap[3]) return LBM_OK;
-    if (b->d_run[3]) (void)hipFree(b->d_run[3]);
-    b->d_run[3] = nullptr;
-    b->run_cap[3] = 0;
-    int rc = check_hip(hipMalloc(&b->d_run[3], sizeof(int2) * (size_t)total), "hipMalloc(strip run)");
-    if (rc == LBM_OK) b->run_cap[3] = total;
+    if (b->d_run[k] && total <= b->run_cap[k]) return LBM_OK;
+    if (b->d_run[k]) (void)hipFree(b->d_run[k]);
+    b->d_run[k] = nullptr;
+    b->run_cap[k] = 0;
+    int rc = check_hip(hipMalloc(&b->d_run[k], sizeof(int2) * (size_t)std::max(1LL, total)), "hipMalloc(strip run)");
+    if (rc == LBM_OK) b->run_cap[k] = total;
+    return rc;
+}
+
+// (Re)allocate the strip tables (two and three steps per pass) for the current strip height.
+int alloc_strips(lbm_batch* b) {
+    long long t3 = 0, t4 = 0;
+    for (int j = 0; j < b->n; ++j) {
+        t3 += strips_of(b->hdesc[j], b->hs);
+        t4 += strips_of(b->hdesc[j], b->hs, batch3_width(b->prec));
+    }
+    int rc = alloc_table(b, 3, t3);
+    if (rc == LBM_OK && batch3_kernel_p(b->prec)) rc = alloc_table(b, 4, t4);
     return rc;
 }
 
@@ -912,6 +938,8 @@ int lbm_batch_create(lbm_batch** out, const lbm_instance_desc* desc, int n, int 
     if (rc == LBM_OK && batch3_kernel_p(prec) && b->occ[4] < 1)
         rc = set_error(LBM_EHIP, "persistent three-step kernel does not fit a CU");
     if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_xtab[3], sizeof(int) * 2 * kMaxXcc), "hipMalloc(xtab)");
+    if (rc == LBM_OK && batch3_kernel_p(prec))
+        rc = check_hip(hipMalloc(&b->d_xtab[4], sizeof(int) * 2 * kMaxXcc), "hipMalloc(xtab)");
     if (rc == LBM_OK) rc = alloc_strips(b);
     if (rc == LBM_OK) rc = deal_tables(b, std::vector<char>((size_t)n, 1));
     if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_blowup, sizeof(int) * (size_t)n), "hipMalloc(blowup)");
@@ -1209,7 +1237,7 @@ void lbm_batch_destroy(lbm_batch* b) {
         if (b->d_desc[k]) (void)hipFree(b->d_desc[k]);
         if (b->d_tiles[k]) (void)hipFree(b->d_tiles[k]);
     }
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 5; ++k) {
         if (b->d_xtab[k]) (void)hipFree(b->d_xtab[k]);
         if (b->d_run[k]) (void)hipFree(b->d_run[k]);
     }

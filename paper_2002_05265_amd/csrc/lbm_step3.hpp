@@ -208,8 +208,9 @@ namespace lbm {
 // halo columns each side), the second on lanes 1 .. WP + 2, the third on lanes 2 .. WP + 1, which
 // write; there are no halo passes.  With WP = 48 in FP64 an output row segment is three whole
 // 128-byte lines and the rings take 44 KiB (three workgroups per CU against two for 64 columns).
-// Same rows, ring slots and barriers as strip_three_steps; one wave per row.
-template <int RING, int WP, typename S, typename R, typename Coll>
+// Same rows, ring slots and barriers as strip_three_steps; one wave per row.  VIA_L2 selects
+// L1-bypassing loads, NT streaming stores.
+template <int RING, int WP, bool VIA_L2 = false, bool NT = true, typename S, typename R, typename Coll>
 __device__ __forceinline__ void strip_three_steps_narrow(S (&ring1)[9][RING + 2][WP + 4],
                                                          S (&ring2)[9][RING + 2][WP + 3],
                                                          const S* __restrict__ src, S* __restrict__ dst,
@@ -242,15 +243,18 @@ __device__ __forceinline__ void strip_three_steps_narrow(S (&ring1)[9][RING + 2]
         unsigned o0 = xo0, om = xom, op = xop;
         asm("" : "+v"(o0), "+v"(om), "+v"(op));
         auto at = [&](int q, long long r, unsigned xo) { return byte_off(wave_uniform(src + q * g.plane + r), xo); };
-        h[0] = R(ld(at(0, r0, o0)));
-        h[1] = R(ld(at(1, r0, om)));
-        h[2] = R(ld(at(2, rm, o0)));
-        h[3] = R(ld(at(3, r0, op)));
-        h[4] = R(ld(at(4, rp, o0)));
-        h[5] = R(ld(at(5, rm, om)));
-        h[6] = R(ld(at(6, rm, op)));
-        h[7] = R(ld(at(7, rp, op)));
-        h[8] = R(ld(at(8, rp, om)));
+        auto get = [&](const S* p) {
+            if constexpr (VIA_L2) return ld_l2(p); else return ld(p);
+        };
+        h[0] = R(get(at(0, r0, o0)));
+        h[1] = R(get(at(1, r0, om)));
+        h[2] = R(get(at(2, rm, o0)));
+        h[3] = R(get(at(3, r0, op)));
+        h[4] = R(get(at(4, rp, o0)));
+        h[5] = R(get(at(5, rm, om)));
+        h[6] = R(get(at(6, rm, op)));
+        h[7] = R(get(at(7, rp, op)));
+        h[8] = R(get(at(8, rp, om)));
     };
     auto wrap = [](int t) { return t < 0 ? t + NR : (t >= NR ? t - NR : t); };
     auto finish1 = [&](int slot, R (&h)[9]) {
@@ -326,7 +330,7 @@ __device__ __forceinline__ void strip_three_steps_narrow(S (&ring1)[9][RING + 2]
                 asm("" : "+v"(o));
 #pragma unroll
                 for (int i = 0; i < 9; ++i)
-                    st<S, true>(byte_off(wave_uniform(dst + i * g.plane + r), o), to_store<S>(h[i]));
+                    st<S, NT>(byte_off(wave_uniform(dst + i * g.plane + r), o), to_store<S>(h[i]));
             }
         }
     }
