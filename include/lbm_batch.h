@@ -127,7 +127,8 @@ int lbm_batch_get_fusion(lbm_batch* b, int* strip_rows);
  * advances a strip three steps (eq. StreamCollide each) with the first and second steps' values in
  * two LDS rings of 6 rows (as lbm_set_fusion_depth for a single grid), and the workgroups of an XCD
  * meet at one barrier per three steps; any number of triples keeps the states in the copy of their
- * step's parity.  Bit-identical to single steps, blow-up steps included.  LBM_EUNSUPPORTED for 3 on
+ * step's parity.  FP64 strips are 48 columns wide (strip and halo fit one wave), FP32 strips 64.
+ * Bit-identical to single steps, blow-up steps included.  LBM_EUNSUPPORTED for 3 on
  * an FP16 batch; LBM_EINVAL for other values. */
 int lbm_batch_set_fusion_depth(lbm_batch* b, int steps);
 
