@@ -615,7 +615,8 @@ PROFILE_COMMANDS = {
 
 def profile_commands(prec: str) -> dict:
     """The rocprofv3 commands whose csv output `--profile-summary` reads, for one precision (FP32:
-    PROFILE_COMMANDS; others under gpurun_out/p_<prec>/, with the FP32 run's copy calibration)."""
+    PROFILE_COMMANDS; others in a p_<prec> folder beside those outputs, with the FP32 run's copy
+    calibration)."""
     if prec == "f32":
         return PROFILE_COMMANDS
     args = f"{PROFILE_ARGS} --prec {prec}"
