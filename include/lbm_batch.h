@@ -136,7 +136,7 @@ int lbm_batch_set_fusion_depth(lbm_batch* b, int steps);
 int lbm_batch_get_fusion_depth(lbm_batch* b, int* steps);
 
 /* Autotune the persistent launch: each candidate (nodes per thread in {1, 2, 4}, or two or, for
- * FP64 and FP32, three steps per pass at the current strip height (32 rows unless set), x groups
+ * FP64 and FP32, three steps per pass at the current strip height (64 rows unless set), x groups
  * per CU in {limit, limit/2}, limit = the probed residency limit of that shape) runs `trials`
  * (>= 1) steps, pairs or triples that all recompute from the same input copy, so states and
  * counters are unchanged, and the blow-up records are restored afterwards.  Keeps the fastest per

@@ -444,9 +444,9 @@ struct lbm_batch {
     int cus = 0, occ[5] = {0, 0, 0, 0, 0};     // CUs, occupancy limit per shape (runtime query)
     int resident[5] = {0, 0, 0, 0, 0};         // groups per CU confirmed co-resident (0 = not probed)
     int npt = 1, gpc = 0;              // launch shape (gpc 0 = occupancy limit)
-    // fused passes over strips of hs rows (32: on the 512-instance FP64 sweep 4% faster than 16 with
-    // two steps per pass, 10% with three)
-    int fuse = 0, hs = 32;
+    // fused passes over strips of hs rows (64: on the 512-instance FP64 sweep with three steps per
+    // pass on 48-column strips 77-78 GLUPS against 75 with 32 rows, 69 with 16, 76-77 with 80-128)
+    int fuse = 0, hs = 64;
     int depth = 2;                     // steps per fused pass: 2 (runs of 4 steps) or 3
     long long step = 0;                // host mirror of the step counter
     void* d_desc[3] = {nullptr, nullptr, nullptr};  // descriptors per NPT (tile0 differs)

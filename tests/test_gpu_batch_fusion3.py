@@ -88,7 +88,7 @@ def test_three_steps_autotune_and_validation(gpu):
     blow0 = b.status()[1]
     npt, gpc, us = b.autotune(2)
     print(f"autotune: npt {npt} gpc {gpc} fusion {b.fusion()} depth {b.fusion_depth()} {us:.1f} us/step", flush=True)
-    assert npt in (1, 2, 4) and gpc >= 1 and us > 0 and b.fusion() in (0, 32) and b.fusion_depth() in (2, 3)
+    assert npt in (1, 2, 4) and gpc >= 1 and us > 0 and b.fusion() in (0, 64) and b.fusion_depth() in (2, 3)
     step, blow = b.status()  # the timed passes ran ahead of the counter: records as they were
     assert step == 5 and list(blow) == list(blow0)
     b.set_fusion(16)  # a strip height other than the autotuned one: the tables are re-dealt
