@@ -88,7 +88,7 @@ def test_adjoint_run_matches_oracle(gpu, name):
         loss = transport_loss(u0, w, torch.tensor(rho, device=gpu), torch.tensor(np.stack([tx, ty]), device=gpu),
                               model=name, nsteps=steps, prec="f64", schedule=schedule, slots=slots)
         loss.backward()
-        results[schedule] = (float(loss), u0.grad.cpu().numpy(), w.grad.numpy())
+        results[schedule] = (float(loss.detach()), u0.grad.cpu().numpy(), w.grad.numpy())
         gu, gw = results[schedule][1], results[schedule][2]
         eu = np.max(np.abs(gu - np.stack([dux, duy]))) / np.max(np.abs(np.stack([dux, duy])))
         ew = np.max(np.abs(gw - dw)) / np.max(np.abs(dw))
