@@ -103,9 +103,9 @@ def test_collision_model_identities():
 @pytest.mark.parametrize("preset", ["SRT", "REG"])
 def test_flow_at_rest_is_stable(preset):
     # Section 4b finds the flow at rest stable for every model but K.  With the textbook cumulants
-    # (K22 = n22 - n20 n02 - 2 n11^2) K is stable at rest too: under SRT the quadratic term has no
-    # first variation about equilibrium, so K linearises exactly like CM there (checked below), and
-    # under REG the difference is a linear coupling of k22 to the relaxed second-order moments.
+    # (K22 = n22 - n20 n02 - 2 n11^2) K is stable at rest too: it linearises exactly like CM under
+    # SRT (checked below) and like CHM under REG, as every admissible reading of K must
+    # (test_oracle_cumulant_readings.py); this departs from the paper's K.
     ks = np.linspace(-math.pi, math.pi, 17)
     for model in inputs.MODEL_NAMES:
         JJ = J(model, 4, inputs.rates(1e-6, preset))
