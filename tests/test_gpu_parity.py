@@ -27,7 +27,7 @@ def rel(a, b):
 
 
 def orders(name):
-    return [4] if name in CENTRAL else [2, 4]
+    return [4] if name in CENTRAL else [2, 3, 4]
 
 
 def omega_sets():
@@ -282,3 +282,22 @@ def test_argument_errors_of_two_step_and_dvbe_entry_points(gpu):
     bad = dict(pt, eq_order=5)
     with pytest.raises(B.LbmError):
         lsa.dvbe_growth([bad], kx, kx)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_third_order_equilibrium_default_launch(gpu, prec):
+    # N = 3 (A21, A12 kept, A22 = 0) on a grid large enough for the default launch of three steps
+    # per launch, 7 steps (two three-step launches and a single step)
+    nx, ny, steps = 520, 512, 7
+    rho, ux, uy = inputs.vortex_fields(nx, ny, 0.3, beta=0.5, radius_frac=0.15)
+    f0 = oracle.init_eq(3, rho, ux, uy)
+    for name in ("BGK", "RM", "HM", "PR", "RR"):
+        omega = omega_sets()["custom"]
+        print(f"{name} N=3 {prec} {nx}x{ny}", flush=True)
+        sim = Sim(rho, ux, uy, prec=prec, eq_order=3, device=gpu)
+        assert sim.fusion_depth(name) == 3
+        sim.step(name, omega, steps)
+        g = sim.state().cpu().numpy()
+        sim.close()
+        ref = oracle.step(f0, inputs.MODEL_CODES[name], 3, omega, steps)
+        assert rel(g, ref) < (1e-12 if prec == "f64" else 1e-5), (name, rel(g, ref))
