@@ -365,9 +365,13 @@ __global__ __launch_bounds__(256) void k_batch_get(const typename Store<PREC>::S
 // its tiles in order (deterministic).
 template <int PREC>
 __global__ __launch_bounds__(kTileThreads) void k_batch_u2_tiles(
-    const typename Store<PREC>::S* __restrict__ cur, const BDesc<typename Store<PREC>::R>* __restrict__ desc,
-    const int* __restrict__ tile_inst, double* __restrict__ partial) {
+    const typename Store<PREC>::S* __restrict__ base, long long copy_elems, const long long* __restrict__ step_ctr,
+    const BDesc<typename Store<PREC>::R>* __restrict__ desc, const int* __restrict__ tile_inst,
+    double* __restrict__ partial) {
     __shared__ double red[kTileThreads / 64];
+    // the copy of the current step's parity (read on the device: a replayed graph advances the
+    // counter without the host)
+    const typename Store<PREC>::S* cur = base + (*step_ctr & 1) * copy_elems;
     const int j = tile_inst[blockIdx.x];
     const BDesc<typename Store<PREC>::R>& d = desc[j];
     const int c = (blockIdx.x - d.tile0) * kTileThreads + threadIdx.x;
@@ -405,11 +409,11 @@ __global__ void k_batch_u2_sum(const BDesc<R>* __restrict__ desc, int n, const d
 
 // Retire the instances whose flag is 0 (for good) and record the step at which they left.
 __global__ void k_retire(const int* __restrict__ flags, int* __restrict__ active, int* __restrict__ retired,
-                         int n, int step) {
+                         int n, const long long* __restrict__ step_ctr) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n && active[i] && !flags[i]) {
         active[i] = 0;
-        retired[i] = step;
+        retired[i] = (int)*step_ctr;
     }
 }
 
@@ -725,7 +729,15 @@ int ensure_resident(lbm_batch* b, int k) {
 // launches short enough that the barrier counter G * units stays below 2^31.
 int run_units(lbm_batch* b, int k, int units) {
     if (units <= 0) return LBM_OK;
-    int rc = ensure_resident(b, k);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    int rc = check_hip(hipStreamIsCapturing(b->stream, &cap), "hipStreamIsCapturing");
+    if (rc != LBM_OK) return rc;
+    const bool capturing = cap != hipStreamCaptureStatusNone;
+    // the residency probe synchronises: it cannot run inside a stream capture
+    if (capturing && b->resident[k] == 0)
+        return set_error(LBM_ESTATE, "launch shape not probed yet: run (or autotune) the batch once with the "
+                                     "same settings before capturing it");
+    rc = ensure_resident(b, k);
     if (rc != LBM_OK) return rc;
     const long long G = grid_size(b, k);
     const int chunk = (int)std::min<long long>(units, (1LL << 31) / G);
@@ -735,7 +747,9 @@ int run_units(lbm_batch* b, int k, int units) {
         rc = run_persistent(b, k, u, 1);
         if (rc != LBM_OK) return rc;
         left -= u;
-        b->step += k == 4 ? 3LL * u : (k == 3 ? 2LL * u : (long long)u);
+        // a captured launch runs only when the graph is replayed; the synchronising calls then
+        // take the step from the device counter
+        if (!capturing) b->step += k == 4 ? 3LL * u : (k == 3 ? 2LL * u : (long long)u);
     }
     return LBM_OK;
 }
@@ -1023,7 +1037,8 @@ int lbm_batch_status(lbm_batch* b, long long* step, long long* blowup_steps) {
     if (rc != LBM_OK) return rc;
     if (err == 2) return set_error(LBM_EHIP, "persistent launch stopped: an XCD that owns instances got no workgroup");
     if (err) return set_error(LBM_EHIP, "persistent launch stopped: a barrier timed out");
-    if (dstep != b->step) return set_error(LBM_EHIP, "device step counter %lld != %lld", dstep, b->step);
+    if (dstep < b->step) return set_error(LBM_EHIP, "device step counter %lld behind %lld", dstep, b->step);
+    b->step = dstep;  // ahead after replays of a captured run
     if (step) *step = b->step;
     if (blowup_steps)
         for (int j = 0; j < b->n; ++j) blowup_steps[j] = flags[j] == INT_MAX ? -1 : (long long)flags[j];
@@ -1047,7 +1062,10 @@ int lbm_batch_get_state(lbm_batch* b, int instance, double* f) {
         rc = check_hip(hipMemcpy(&ret, b->d_retired + instance, sizeof(int), hipMemcpyDeviceToHost), "copy retired");
     if (rc == LBM_OK)
         rc = check_hip(hipMemcpy(&last, b->d_lastcopy + instance, sizeof(int), hipMemcpyDeviceToHost), "copy last copy");
+    long long dstep = 0;
+    if (rc == LBM_OK) rc = check_hip(hipMemcpy(&dstep, b->d_step, sizeof(dstep), hipMemcpyDeviceToHost), "copy step");
     if (rc != LBM_OK) return rc;
+    if (dstep > b->step) b->step = dstep;  // ahead after replays of a captured run
     const int sc = (blow == INT_MAX && ret == INT_MAX) ? (int)(b->step & 1) : last;
     const size_t eoff = (size_t)(sc * b->copy_elems + b->off[instance]);
     const Pop9 fref = reference_populations(storage_reference(b->prec, d.rho0, d.ux0, d.uy0), d.eq_order);
@@ -1071,26 +1089,25 @@ int lbm_batch_get_state(lbm_batch* b, int instance, double* f) {
 int lbm_batch_mean_u2(lbm_batch* b, double* mean_u2) {
     if (!b) return set_error(LBM_ESTATE, "batch is NULL");
     if (!mean_u2) return set_error(LBM_EINVAL, "mean_u2 is NULL");
-    const long long eoff = (b->step & 1) * b->copy_elems;
     const dim3 tiles(b->ntiles[0]), tb(kTileThreads), ib((b->n + 255) / 256), ibt(256);
     switch (b->prec) {
         case LBM_F64:
             hipLaunchKernelGGL(k_batch_u2_tiles<kF64>, tiles, tb, 0, b->stream,
-                               reinterpret_cast<const double*>(b->buf) + eoff,
+                               reinterpret_cast<const double*>(b->buf), b->copy_elems, b->d_step,
                                reinterpret_cast<const BDesc<double>*>(b->d_desc[0]), b->d_tiles[0], b->d_u2part);
             hipLaunchKernelGGL(k_batch_u2_sum<double>, ib, ibt, 0, b->stream,
                                reinterpret_cast<const BDesc<double>*>(b->d_desc[0]), b->n, b->d_u2part, mean_u2);
             break;
         case LBM_F32_SHIFTED:
             hipLaunchKernelGGL(k_batch_u2_tiles<kF32>, tiles, tb, 0, b->stream,
-                               reinterpret_cast<const float*>(b->buf) + eoff,
+                               reinterpret_cast<const float*>(b->buf), b->copy_elems, b->d_step,
                                reinterpret_cast<const BDesc<float>*>(b->d_desc[0]), b->d_tiles[0], b->d_u2part);
             hipLaunchKernelGGL(k_batch_u2_sum<float>, ib, ibt, 0, b->stream,
                                reinterpret_cast<const BDesc<float>*>(b->d_desc[0]), b->n, b->d_u2part, mean_u2);
             break;
         default:
             hipLaunchKernelGGL(k_batch_u2_tiles<kF16>, tiles, tb, 0, b->stream,
-                               reinterpret_cast<const _Float16*>(b->buf) + eoff,
+                               reinterpret_cast<const _Float16*>(b->buf), b->copy_elems, b->d_step,
                                reinterpret_cast<const BDesc<float>*>(b->d_desc[0]), b->d_tiles[0], b->d_u2part);
             hipLaunchKernelGGL(k_batch_u2_sum<float>, ib, ibt, 0, b->stream,
                                reinterpret_cast<const BDesc<float>*>(b->d_desc[0]), b->n, b->d_u2part, mean_u2);
@@ -1103,7 +1120,7 @@ int lbm_batch_set_active(lbm_batch* b, const int* active) {
     if (!b) return set_error(LBM_ESTATE, "batch is NULL");
     if (!active) return set_error(LBM_EINVAL, "active is NULL");
     hipLaunchKernelGGL(k_retire, dim3((b->n + 255) / 256), dim3(256), 0, b->stream, active, b->d_active,
-                       b->d_retired, b->n, (int)b->step);
+                       b->d_retired, b->n, b->d_step);
     return check_hip(hipGetLastError(), "batch set_active launch");
 }
 
