@@ -64,9 +64,10 @@ def profile_path(prec: str, kind: str) -> str:
     return os.path.join(PROFILE_DIR, f"step_kernels_{prec}_dsl4096_{kind}.md")
 
 
-def measured_traffic(model: str, prec: str):
-    """HBM bytes per launch of the step kernel from the committed counter summary, or None when
-    there is none for this kernel or its sources changed since it was taken."""
+def counter_record(model: str, prec: str):
+    """The step kernel's record in the committed counter summary (HBM bytes, VALUBusy, flops per
+    node update), or None when there is none for this kernel or its sources changed since the
+    counters were taken."""
     path = profile_path(prec, "counters")
     try:
         with open(path) as fh:
@@ -76,53 +77,138 @@ def measured_traffic(model: str, prec: str):
         return None
     if blob.get("step_source_hash") != step_source_hash():
         return None
-    rec = blob.get("per_launch", {}).get(model)
+    return blob.get("per_launch", {}).get(model)
+
+
+def measured_traffic(model: str, prec: str):
+    """HBM bytes per launch of the step kernel from the committed counter summary, or None."""
+    rec = counter_record(model, prec)
     return None if rec is None else rec["hbm_bytes"]
 
 
 def measured_valu_busy(model: str, prec: str):
     """Fraction of the vector-ALU issue capacity the step kernel used (rocprofv3 VALUBusy) from the
-    committed counter summary, or None when there is none for this kernel or its sources changed
-    since it was taken."""
-    path = profile_path(prec, "counters")
-    try:
-        with open(path) as fh:
-            text = fh.read()
-        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
-    except (OSError, IndexError, ValueError):
-        return None
-    if blob.get("step_source_hash") != step_source_hash():
-        return None
-    rec = blob.get("per_launch", {}).get(model)
+    committed counter summary, or None."""
+    rec = counter_record(model, prec)
     return None if rec is None or rec.get("valu_busy") is None else rec["valu_busy"]
 
 
-def cpu_baseline(models, n: int = 4096, rows: int = 2048, steps: int = 1):
-    """The oracle (single-threaded FP64 C) on a bounded sample of the bench workload: `rows` full
-    rows (4096 nodes wide) of the 4096 x 4096 double shear layer with the bench's rates, run as a
-    periodic band, `steps` step(s) per model (10-30 s of one core)."""
+# FP32 / FP64 vector peaks of MI355X (256 CUs at 2.4 GHz): 157.3 TFLOP/s counts packed FP32 FMAs
+# (two per lane and cycle), 78.6 TFLOP/s one FMA per lane and cycle (FP64, or FP32 built without
+# packed FP32, as this library is)
+VECTOR_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+UNPACKED_PEAK_TFLOPS = 78.6
+VALU_BOUND = 0.85  # VALUBusy from which a kernel counts as bound by vector-ALU issue
+
+
+def limiter(rec, hbm_frac_measured):
+    """What bounds a step kernel, from its counters: vector-ALU issue (VALUBusy >= 0.85), HBM
+    (measured traffic >= 0.8 of the peak), else neither: the pass structure / latency."""
+    if rec is None:
+        return None
+    if rec.get("valu_busy") is not None and rec["valu_busy"] >= VALU_BOUND:
+        return "valu-issue"
+    if hbm_frac_measured is not None and hbm_frac_measured >= 0.8:
+        return "hbm"
+    return "pass-structure/latency"
+
+
+def roofline_block(model, prec, kname, cells, bpc, spl, launch_us, stream_launch_us, n):
+    """Roofline entry of the dominant kernel.  The bound comes from its counters: vector-ALU issue
+    gives "alu" with the algorithmic flops (the single-step kernel's flops per node update x nodes x
+    steps per launch) over the launch time against the FP32 (FP64) vector peak; otherwise "hbm"
+    with the algorithmic bytes per launch (each population read and written once) over the launch
+    time against 8 TB/s.  Both views are reported either way, with the per-update HBM figure of the
+    18 s bytes-per-node-and-step model (above 1 when a launch advances several steps per read)."""
+    rec = counter_record(model, prec) if n == 4096 else None
+    traffic = None if rec is None else rec["hbm_bytes"]
+    valu_busy = None if rec is None else rec.get("valu_busy")
+    fpu = None if rec is None else rec.get("flops_per_update")
+    gbs = cells * bpc / (launch_us * 1e-6) / 1e9
+    measured_frac = None if traffic is None else traffic / (launch_us * 1e-6) / 1e9 / HBM_PEAK_GBS
+    hbm = {"achieved_gbs": round(gbs, 1), "frac_at_bytes_per_launch": round(gbs / HBM_PEAK_GBS, 4),
+           "per_update_gbs": round(gbs * spl, 1), "frac_at_18s_bytes_per_update": round(gbs * spl / HBM_PEAK_GBS, 4),
+           "measured_frac": None if measured_frac is None else round(measured_frac, 4),
+           "stream_only_gbs": round(cells * bpc / (stream_launch_us * 1e-6) / 1e9, 1),
+           "frac_of_stream_only": round(stream_launch_us / launch_us, 4)}
+    alu = None
+    if fpu is not None:
+        tf = fpu * cells * spl / (launch_us * 1e-6) / 1e12
+        peak = VECTOR_PEAK_TFLOPS[prec if prec == "f64" else "f32"]
+        alu = {"achieved_tflops": round(tf, 2), "peak_tflops": peak, "frac": round(tf / peak, 4),
+               "frac_of_unpacked_peak": round(tf / UNPACKED_PEAK_TFLOPS, 4),
+               "flops_per_update": fpu, "executed_flops_per_update": rec.get("executed_flops_per_update")}
+    lim = limiter(rec, measured_frac)
+    common = {"kernel": f"{kname}<{model}>", "limiter": lim, "valu_busy": valu_busy, "traffic": traffic,
+              "traffic_unit": "HBM bytes per launch (counters)", "algorithmic_bytes": cells * bpc,
+              "launch_us": round(launch_us, 2), "steps_per_launch": spl, "hbm": hbm, "alu": alu}
+    if lim == "valu-issue" and alu is not None:
+        return {"bound": "alu", "achieved": alu["achieved_tflops"], "peak": alu["peak_tflops"], "unit": "TFLOP/s",
+                "frac": alu["frac"], **common}
+    return {"bound": "hbm", "achieved": hbm["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": hbm["frac_at_bytes_per_launch"], **common}
+
+
+def _oracle_rate(job):
+    """One model's oracle run (single-threaded FP64 C, in a spawned process): MLUPS on the n x n
+    double shear layer (the bench workload's field and rates at that size), `steps` steps."""
+    name, n, steps = job
     import oracle
     from paper_2002_05265_amd import inputs
 
-    rho, ux, uy = (np.ascontiguousarray(a[:rows]) for a in inputs.dsl_fields(n, n, 0.1))
+    rho, ux, uy = inputs.dsl_fields(n, n, 0.1)
     omega = inputs.rates(inputs.dsl_nu(n), "REG")
     f0 = oracle.init_eq(4, rho, ux, uy)
-    elapsed = 0.0
-    for name in models:
-        t0 = time.perf_counter()
-        f = oracle.step(f0, oracle.MODELS[name], 4, omega, steps)
-        elapsed += time.perf_counter() - t0
-        del f
-    updates = n * rows * steps * len(models)
+    del rho, ux, uy
+    t0 = time.perf_counter()
+    f = oracle.step(f0, oracle.MODELS[name], 4, omega, steps)
+    dt = time.perf_counter() - t0
+    del f, f0
+    return name, n, steps, n * n * steps / dt / 1e6, dt
+
+
+def host_cpu():
+    """(CPU model name from /proc/cpuinfo, logical CPUs of the host, CPUs this process may use)."""
     cpu = "unknown"
     try:
         with open("/proc/cpuinfo") as fh:
             cpu = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), cpu)
     except OSError:
         pass
-    return {"value": updates / elapsed / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle", "host_cpu": cpu,
-            "sample": f"{rows} rows x {n} of the {n}x{n} double shear layer (a periodic band of the bench "
-                      f"workload), FP64, {steps} step(s) of each of {len(models)} models, {elapsed:.1f} s total"}
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return cpu, os.cpu_count(), usable
+
+
+def cpu_baseline(models, sizes=((1024, 100), (4096, 3)), procs: int = 8):
+    """The oracle (single-threaded FP64 C) timed per model on the bench workload at two sizes:
+    the double shear layer at 1024^2 for 100 steps and at the bench's 4096^2 for 3 steps.  Every
+    run uses one core; the runs go to `procs` spawned processes at a time (each its own core), so
+    the per-model rates are one-core rates.  `value` is the one-core rate of a bench step (one
+    step of every model) at 4096^2: total updates over total one-core seconds."""
+    import multiprocessing as mp
+
+    cpu, ncpu, usable = host_cpu()
+    jobs = [(m, n, st) for n, st in sizes for m in models]
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(max(1, min(procs, usable or 1, len(jobs)))) as pool:
+        res = pool.map(_oracle_rate, jobs, chunksize=1)
+    wall = time.perf_counter() - t0
+    per_model = {m: {} for m in models}
+    for name, n, st, mlups, dt in res:
+        per_model[name][f"{n}x{n}x{st}"] = round(mlups, 3)
+    big_n, big_st = sizes[-1]
+    big = [(dt, n * n * st) for _, n, st, _, dt in res if n == big_n]
+    value = sum(u for _, u in big) / sum(dt for dt, _ in big) / 1e6
+    return {"value": round(value, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "host_cpu": cpu, "host_nproc": ncpu, "usable_cpus": usable, "per_model": per_model,
+            "sample": (f"every model on the double shear layer at "
+                       + " and ".join(f"{n}x{n} for {st} steps" for n, st in sizes)
+                       + f" (FP64, one thread per run; {min(procs, usable or 1, len(jobs))} runs at a time "
+                       f"in separate processes, {wall:.0f} s wall); value: one core's rate over one step of "
+                       f"each model at {big_n}x{big_n}")}
 
 
 def single_step_rates(sims, models, omega, cells, bpc, steps):
@@ -163,6 +249,22 @@ def cache_resident_rates(models, sizes=(1024, 512), precs=("f32", "f64"), steps:
     return {"cache_resident": True, "steps": steps, "mlups": out}
 
 
+def settle_clocks(seconds: float = 0.3):
+    """Keep the GPU busy with plain device copies (256 MiB each way) for `seconds` before warm-up
+    steps: after an idle stretch (host-side set-up) MI355X runs the step kernels ~15% slower for
+    about 10 ms once work resumes (measured), which would fall into short timed windows."""
+    import torch
+
+    a = torch.empty(1 << 26, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(16):
+            b.copy_(a)
+        torch.cuda.synchronize()
+    del a, b
+
+
 def time_models(prec: str, n: int, models, steps: int, warmup: int, omega, fields):
     """Per-model timing of `steps` launches on an n x n grid (HIP events on the launch stream)."""
     import torch
@@ -172,6 +274,7 @@ def time_models(prec: str, n: int, models, steps: int, warmup: int, omega, field
     out = {}
     for m in models:
         s = Sim(*fields, prec=prec, eq_order=4, device="cuda:0")
+        settle_clocks(0.1)
         s.step(m, omega, warmup)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -485,10 +588,27 @@ def _find_csv(d, suffix):
     raise FileNotFoundError(f"no *{suffix} under {d}")
 
 
-def _per_dispatch(rows, key):
-    """Mean counter value (KiB) per dispatch of every kernel whose name contains key."""
-    vals = [float(r["Counter_Value"]) for r in rows if key in r["Kernel_Name"]]
+def _per_dispatch(rows, key, counter=None):
+    """Mean counter value per dispatch of every kernel whose name contains key (only rows of
+    `counter` when given: a run that collects several counters has one row per counter)."""
+    vals = [float(r["Counter_Value"]) for r in rows
+            if key in r["Kernel_Name"] and (counter is None or r.get("Counter_Name") == counter)]
     return (sum(vals) / len(vals), len(vals)) if vals else (None, 0)
+
+
+def flop_counters(prec: str):
+    """The VALU instruction counters whose sum gives the floating-point operations of the
+    arithmetic precision (FP32 for the shifted storages, FP64 otherwise); FMA counts twice."""
+    t = "F64" if prec == "f64" else "F32"
+    return [f"SQ_INSTS_VALU_ADD_{t}", f"SQ_INSTS_VALU_MUL_{t}", f"SQ_INSTS_VALU_FMA_{t}", f"SQ_INSTS_VALU_TRANS_{t}"]
+
+
+def _flops_per_dispatch(rows, key, prec):
+    """Floating-point operations per dispatch: 64 lanes x (add + mul + trans + 2 fma) wave instructions."""
+    add, mul, fma, trans = (_per_dispatch(rows, key, c)[0] for c in flop_counters(prec))
+    if None in (add, mul, fma, trans):
+        return None
+    return 64.0 * (add + mul + trans + 2.0 * fma)
 
 
 def profile_summary(out_root: str, prec: str, n: int, commands: dict):
@@ -530,16 +650,22 @@ def profile_summary(out_root: str, prec: str, n: int, commands: dict):
     copy_key = "copyBuffer"  # the runtime's device-to-device copy kernel behind the 1 GiB copy
     valu_dir = os.path.join(out_root, "rp_valu")
     valu = _csv_rows(_find_csv(valu_dir, "counter_collection.csv")) if os.path.isdir(valu_dir) else []
+    flops_dir = os.path.join(out_root, "rp_flops")
+    flops = _csv_rows(_find_csv(flops_dir, "counter_collection.csv")) if os.path.isdir(flops_dir) else []
     cf, _ = _per_dispatch(cfetch, copy_key)
     cw, _ = _per_dispatch(cwrite, copy_key)
     gib_kib = (1 << 30) / 1024
     fscale, wscale = gib_kib / cf, gib_kib / cw
     per_launch = {}
-    rows = ["| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) | / algorithmic | VALUBusy % |",
-            "|---|---|---|---|---|---|---|"]
+    rows = ["| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) | / algorithmic | VALUBusy % "
+            "| flops per node and step |",
+            "|---|---|---|---|---|---|---|---|"]
+    steps_of = {"k_step3": 3, "k_step3n": 3, "k_step2": 2, "k_step": 1}
     for m in MODEL_ORDER:
         # the first kernel of the model found (three-step, then two-step, then single-step) is the
-        # one reported
+        # one reported; the single-step kernel (no halo recomputation) gives the algorithmic flops
+        # per node update
+        single = _flops_per_dispatch(flops, step_kernel_keys(m, prec)[-1][1], prec)
         for label, key in step_kernel_keys(m, prec):
             f_kib, nf = _per_dispatch(fetch, key)
             w_kib, _ = _per_dispatch(write, key)
@@ -548,19 +674,29 @@ def profile_summary(out_root: str, prec: str, n: int, commands: dict):
             hbm = f_kib * 1024 * fscale + w_kib * 1024 * wscale
             vb, _ = _per_dispatch(valu, key)
             vtxt = "" if vb is None else f"{vb:.1f}"
-            rows.append(f"| {label}<{m}, {prec}> | {nf} | {f_kib:.1f} | {w_kib:.1f} | {hbm:.4g} | {hbm / alg:.4f} | {vtxt} |")
+            fl = _flops_per_dispatch(flops, key, prec)
+            executed = None if fl is None else fl / (cells * steps_of[label])
+            ftxt = "" if executed is None else f"{executed:.1f}"
+            rows.append(f"| {label}<{m}, {prec}> | {nf} | {f_kib:.1f} | {w_kib:.1f} | {hbm:.4g} | {hbm / alg:.4f} | "
+                        f"{vtxt} | {ftxt} |")
             per_launch.setdefault(m, {"kernel": label, "fetch_kib": round(f_kib, 1), "write_kib": round(w_kib, 1),
                                       "hbm_bytes": int(round(hbm)), "vs_algorithmic": round(hbm / alg, 4),
-                                      "valu_busy": None if vb is None else round(vb / 100.0, 4)})
+                                      "valu_busy": None if vb is None else round(vb / 100.0, 4),
+                                      "flops_per_update": None if single is None else round(single / cells, 2),
+                                      "executed_flops_per_update": None if executed is None else round(executed, 2)})
     blob = {"step_source_hash": step_source_hash(), "prec": prec, "n": n, "algorithmic_bytes": alg,
             "copy_probe_kib": {"fetch": round(cf, 1), "write": round(cw, 1), "true": gib_kib},
             "scale": {"fetch": round(fscale, 4), "write": round(wscale, 4)}, "per_launch": per_launch}
     text = [f"# k_step3 / k_step2 / k_step ({prec}, {n}x{n} double shear layer): HBM counters", "",
             "Commands (each counter in a run of its own):", "", "```", commands["fetch"], commands["write"],
-            commands["copy_fetch"], commands["copy_write"], commands["valu"], "```", "",
+            commands["copy_fetch"], commands["copy_write"], commands["valu"], commands["flops"], "```", "",
             "VALUBusy is rocprofv3's derived counter 100 * SQ_ACTIVE_INST_VALU / CUs / GRBM_GUI_ACTIVE: the "
             "share of the SIMDs' vector-ALU issue time in use (100 = every SIMD issues a VALU instruction "
             "every cycle it can).", "",
+            "Flops per node and step: 64 lanes x (ADD + MUL + TRANS + 2 FMA) VALU instructions of the "
+            "arithmetic's precision per dispatch (the SQ_INSTS_VALU_*_F32 or _F64 counters), over the nodes "
+            "and steps the dispatch advances; the fused kernels' figure includes the halo recomputation. "
+            "The single-step kernel's figure (`flops_per_update` below) is the algorithmic one.", "",
             "Calibration: a plain device copy of 1 GiB (torch, same box) reads "
             f"{cf:.1f} KiB of FETCH_SIZE and {cw:.1f} KiB of WRITE_SIZE per dispatch against "
             f"{gib_kib:.0f} KiB moved each way, so FETCH_SIZE is scaled by {fscale:.4f} and "
@@ -610,6 +746,8 @@ PROFILE_COMMANDS = {
                   "python bench.py --copy-probe",
     "valu": f"rocprofv3 --pmc VALUBusy --output-format csv -d gpurun_out/rp_valu -o bench -- "
             f"python bench.py {PROFILE_ARGS}",
+    "flops": f"rocprofv3 --pmc {' '.join(flop_counters('f32'))} --output-format csv -d gpurun_out/rp_flops -o bench -- "
+             f"python bench.py {PROFILE_ARGS}",
 }
 
 
@@ -622,7 +760,8 @@ def profile_commands(prec: str) -> dict:
     args = f"{PROFILE_ARGS} --prec {prec}"
     d = f"gpurun_out/p_{prec}"
     out = {k: f"rocprofv3 --pmc {c} --output-format csv -d {d}/rp_{k} -o bench -- python bench.py {args}"
-           for k, c in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE"), ("valu", "VALUBusy"))}
+           for k, c in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE"), ("valu", "VALUBusy"),
+                        ("flops", " ".join(flop_counters(prec))))}
     out["trace"] = (f"rocprofv3 --kernel-trace --stats --output-format csv -d {d}/rp_trace -o bench -- "
                     f"python bench.py {args}")
     out["copy_fetch"], out["copy_write"] = PROFILE_COMMANDS["copy_fetch"], PROFILE_COMMANDS["copy_write"]
@@ -688,6 +827,7 @@ def main():
     omega = inputs.rates(nu, "REG")
     rho, ux, uy = inputs.dsl_fields(n, n, mach)
     sims = {m: Sim(rho, ux, uy, prec=args.prec, eq_order=4, device="cuda:0") for m in models}
+    settle_clocks()
     for m, s in sims.items():
         s.step(m, omega, args.warmup)
     torch.cuda.synchronize()
@@ -728,11 +868,14 @@ def main():
     dominant = max(models, key=lambda m: per_model[m]["us_per_step"])
     spl = per_model[dominant]["steps_per_launch"]
     launch_us = per_model[dominant]["us_per_step"] * spl
-    achieved = cells * bpc / (launch_us * 1e-6) / 1e9
-    traffic = measured_traffic(dominant, args.prec) if n == 4096 else None
-    valu_busy = measured_valu_busy(dominant, args.prec) if n == 4096 else None
     kname = {3: "k_step3n" if args.prec == "f64" and per_model[dominant]["ring_rows"] == 4 else "k_step3",
              2: "k_step2", 1: "k_step"}[spl]
+    for m in models:
+        rec = counter_record(m, args.prec) if n == 4096 else None
+        lu = per_model[m]["us_per_step"] * per_model[m]["steps_per_launch"]
+        mf = None if rec is None else rec["hbm_bytes"] / (lu * 1e-6) / 1e9 / HBM_PEAK_GBS
+        per_model[m]["valu_busy"] = None if rec is None else rec.get("valu_busy")
+        per_model[m]["limiter"] = limiter(rec, mf)
     line = {
         "metric": "MLUPS per collision model at 4096^2 FP32 + % HBM roofline; adjoint/batched vs plain",
         "value": round(value, 1),
@@ -750,19 +893,7 @@ def main():
                                f"{'shifted ' if args.prec != 'f64' else ''}{args.prec} populations, "
                                f"REG rates, 8 collision models (one grid each)",
                    "nx": n, "ny": n, "models": models, "omega": [round(w, 6) for w in omega]},
-        # one launch of the dominant kernel reads and writes every population once; with two
-        # steps per launch it advances the grid two steps for those bytes
-        "roofline": {"bound": "hbm", "kernel": f"{kname}<{dominant}>", "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "traffic_unit": "bytes per launch",
-                     "algorithmic_bytes": cells * bpc, "launch_us": round(launch_us, 2),
-                     "steps_per_launch": spl,
-                     "single_step_equivalent_gbs": round(achieved * spl, 1),
-                     "measured_frac": (None if traffic is None else
-                                       round(traffic / (launch_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)),
-                     "valu_busy": valu_busy,
-                     "stream_only_gbs": round(cells * bpc / (stream_launch_us * 1e-6) / 1e9, 1),
-                     "frac_of_stream_only": round(stream_launch_us / launch_us, 4)},
+        "roofline": roofline_block(dominant, args.prec, kname, cells, bpc, spl, launch_us, stream_launch_us, n),
         "single_step": single,
         "per_model": per_model,
         "blowup": {m: st[1] for m, st in status.items()},

@@ -72,6 +72,15 @@ def test_profile_summary_round_trip(tmp_path, monkeypatch):
                [[f'"{k3}"', 100.0], [f'"{k3}"', 110.0], [f'"{k1}"', 40.0]])
     _write_csv(str(out / "rp_write" / "b_counter_collection.csv"), cc, [[f'"{k3}"', 50.0], [f'"{k1}"', 30.0]])
     _write_csv(str(out / "rp_valu" / "b_counter_collection.csv"), cc, [[f'"{k3}"', 97.0]])
+    # flop counters: one row per counter and dispatch; the single-step K kernel gives the
+    # algorithmic flops per node update, the three-step one the executed flops (halo included)
+    k1k = "void (anonymous namespace)::k_step<5, 1, 1>(float const*, ...)"
+    fc = ["Kernel_Name", "Counter_Name", "Counter_Value"]
+    frows = []
+    for kern, (add, mul, fma, trans) in ((k3, (30, 20, 100, 3)), (k1k, (9, 6, 30, 1))):
+        for c, v in zip(bench.flop_counters("f32"), (add, mul, fma, trans)):
+            frows.append([f'"{kern}"', c, v * n * n / 64])
+    _write_csv(str(out / "rp_flops" / "b_counter_collection.csv"), fc, frows)
     bench.profile_summary(str(out), "f32", n, bench.profile_commands("f32"))
     counters = (prof / "step_kernels_f32_dsl4096_counters.md").read_text()
     blob = json.loads(counters.split("```json", 1)[1].split("```", 1)[0])
@@ -83,10 +92,23 @@ def test_profile_summary_round_trip(tmp_path, monkeypatch):
     assert rec["hbm_bytes"] == int(round(105.0 * 1024 * 2.0 + 50.0 * 1024))
     assert rec["vs_algorithmic"] == round(rec["hbm_bytes"] / alg, 4)
     assert rec["valu_busy"] == 0.97
+    assert rec["flops_per_update"] == 9 + 6 + 1 + 2 * 30
+    assert rec["executed_flops_per_update"] == round((30 + 20 + 3 + 2 * 100) / 3, 2)
     assert blob["per_launch"]["BGK"]["kernel"] == "k_step"
     # read back through the bench's own reader while the step sources hash as recorded
     assert bench.measured_traffic("K", "f32") == rec["hbm_bytes"]
     assert bench.measured_valu_busy("K", "f32") == 0.97
+    # the roofline entry takes its bound from the counters: K is VALU-bound (0.97), so "alu" with
+    # the algorithmic flops per launch over the launch time against the FP32 vector peak
+    roof = bench.roofline_block("K", "f32", "k_step3", n * n, 72, 3, 10.0, 8.0, 4096)
+    assert roof["bound"] == "alu" and roof["unit"] == "TFLOP/s" and roof["peak"] == 157.3
+    assert roof["achieved"] == round(76 * n * n * 3 / 10e-6 / 1e12, 2)
+    assert roof["frac"] == round(roof["achieved"] / 157.3, 4)
+    assert roof["hbm"]["frac_at_18s_bytes_per_update"] == round(3 * roof["hbm"]["frac_at_bytes_per_launch"], 4)
+    assert roof["traffic"] == rec["hbm_bytes"] and roof["limiter"] == "valu-issue"
+    # BGK has no VALUBusy record: HBM bound by default, at the algorithmic bytes per launch
+    roof = bench.roofline_block("BGK", "f32", "k_step", n * n, 72, 1, 10.0, 8.0, 4096)
+    assert roof["bound"] == "hbm" and roof["frac"] == round(n * n * 72 / 10e-6 / 1e9 / 8000.0, 4)
     trace = (prof / "step_kernels_f32_dsl4096_trace.md").read_text()
     assert "| k_step3<K, f32> | 4 | 3.00 |" in trace
     # a summary taken from other sources is not used
