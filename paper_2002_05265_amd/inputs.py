@@ -99,16 +99,21 @@ def dsl_nu(nx: int, mach: float = 0.1, reynolds: float = 3.0e4) -> float:
     return mach * CS * nx / reynolds
 
 
-def fourier_mode_fields(nx: int, ny: int, mach: float, rng: np.random.Generator,
-                        amplitude: float = 1e-3, kmax: int = 4):
-    """Uniform flow (Ma cs, 0) plus one velocity mode
-    amplitude * (cos th, sin th) * sin(2 pi (kx i / nx + ky j / ny) + phi),
-    integers kx, ky in [-kmax, kmax] not both zero, th and phi uniform in [0, 2 pi), rho = 1."""
+def _draw_mode(rng: np.random.Generator, kmax: int):
     while True:
         kx, ky = (int(v) for v in rng.integers(-kmax, kmax + 1, size=2))
         if kx or ky:
             break
     th, ph = rng.uniform(0.0, 2.0 * np.pi, size=2)
+    return kx, ky, float(th), float(ph)
+
+
+def fourier_mode_fields(nx: int, ny: int, mach: float, rng: np.random.Generator,
+                        amplitude: float = 1e-3, kmax: int = 4):
+    """Uniform flow (Ma cs, 0) plus one velocity mode
+    amplitude * (cos th, sin th) * sin(2 pi (kx i / nx + ky j / ny) + phi),
+    integers kx, ky in [-kmax, kmax] not both zero, th and phi uniform in [0, 2 pi), rho = 1."""
+    kx, ky, th, ph = _draw_mode(rng, kmax)
     i = np.arange(nx, dtype=np.float64)[None, :]
     j = np.arange(ny, dtype=np.float64)[:, None]
     s = np.sin(2.0 * np.pi * (kx * i / nx + ky * j / ny) + ph)
@@ -168,3 +173,29 @@ def sweep_instances(n: int = 512, seed: int = 2002_05265, sides=SWEEP_SIDES, mod
 def sweep_fields(inst: dict):
     rng = np.random.default_rng(inst["field_seed"])
     return fourier_mode_fields(inst["nx"], inst["ny"], inst["mach"], rng)
+
+
+def sweep_mode(inst: dict):
+    """(kx, ky) of the Fourier mode of sweep_fields(inst): the fields depend on the node (i, j)
+    only through the phase kx i / nx + ky j / ny."""
+    kx, ky, _, _ = _draw_mode(np.random.default_rng(inst["field_seed"]), 4)
+    return kx, ky
+
+
+def stratified_sweep_instances(per_model: int = 2, side: int = 64, seed: int = 2002_05265 + 20_000,
+                               ma_range=(0.0, 0.6), log10_nu_range=(-7.0, -2.0)):
+    """A stratified subset of the random stability sweep: per_model instances of every model on
+    side x side grids, Ma ~ U(ma_range), log10 nu ~ U(log10_nu_range), the SRT and REG presets in
+    turn within each model, one Fourier-mode perturbation seed each."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for m, model in enumerate(MODEL_NAMES):
+        for j in range(per_model):
+            k = m * per_model + j
+            ma = float(rng.uniform(*ma_range))
+            nu = float(10.0 ** rng.uniform(*log10_nu_range))
+            preset = "SRT" if j % 2 == 0 else "REG"
+            out.append({"index": k, "nx": side, "ny": side, "mach": ma, "nu": nu, "model": model,
+                        "preset": preset, "omega": rates(nu, preset), "eq_order": 4,
+                        "field_seed": seed + 1 + k})
+    return out
