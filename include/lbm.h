@@ -122,6 +122,21 @@ int lbm_step(lbm_ctx* ctx, int model, const double* omega, int nsteps);
  * stream when totals != NULL. */
 int lbm_moments(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* totals);
 
+/* For callers that cannot allocate device memory or synchronise (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): lbm_moments with the six totals written
+ * to device memory, asynchronously, and its reduction partials kept in a static device array of
+ * the library instead of the context's own scratch.  No allocation and no synchronisation.
+ *   ctx          a context made by lbm_init / lbm_init_shifted (outside the no-allocation region)
+ *   rho, ux, uy  device, nx*ny FP64 each, [y][x], or NULL: as lbm_moments
+ *   totals       device, 6 doubles, or NULL: the same six values lbm_moments returns on the
+ *                host, summed in the same order (identical results)
+ * Limit: grids whose per-cell launch has at most 65536 blocks of 256 nodes (16.7 M nodes, e.g.
+ * 4096 x 4096); larger grids get LBM_EINVAL.  The static array (2.5 MiB per device, held until
+ * the process ends) is shared by every context on a device and keeps the last call's partial
+ * sums; calls on one device that overlap in time (other streams or threads) race.  Calls in
+ * order on one stream are safe. */
+int lbm_moments_noalloc(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* totals);
+
 /* Step counter n of the current state and the first step whose state had a node with
  * !(rho > 0) (-1 if none so far).  A bad state n is detected when it is next read: by
  * lbm_step (state n is read by the step that leaves it) or by lbm_moments.

@@ -22,7 +22,8 @@ STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_EUNSUPPORTED", -3: "LBM_EHIP",
 
 # every symbol declared in include/*.h
 EXPORTS = (
-    "lbm_population_bytes", "lbm_init", "lbm_init_shifted", "lbm_step", "lbm_moments", "lbm_status",
+    "lbm_population_bytes", "lbm_init", "lbm_init_shifted", "lbm_step", "lbm_moments", "lbm_moments_noalloc",
+    "lbm_status",
     "lbm_get_state", "lbm_set_state", "lbm_set_launch", "lbm_set_fusion", "lbm_get_fusion",
     "lbm_set_fusion_depth", "lbm_get_fusion_depth", "lbm_autotune", "lbm_destroy", "lbm_last_error",
     "lbm_batch_population_bytes", "lbm_batch_create", "lbm_batch_run", "lbm_batch_status",
@@ -69,6 +70,7 @@ def _declare(L: ctypes.CDLL):
                                   _sz, _vp]),
         "lbm_step": (_i, [_vp, _i, _dp, _i]),
         "lbm_moments": (_i, [_vp, _vp, _vp, _vp, _dp]),
+        "lbm_moments_noalloc": (_i, [_vp, _vp, _vp, _vp, _vp]),
         "lbm_status": (_i, [_vp, ctypes.POINTER(_ll), ctypes.POINTER(_ll)]),
         "lbm_get_state": (_i, [_vp, _vp]),
         "lbm_set_state": (_i, [_vp, _vp, _ll]),
@@ -181,6 +183,11 @@ def lbm_moments(ctx: int, rho: int | None, ux: int | None, uy: int | None, want_
     tot = (ctypes.c_double * 6)() if want_totals else None
     _check(lib().lbm_moments(ctx, rho, ux, uy, tot), "lbm_moments")
     return list(tot) if want_totals else None
+
+
+def lbm_moments_noalloc(ctx: int, rho: int | None, ux: int | None, uy: int | None, totals: int | None):
+    """totals: device address of 6 doubles (or None); nothing is synchronised or allocated."""
+    _check(lib().lbm_moments_noalloc(ctx, rho, ux, uy, totals), "lbm_moments_noalloc")
 
 
 def lbm_status(ctx: int):

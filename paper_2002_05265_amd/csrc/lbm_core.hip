@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <type_traits>
 
@@ -45,6 +46,39 @@ int check_hip(hipError_t e, const char* what) {
     if (e == hipSuccess) return LBM_OK;
     return set_error(LBM_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
+
+}  // namespace lbm
+
+// Reduction scratch of lbm_moments_noalloc: 5 per-block partial sums for up to
+// kNoAllocMaxBlocks blocks of the per-cell launch, then 5 totals.  One copy per device, held
+// until the process ends.  In host code `scratch` is only a symbol: its device address comes
+// from hipGetSymbolAddress (per device, at context creation) and is kept in lbm_ctx.
+constexpr int kNoAllocMaxBlocks = 65536;
+static __device__ __align__(256) double scratch[5 * kNoAllocMaxBlocks + 8];
+
+namespace lbm {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be the current device.
+int scratch_address(int device, double** out) {
+    if (device < 0 || device >= kMaxDevices)
+        return set_error(LBM_EUNSUPPORTED, "device %d: at most %d devices", device, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void* p = nullptr;
+        const int rc = check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (rc != LBM_OK) return rc;
+        g_scratch_addr[device] = static_cast<double*>(p);
+    }
+    *out = g_scratch_addr[device];
+    return LBM_OK;
+}
+
+}  // namespace
 
 Launch launch_for(int nx, int ny) {
     int bw = 256;
@@ -301,6 +335,16 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
     for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
         for (int k = 0; k < 5; ++k) v[k] += partials[5 * (size_t)b + k];
     block_sum<5>(v, out);
+}
+
+// The six totals of lbm_moments from the five reduced sums, written to device memory
+// (the mean of |u|^2 divided by the node count, and the step), one thread.
+__global__ void k_totals_out(const double* __restrict__ t, double nodes, double step, double* __restrict__ out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        for (int k = 0; k < 4; ++k) out[k] = t[k];
+        out[4] = t[4] / nodes;
+        out[5] = step;
+    }
 }
 
 // Unshifted FP64 pre-collision populations, [q][y][x] dense.
@@ -585,12 +629,12 @@ void launch_step_p(lbm_ctx* ctx, int model, const double* w, const StepShape& sh
 }
 
 template <int PREC>
-void launch_moments_p(lbm_ctx* ctx, double* rho, double* ux, double* uy) {
+void launch_moments_p(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* partials) {
     using S = typename Store<PREC>::S;
     const Launch l = launch_for(ctx->nx, ctx->ny);
     hipLaunchKernelGGL((k_moments<PREC>), l.grid, l.block, 0, ctx->stream,
                        reinterpret_cast<const S*>(ctx->copy(ctx->cur)), ctx->geom(), ctx->ref, rho,
-                       ux, uy, ctx->d_part, (int)ctx->step, ctx->d_flag);
+                       ux, uy, partials, (int)ctx->step, ctx->d_flag);
 }
 
 template <int PREC>
@@ -730,6 +774,7 @@ int lbm_init_shifted(lbm_ctx** out, int nx, int ny, int prec, int eq_order, doub
             ctx->fuse_strip[k] = wide ? w.strip : fstrip;
         }
     int rc = check_hip(hipGetDevice(&ctx->device), "hipGetDevice");
+    if (rc == LBM_OK) rc = scratch_address(ctx->device, &ctx->d_static);
     if (rc == LBM_OK) rc = check_hip(hipMalloc(&ctx->d_flag, sizeof(int)), "hipMalloc(flag)");
     if (rc == LBM_OK)
         rc = check_hip(hipMalloc(&ctx->d_part, sizeof(double) * 5 * (size_t)ctx->nblocks), "hipMalloc(partials)");
@@ -836,7 +881,7 @@ int lbm_step2_raw_many(lbm_ctx* ctx, int model, const double* omega, const void*
 
 int lbm_moments(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* totals) {
     if (!ctx) return set_error(LBM_ESTATE, "context is NULL");
-    LBM_DISPATCH_PREC(ctx->prec, launch_moments_p, ctx, rho, ux, uy);
+    LBM_DISPATCH_PREC(ctx->prec, launch_moments_p, ctx, rho, ux, uy, ctx->d_part);
     int rc = check_hip(hipGetLastError(), "moments kernel launch");
     if (rc != LBM_OK || !totals) return rc;
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, ctx->stream, ctx->d_part, ctx->nblocks,
@@ -852,6 +897,25 @@ int lbm_moments(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* total
     totals[4] = t[4] / ((double)ctx->nx * (double)ctx->ny);
     totals[5] = (double)ctx->step;
     return LBM_OK;
+}
+
+int lbm_moments_noalloc(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* totals) {
+    if (!ctx) return set_error(LBM_ESTATE, "context is NULL");
+    if (!ctx->d_static) return set_error(LBM_ESTATE, "context has no static scratch address");
+    if (ctx->nblocks > kNoAllocMaxBlocks)
+        return set_error(LBM_EINVAL, "grid %d x %d needs %d reduction blocks; lbm_moments_noalloc holds %d",
+                         ctx->nx, ctx->ny, ctx->nblocks, kNoAllocMaxBlocks);
+    double* part = ctx->d_static;
+    double* tot = ctx->d_static + 5 * (size_t)kNoAllocMaxBlocks;
+    LBM_DISPATCH_PREC(ctx->prec, launch_moments_p, ctx, rho, ux, uy, part);
+    int rc = check_hip(hipGetLastError(), "moments kernel launch");
+    if (rc != LBM_OK || !totals) return rc;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, ctx->stream, part, ctx->nblocks, tot);
+    rc = check_hip(hipGetLastError(), "finalize kernel launch");
+    if (rc != LBM_OK) return rc;
+    hipLaunchKernelGGL(k_totals_out, dim3(1), dim3(64), 0, ctx->stream, tot,
+                       (double)ctx->nx * (double)ctx->ny, (double)ctx->step, totals);
+    return check_hip(hipGetLastError(), "totals kernel launch");
 }
 
 int lbm_status(lbm_ctx* ctx, long long* step, long long* blowup_step) {

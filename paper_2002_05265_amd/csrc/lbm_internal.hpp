@@ -316,6 +316,7 @@ struct lbm_ctx {
     int* d_flag = nullptr;        // first bad step (INT_MAX = none)
     double* d_part = nullptr;     // per-block partial sums, 5 per block (reduction scratch)
     double* d_tot = nullptr;      // 5 totals
+    double* d_static = nullptr;   // this device's address of the library's static reduction scratch
     double* d_wslots = nullptr;   // adjoint: per-block pending rate-gradient sums, 5 per block
     bool wslots_live = false;     // d_wslots holds pending sums
 

@@ -66,4 +66,7 @@ def test_null_context_errors(B):
     assert e.value.code == -4
     with pytest.raises(B.LbmError):
         B.lbm_status(0)
+    with pytest.raises(B.LbmError) as e:
+        B.lbm_moments_noalloc(0, None, None, None, None)
+    assert e.value.code == -4
     B.lbm_destroy(0)  # NULL is accepted
