@@ -6,10 +6,16 @@ log10 nu ~ U[-7, -2], SRT and REG in turn, one random Fourier-mode perturbation 
 Stored per instance: its parameters; the first step whose state has a node with !(rho > 0)
 (-1 if none up to step 20000); for runs that stay positive, the FP64 totals of the final state
 and the final populations at 256 seeded nodes.  Also NPERT runs in which every population is
-perturbed by one ulp after every step (random signs, a new draw per step and run), a model of
-the rounding differences between two implementations of the same arithmetic: their blow-up steps
+perturbed by ULPS ulps (relative 64 x 2^-52) after every step, random signs drawn anew per step
+and run: a model of the rounding differences between two FP64 implementations of the same
+collision, whose ~200 roundings per node in a different order and with or without fused
+multiply-adds differ by up to tens of ulps per population and step.  Stored: their blow-up steps
 (how far rounding alone moves the blow-up of this run) and, where all stay positive, the largest
-relative change of the final state (the trajectory's sensitivity to rounding).
+relative change of the final state and the largest change of each total (the trajectory's
+sensitivity to rounding).
+
+For a run that blows up in any of these, also its state half-way to the earliest blow-up, where
+the trajectories still agree, and the perturbed runs' largest relative change there.
 
 Each initial field is one Fourier mode (kx, ky), so it is constant along the lines of constant
 phase kx i / nx + ky j / ny, and any arithmetic that treats every node alike keeps it so (the
@@ -36,6 +42,7 @@ import oracle  # noqa: E402
 from paper_2002_05265_amd import inputs  # noqa: E402
 
 STEPS, CHUNK, NSAMPLE, NPERT = 20000, 100, 256, 3
+ULPS = 64  # perturbation per population and step, in units of 2^-52 (relative)
 OUT = pathlib.Path(__file__).with_name("c4_subset.npz")
 
 
@@ -60,7 +67,7 @@ def run_to_blowup(f, code, omega, steps):
 
 
 def run_perturbed(f0, code, omega, line, seed, steps):
-    """(final state, blow-up step) with a one-ulp perturbation of every population after every
+    """(final state, blow-up step) with a perturbation of ULPS ulps of every population after every
     step, signs per population and phase line."""
     rng = np.random.default_rng(seed)
     f = f0
@@ -68,7 +75,7 @@ def run_perturbed(f0, code, omega, line, seed, steps):
         if bad(f):
             return f, n
         signs = rng.choice([-1.0, 1.0], size=(9, line.max() + 1))
-        f = oracle.step(f, code, 4, omega, 1) * (1.0 + signs[:, line] * 2.0 ** -52)
+        f = oracle.step(f, code, 4, omega, 1) * (1.0 + signs[:, line] * (ULPS * 2.0 ** -52))
     return f, (steps if bad(f) else -1)
 
 
@@ -87,13 +94,26 @@ def run(d):
     pert = [run_perturbed(f0, code, d["omega"], line.reshape(d["ny"], d["nx"]),
                           s, STEPS) for s in range(NPERT)]
     out = {"blowup": blow, "perturbed_blowup": [b for _, b in pert]}
+    finite = [b for b in (blow, *out["perturbed_blowup"]) if b >= 0]
+    idx = np.random.default_rng(100 + d["index"]).choice(d["nx"] * d["ny"], NSAMPLE, replace=False)
+    out["nodes"] = idx
+    if finite:
+        # an unstable run: its state half-way to the earliest blow-up of any run, where the
+        # trajectories still agree, and their spread there
+        mid = min(finite) // 2
+        fm = oracle.step(f0, code, 4, d["omega"], mid)
+        gm = [run_perturbed(f0, code, d["omega"], line.reshape(d["ny"], d["nx"]), s, mid)[0] for s in range(NPERT)]
+        out["mid_step"] = mid
+        out["mid_f"] = fm.reshape(9, -1)[:, idx]
+        out["mid_sensitivity"] = max(float(np.max(np.abs(g - fm)) / np.max(np.abs(fm))) for g in gm)
     if blow < 0:
         stable = all(b < 0 for _, b in pert)
         out["sensitivity"] = (max(float(np.max(np.abs(g - f)) / np.max(np.abs(f))) for g, _ in pert)
                               if stable else np.inf)
         out["totals"] = oracle.moments(f)[3]
-        idx = np.random.default_rng(100 + d["index"]).choice(d["nx"] * d["ny"], NSAMPLE, replace=False)
-        out["nodes"] = idx
+        tp = [oracle.moments(g)[3] for g, _ in pert]
+        out["totals_spread"] = (np.max([np.abs(t - out["totals"]) for t in tp], axis=0)
+                                if stable else np.full(5, np.inf))
         out["f"] = f.reshape(9, -1)[:, idx]
     print(f"{d['index']:2d} {d['model']:3s} {d['preset']} Ma {d['mach']:.3f} nu {d['nu']:.2e}: "
           f"blow-up {blow}, perturbed {out['perturbed_blowup']}, "
@@ -106,13 +126,14 @@ if __name__ == "__main__":
     insts = inputs.stratified_sweep_instances()
     with mp.Pool(8) as pool:
         res = pool.map(run, insts)
-    data = {"steps": np.array(STEPS),
+    data = {"steps": np.array(STEPS), "ulps": np.array(ULPS),
             "mach": np.array([d["mach"] for d in insts]), "nu": np.array([d["nu"] for d in insts]),
             "blowup": np.array([r["blowup"] for r in res]),
             "perturbed_blowup": np.array([r["perturbed_blowup"] for r in res])}
     for k, r in enumerate(res):
-        if r["blowup"] < 0:
-            for key in ("sensitivity", "totals", "nodes", "f"):
+        data[f"{k}_nodes"] = np.asarray(r["nodes"])
+        for key in ("sensitivity", "totals", "totals_spread", "f", "mid_step", "mid_f", "mid_sensitivity"):
+            if key in r:
                 data[f"{k}_{key}"] = np.asarray(r[key])
     np.savez_compressed(OUT, **data)
     print("wrote", OUT)

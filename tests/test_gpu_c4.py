@@ -3,13 +3,18 @@ the benchmark times (FP64, autotuned pass shape, live instances re-dealt over th
 steps):
 
 - a stratified subset (two instances per model, 64 x 64, SRT and REG) against the oracle's runs
-  stored in tests/golden/c4_subset.npz.  Rounding alone moves the blow-up step of these runs:
-  the oracle's own runs with a one-ulp perturbation of every population at every step (a model
-  of the rounding differences between two implementations) blow up up to ~200 steps from the
-  unperturbed one.  So the GPU's blow-up step must lie within the spread of those oracle runs
-  widened by twice that spread on each side (blowup_window), one step at least; where every
-  oracle run stays positive, the final populations at 256 nodes and the FP64 totals must agree
-  within max(1e-12, 64 x the largest relative change the perturbed runs show);
+  stored in tests/golden/c4_subset.npz, with bounds set by what rounding alone can change.  The
+  oracle's own runs with a perturbation of 64 ulps of every population at every step (more than
+  the rounding differences of two FP64 implementations of the collision) move blow-up steps by up
+  to a few hundred steps, and a less noisy arithmetic seeds a rounding-seeded instability less,
+  possibly beyond the horizon.  So:
+  * blow-up: no earlier than the earliest of those runs minus twice their spread (blowup_window),
+    and the state half-way to the earliest blow-up within max(4 x the perturbed runs' relative
+    change there, steps x 2^-52);
+  * runs that stay positive in every oracle run: the final populations at 256 nodes within
+    max(4 x the perturbed runs' relative change, 20000 x 2^-52), the floor being the coherent
+    drift of a near-uniform state, where every node rounds alike each step; each FP64 total within
+    max(4 x its change in the perturbed runs, the same coherent drift of the sum);
 - the same subset, and the benchmark's whole 512-instance sweep, against each instance's run
   through the plain kernel: the same blow-up steps and bit-identical final states."""
 import math
@@ -49,43 +54,69 @@ def subset(gpu):
     b.close()
 
 
+U = 2.0 ** -52  # unit roundoff of FP64 relative to a value's own magnitude (one ulp)
+
+
 def blowup_window(b, perturbed):
-    """(lo, hi) of admissible blow-up steps given the oracle's blow-up step b and those of its
-    perturbed runs (-1: positive to the end, read as never); None when all stay positive."""
-    vals = [b, *perturbed]
-    finite = [v for v in vals if v >= 0]
+    """(lo, inf) of admissible blow-up steps given the oracle's blow-up step b and those of its
+    perturbed runs (-1: positive to the end); None when all stay positive."""
+    finite = [v for v in (b, *perturbed) if v >= 0]
     if not finite:
         return None
     spread = max(finite) - min(finite)
-    lo = min(finite) - 1 - 2 * spread
-    hi = max(finite) + 1 + 2 * spread if len(finite) == len(vals) else math.inf
-    return lo, hi
+    return min(finite) - 1 - 2 * spread, math.inf
 
 
-def test_c4_subset_against_oracle(subset):
-    golden, insts, _, b = subset
+def sampled_state(fields, d, steps, nodes, device):
+    s = Sim(*fields, prec="f64", eq_order=4, device=device)
+    s.step(d["model"], d["omega"], steps)
+    g = s.state().cpu().numpy().reshape(9, -1)[:, nodes]
+    s.close()
+    return g
+
+
+def test_c4_subset_against_oracle(subset, gpu):
+    golden, insts, fields, b = subset
     _, blow = b.status()
+    bad = []
     for k, d in enumerate(insts):
         ob = int(golden["blowup"][k])
-        win = blowup_window(ob, [int(v) for v in golden["perturbed_blowup"][k]])
-        print(f"  {k:2d} {d['model']:3s} {d['preset']} blow-up gpu {blow[k]} oracle {ob} "
-              f"perturbed {list(golden['perturbed_blowup'][k])} window {win}", flush=True)
+        pert = [int(v) for v in golden["perturbed_blowup"][k]]
+        win = blowup_window(ob, pert)
+        line = f"  {k:2d} {d['model']:3s} {d['preset']} blow-up gpu {blow[k]} oracle {ob} perturbed {pert} window {win}"
+        nodes = golden[f"{k}_nodes"]
         if win is not None:
             g = math.inf if blow[k] < 0 else blow[k]
-            assert win[0] <= g <= win[1], (k, blow[k], ob, win)
+            if not win[0] <= g <= win[1]:
+                bad.append((k, "blow-up", blow[k], ob, win))
+            # the trajectory half-way to the earliest blow-up (plain kernel: bit-identical to the batch)
+            mid = int(golden[f"{k}_mid_step"])
+            ref = golden[f"{k}_mid_f"]
+            gm = sampled_state(fields[k], d, mid, nodes, gpu)
+            bound = max(4.0 * float(golden[f"{k}_mid_sensitivity"]), mid * U)
+            err = float(np.max(np.abs(gm - ref)) / np.max(np.abs(ref)))
+            print(f"{line}; state at step {mid}: error {err:.2e} (bound {bound:.2e})", flush=True)
+            if not err < bound:
+                bad.append((k, "mid-state", mid, err, bound))
             continue
-        assert blow[k] < 0, (k, blow[k])
+        if blow[k] >= 0:
+            print(line, flush=True)
+            bad.append((k, "blow-up", blow[k], ob, win))
+            continue
         ref = golden[f"{k}_f"]
-        g = b.state(k).cpu().numpy().reshape(9, -1)[:, golden[f"{k}_nodes"]]
-        bound = max(1e-12, 64.0 * float(golden[f"{k}_sensitivity"]))
+        g = b.state(k).cpu().numpy().reshape(9, -1)[:, nodes]
+        bound = max(4.0 * float(golden[f"{k}_sensitivity"]), STEPS * U)
         err = float(np.max(np.abs(g - ref)) / np.max(np.abs(ref)))
-        print(f"     state error {err:.2e} (bound {bound:.2e})", flush=True)
-        assert err < bound, (k, err, bound)
+        print(f"{line}; state error {err:.2e} (bound {bound:.2e})", flush=True)
+        if not err < bound:
+            bad.append((k, "state", err, bound))
+    assert not bad, bad
 
 
 def test_c4_subset_totals_against_oracle(subset, gpu):
     golden, insts, fields, b = subset
     _, blow = b.status()
+    bad = []
     for k, d in enumerate(insts):
         if blow[k] >= 0 or int(golden["blowup"][k]) >= 0 or np.any(golden["perturbed_blowup"][k] >= 0):
             continue
@@ -94,10 +125,17 @@ def test_c4_subset_totals_against_oracle(subset, gpu):
         tot = np.array(s.totals()[:5])
         s.close()
         ref = golden[f"{k}_totals"]
-        bound = max(1e-12, 64.0 * float(golden[f"{k}_sensitivity"]))
-        # the totals are sums of O(1) terms per node: normwise relative to the largest total
-        err = float(np.max(np.abs(tot - ref)) / np.max(np.abs(ref)))
-        assert err < bound, (k, tot, ref)
+        # coherent drift: every node rounds alike every step, by up to one ulp of its density and
+        # momentum; the kinetic energy and mean |u|^2 follow at twice the relative rate
+        mass = ref[0]
+        coherent = STEPS * U * np.array([mass, mass, mass, 2.0 * abs(ref[3]), 2.0 * abs(ref[4])])
+        bound = np.maximum(4.0 * golden[f"{k}_totals_spread"], coherent)
+        diff = np.abs(tot - ref)
+        print(f"  {k:2d} {d['model']:3s} {d['preset']} totals diff {np.array2string(diff, precision=2)} "
+              f"bound {np.array2string(bound, precision=2)}", flush=True)
+        if not np.all(diff <= bound):
+            bad.append((k, diff.tolist(), bound.tolist()))
+    assert not bad, bad
 
 
 def test_c4_subset_bit_identical_to_plain(subset, gpu):
