@@ -256,8 +256,12 @@ __global__ __launch_bounds__(256) void k_step2(const typename Store<PREC>::S* __
 }
 
 // Three steps per launch: strips of W columns and hs rows, two LDS rings (strip_three_steps).
+// A ring of 8 rows runs 8 waves (512 threads), one row each per pass: the two halo passes then cost
+// two wave-collisions per 24 useful ones instead of per 12 with a ring of 4 rows.
+template <int RING> constexpr int step3_waves() { return RING == 8 ? 8 : 4; }
+
 template <int MODEL, int PREC, int RING, int W>
-__global__ __launch_bounds__(256) void k_step3(const typename Store<PREC>::S* __restrict__ src,
+__global__ __launch_bounds__(64 * step3_waves<RING>()) void k_step3(const typename Store<PREC>::S* __restrict__ src,
                                                typename Store<PREC>::S* __restrict__ dst, Geom g,
                                                Coef<typename Store<PREC>::R> c,
                                                Ref<typename Store<PREC>::R> ref, int N, int step,
@@ -273,8 +277,9 @@ __global__ __launch_bounds__(256) void k_step3(const typename Store<PREC>::S* __
     tile_of_block(blockIdx.x, gsx, gridDim.x, PREC == kF32 ? 1 : 0, sx, sy);
     const int x0 = (int)sx * W;
     const int ys = (int)sy * hs;
-    strip_three_steps<RING, W>(ring1, ring2, src, dst, g, ref, x0, ys, min(ys + hs, g.ny), step, blowup,
-                               [&](R(&h)[9], const Macro<R>& m) { collide<MODEL>(h, m, ref, c, N); });
+    strip_three_steps<RING, W, false, true, step3_waves<RING>()>(
+        ring1, ring2, src, dst, g, ref, x0, ys, min(ys + hs, g.ny), step, blowup,
+        [&](R(&h)[9], const Macro<R>& m) { collide<MODEL>(h, m, ref, c, N); });
 }
 
 // Three steps per launch on strips of WP columns whose halo columns fit the wave (FP64: WP = 48;
@@ -545,7 +550,7 @@ void launch_step3_w(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int hs
     using S = typename Store<PREC>::S;
     const unsigned gsx = (unsigned)((ctx->nx + W - 1) / W);
     const unsigned gsy = (unsigned)((ctx->ny + hs - 1) / hs);
-    hipLaunchKernelGGL((k_step3<MODEL, PREC, RING, W>), dim3(gsx * gsy), dim3(256), 0, ctx->stream,
+    hipLaunchKernelGGL((k_step3<MODEL, PREC, RING, W>), dim3(gsx * gsy), dim3(64 * step3_waves<RING>()), 0, ctx->stream,
                        reinterpret_cast<const S*>(ctx->copy(src_copy)), reinterpret_cast<S*>(ctx->copy(src_copy ^ 1)),
                        ctx->geom(), c, ref_as<typename Store<PREC>::R>(ctx->ref), ctx->eq_order, (int)ctx->step,
                        ctx->d_flag, gsx, hs);

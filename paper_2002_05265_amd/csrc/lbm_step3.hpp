@@ -21,17 +21,19 @@ namespace lbm {
 // two-step pass.  Every node is computed by the same arithmetic as in k_step and the rings hold the
 // values in the storage type, so the result is bit-identical to three launches of k_step.  VIA_L2
 // selects L1-bypassing loads, NT streaming stores (as in strip_two_steps).  Requires nx, ny >= 2
-// (one conditional wrap of rows and columns) and strip rows >= 1.  Called by all 256 threads of a
-// workgroup.
-template <int RING, int W, bool VIA_L2 = false, bool NT = true, typename S, typename R, typename Coll>
+// (one conditional wrap of rows and columns) and strip rows >= 1.  Called by all 64 NW threads of a
+// workgroup (NW waves: 4, or 8 with one row per wave and pass for a ring of 8 rows); the last wave
+// also collides the first step's halo columns, the one before it the second step's.
+template <int RING, int W, bool VIA_L2 = false, bool NT = true, int NW = 4, typename S, typename R, typename Coll>
 __device__ __forceinline__ void strip_three_steps(S (&ring1)[9][RING + 2][W + 4], S (&ring2)[9][RING + 2][W + 2],
                                                   const S* __restrict__ src, S* __restrict__ dst, const Geom& g,
                                                   const Ref<R>& ref, int x0, int ys, int ye, int step,
                                                   int* __restrict__ blowup, Coll&& coll) {
     constexpr int NR = RING + 2;
     constexpr int WPR = W / 64;     // waves per row of the strip
-    constexpr int RPW = 4 / WPR;    // rows the block covers at once
+    constexpr int RPW = NW / WPR;   // rows the block covers at once
     constexpr int KR = RING / RPW;  // rows per wave and pass
+    constexpr int H1 = NW - 1, H2 = NW - 2;  // the waves that take the first / second step's halo
     static_assert(RING % RPW == 0 && 4 * RING <= 64, "ring rows: a multiple of the block's rows, at most 16");
     const int lane = (int)(threadIdx.x & 63u);
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -120,7 +122,7 @@ __device__ __forceinline__ void strip_three_steps(S (&ring1)[9][RING + 2][W + 4]
             const int a = yb + 2 + rl + RPW * k;
             if (a <= top && in1) load_own(a, hn[k]);
         }
-        if (wave == 3) {
+        if (wave == H1) {
             const int a = yb + 2 + (lane >> 2);
             if (a <= top && lane < 4 * RING) load_any(a, halo1_col(lane & 3), hh);
         }
@@ -128,25 +130,25 @@ __device__ __forceinline__ void strip_three_steps(S (&ring1)[9][RING + 2][W + 4]
 
     // prologue, first step: rows ys - 2 .. ys + 1 (ring1 slots 0..3) with their halo columns
     {
-        constexpr int KP = 4 / RPW;
+        constexpr int KP = (4 + RPW - 1) / RPW;
         R hp[KP][9];
         R hq[9];
 #pragma unroll
         for (int k = 0; k < KP; ++k)
-            if (in1) load_own(ys - 2 + rl + RPW * k, hp[k]);
-        if (wave == 3 && lane < 16) load_any(ys - 2 + (lane >> 2), halo1_col(lane & 3), hq);
+            if (in1 && rl + RPW * k < 4) load_own(ys - 2 + rl + RPW * k, hp[k]);
+        if (wave == H1 && lane < 16) load_any(ys - 2 + (lane >> 2), halo1_col(lane & 3), hq);
         prefetch(ys);
 #pragma unroll
         for (int k = 0; k < KP; ++k)
-            if (in1) finish1(rl + RPW * k, lc1, hp[k]);
-        if (wave == 3 && lane < 16) finish1(lane >> 2, halo1_col(lane & 3), hq);
+            if (in1 && rl + RPW * k < 4) finish1(rl + RPW * k, lc1, hp[k]);
+        if (wave == H1 && lane < 16) finish1(lane >> 2, halo1_col(lane & 3), hq);
     }
     __syncthreads();
     // prologue, second step: rows ys - 1 and ys (ring2 slots 0, 1; ring1 slots 1, 2) with their
-    // halo columns (wave 2, lanes 0..3)
+    // halo columns (wave H2, lanes 0..3)
     {
         if (rl < 2 && in1) second(1 + rl, lc2, rl);
-        if (wave == 2 && lane < 4) second(1 + (lane >> 1), (lane & 1) ? w + 1 : 0, lane >> 1);
+        if (wave == H2 && lane < 4) second(1 + (lane >> 1), (lane & 1) ? w + 1 : 0, lane >> 1);
     }
     __syncthreads();
 
@@ -160,7 +162,7 @@ __device__ __forceinline__ void strip_three_steps(S (&ring1)[9][RING + 2][W + 4]
             const int a = yb + 2 + rl + RPW * k;
             if (a <= top1 && in1) finish1(wrap(sb1 + 2 + rl + RPW * k), lc1, hn[k]);
         }
-        if (wave == 3) {
+        if (wave == H1) {
             const int a = yb + 2 + (lane >> 2);
             if (a <= top1 && lane < 4 * RING) finish1(wrap(sb1 + 2 + (lane >> 2)), halo1_col(lane & 3), hh);
         }
@@ -171,7 +173,7 @@ __device__ __forceinline__ void strip_three_steps(S (&ring1)[9][RING + 2][W + 4]
             const int off = 1 + rl + RPW * k;  // row yb + off
             if (yb + off <= top2 && in1) second(sb1 + off, lc2, wrap(sb2 + off));
         }
-        if (wave == 2) {
+        if (wave == H2) {
             const int off = 1 + (lane >> 1);
             if (yb + off <= top2 && lane < 2 * RING) second(sb1 + off, (lane & 1) ? w + 1 : 0, wrap(sb2 + off));
         }
