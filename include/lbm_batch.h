@@ -6,8 +6,13 @@
  * numerical stability study (Section 5b-c: one simulation per (model, Ma, nu) point, with a
  * blow-up test).  Instances share nothing; their nodes are cut into tiles of 256 consecutive
  * nodes, and one persistent grid of co-resident workgroups sweeps all tiles of all instances
- * every step, with a grid-wide barrier between steps.  The grid is launched cooperatively, so
- * the runtime guarantees that all its workgroups are resident together (or refuses the launch).
+ * every step, with a barrier between steps.  The grid is launched cooperatively and sized from the
+ * persistent kernel's own resources (VGPRs, LDS, threads against what one CU holds; see
+ * lbm_batch_residency), so that all its workgroups are resident together.  As a safety net, the
+ * first run of each launch shape probes that size with non-advancing steps under a short barrier
+ * bound and lowers it if the grid did not pass every barrier; every barrier wait of the kernel is
+ * bounded in wall-clock time, so a grid that is not resident can fail a run with an error but not
+ * hang it.
  *
  * Per-instance arithmetic is exactly that of lbm_step (same device code, same rounding): an
  * instance of the batch is bit-identical to the same run through lbm_init / lbm_step.
@@ -134,6 +139,14 @@ int lbm_batch_set_fusion_depth(lbm_batch* b, int steps);
 
 /* Steps per fused pass (host pointer, may be NULL). */
 int lbm_batch_get_fusion_depth(lbm_batch* b, int* steps);
+
+/* Residency of launch shape `shape` (0, 1, 2: one step per pass with 1, 2, 4 nodes per thread;
+ * 3: two steps per pass; 4: three steps per pass): the workgroups per CU that the persistent
+ * kernel's resources allow, the runtime's occupancy figure, the figure confirmed by the first run
+ * of that shape (0 before it), and how many residency probes of this batch had to lower a figure.
+ * Host pointers, each may be NULL.  Does not synchronise. */
+int lbm_batch_residency(lbm_batch* b, int shape, int* from_resources, int* occupancy_query, int* resident,
+                        int* probe_stepdowns);
 
 /* Autotune the persistent launch: each candidate (nodes per thread in {1, 2, 4}, or two or, for
  * FP64 and FP32, three steps per pass at the current strip height (64 rows unless set), x groups

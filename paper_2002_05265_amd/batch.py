@@ -102,6 +102,11 @@ class Batch:
         whether two or three steps per pass are used (see fusion(), fusion_depth())."""
         return B.lbm_batch_autotune(self.handle, trials)
 
+    def residency(self, shape: int):
+        """(groups per CU from the kernel's resources, runtime occupancy figure, confirmed figure,
+        probes that had to lower a figure) of launch shape 0-4 (lbm_batch_residency)."""
+        return B.lbm_batch_residency(self.handle, shape)
+
     def close(self):
         if getattr(self, "handle", None):
             B.lbm_batch_destroy(self.handle)

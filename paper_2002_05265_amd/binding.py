@@ -30,7 +30,7 @@ EXPORTS = (
     "lbm_batch_get_state", "lbm_batch_mean_u2", "lbm_batch_set_active", "lbm_batch_rebalance",
     "lbm_batch_set_launch", "lbm_batch_set_fusion", "lbm_batch_get_fusion",
     "lbm_batch_set_fusion_depth", "lbm_batch_get_fusion_depth",
-    "lbm_batch_autotune", "lbm_batch_destroy",
+    "lbm_batch_autotune", "lbm_batch_residency", "lbm_batch_destroy",
     "lbm_state_bytes", "lbm_adjoint_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_raw",
     "lbm_step_raw_many", "lbm_step2_raw_many", "lbm_adjoint_many", "lbm_adjoint_flush",
     "lbm_adjoint_seed_velocity_l2", "lbm_adjoint_step", "lbm_eq_vjp",
@@ -102,6 +102,7 @@ def _declare(L: ctypes.CDLL):
         "lbm_batch_get_fusion_depth": (_i, [_vp, ctypes.POINTER(_i)]),
         "lbm_batch_autotune": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), _dp]),
         "lbm_batch_destroy": (None, [_vp]),
+        "lbm_batch_residency": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
         "lbm_state_bytes": (_sz, [_vp]),
         "lbm_adjoint_bytes": (_sz, [_vp]),
         "lbm_save_state": (_i, [_vp, _vp]),
@@ -320,6 +321,14 @@ def lbm_batch_autotune(b: int, trials: int):
     _check(lib().lbm_batch_autotune(b, trials, ctypes.byref(npt), ctypes.byref(gpc), ctypes.byref(us)),
            "lbm_batch_autotune")
     return npt.value, gpc.value, us.value
+
+
+def lbm_batch_residency(b: int, shape: int):
+    """(groups per CU from the kernel's resources, runtime occupancy figure, confirmed figure,
+    residency probes that had to lower a figure)."""
+    vals = [_i() for _ in range(4)]
+    _check(lib().lbm_batch_residency(b, shape, *(ctypes.byref(v) for v in vals)), "lbm_batch_residency")
+    return tuple(v.value for v in vals)
 
 
 def lbm_batch_destroy(b: int):

@@ -89,6 +89,19 @@ __device__ __forceinline__ unsigned xcc_id() {
     return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kMaxXcc - 1);
 }
 
+// SGPRs per wave that each persistent kernel is compiled to at most (amdgpu_num_sgpr), and the
+// waves per SIMD that leaves.  Measured on MI355X: kernels of 24, 82, 92 and 106 SGPRs held 8, 7, 7
+// and 6 waves per SIMD, one fewer than the usual rule of 800 SGPRs in granules of 16 that the
+// compiler's and the runtime's occupancy figures apply (both report 8, 8, 8, 7): a wave occupies
+// roundup(S, 16) + 16 of the SIMD's 800.  The one-step FP32 / FP16 kernel is held to 80 SGPRs (it
+// would take 82, and so 7 waves per SIMD); the others are limited by VGPRs or LDS well below their
+// SGPR figure.
+template <int PREC> constexpr int batch1_sgprs() { return PREC == kF64 ? 112 : 80; }  // k_batch64 / k_batch
+constexpr int kBatchFusedSgprs = 112;                                                  // k_batch2, k_batch3
+constexpr int sgpr_waves(int sgprs) {
+    return std::min(8, 800 / ((sgprs + 15) / 16 * 16 + 16));
+}
+
 // Spin (thread 0 of a workgroup) until *ctr >= target, or until err is set or the wall-clock
 // bound passes (then err = 1).  Returns false if the launch must stop.
 __device__ __forceinline__ bool wait_count(const unsigned* ctr, unsigned target, int* err, long long timeout_ticks) {
@@ -119,14 +132,22 @@ __device__ __forceinline__ bool xcd_barrier(unsigned* ctr, int step, unsigned co
 }
 
 // Registration of a workgroup of the persistent grid: its rank among the workgroups on its XCD
-// and their count, once every workgroup of the grid has registered.  False if the launch must
-// stop (a bound passed, or an XCD that owns work got no workgroup: err = 2).
+// and their count, once every workgroup of the grid has registered, and the step counter at the
+// launch start.  The counter is read before this workgroup registers: block 0 advances it when it
+// has finished all its passes, and since its barriers wait only for its own XCD, a workgroup that
+// read the counter after registering could read the advanced value (and take the wrong copy and
+// steps).  False if the launch must stop (a bound passed, or an XCD that owns work got no
+// workgroup: err = 2).
 __device__ __forceinline__ bool register_group(unsigned* __restrict__ bar, const int* __restrict__ xtab,
                                                int* __restrict__ err, long long timeout_ticks, unsigned xcc,
-                                               unsigned& rank, unsigned& count) {
+                                               const long long* __restrict__ step_ctr, unsigned& rank,
+                                               unsigned& count, long long& n0) {
     __shared__ unsigned s_rank, s_count;
     __shared__ int s_go;
+    __shared__ long long s_n0;
     if (threadIdx.x == 0) {
+        s_n0 = __hip_atomic_load(step_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // (the s_waitcnt below completes this load before the grid count is incremented)
         s_rank = __hip_atomic_fetch_add(bar + kLine * (1 + xcc), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // the XCD count must be complete before the grid count is: wait until this add has been
         // performed (it returns) before issuing the next one, so that whoever sees the grid count
@@ -147,11 +168,12 @@ __device__ __forceinline__ bool register_group(unsigned* __restrict__ bar, const
     __syncthreads();
     rank = s_rank;
     count = s_count;
+    n0 = s_n0;
     return s_go != 0;
 }
 
 template <int PREC, int NPT>
-__global__ __launch_bounds__(kTileThreads) void k_batch(
+__device__ __forceinline__ void batch_steps(
     typename Store<PREC>::S* __restrict__ base, long long copy_elems,
     const BDesc<typename Store<PREC>::R>* __restrict__ desc, const int2* __restrict__ run,
     const int* __restrict__ xtab, int* __restrict__ blowup, const int* __restrict__ active,
@@ -162,10 +184,10 @@ __global__ __launch_bounds__(kTileThreads) void k_batch(
     const int tid = threadIdx.x;
     const unsigned xcc = xcc_id();
     unsigned rank, count;
-    if (!register_group(bar, xtab, err, timeout_ticks, xcc, rank, count)) return;
+    long long n0;
+    if (!register_group(bar, xtab, err, timeout_ticks, xcc, step_ctr, rank, count, n0)) return;
     const int first_tile = xtab[2 * xcc], ntiles = xtab[2 * xcc + 1];
     unsigned* xbar = bar + kLine * (1 + kMaxXcc + xcc);
-    const long long n0 = *step_ctr;
     for (int s = 0; s < nsteps; ++s) {
         const long long n = n0 + (advance ? s : 0);
         const int sc = (int)(n & 1);
@@ -201,6 +223,36 @@ __global__ __launch_bounds__(kTileThreads) void k_batch(
     if (advance && blockIdx.x == 0 && tid == 0) *step_ctr = n0 + nsteps;
 }
 
+// The one-step persistent kernel: FP32 / FP16 held to 80 SGPRs (8 waves per SIMD), FP64 to 112.
+template <int PREC, int NPT>
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_num_sgpr(80))) void k_batch(
+    typename Store<PREC>::S* __restrict__ base, long long copy_elems,
+    const BDesc<typename Store<PREC>::R>* __restrict__ desc, const int2* __restrict__ run,
+    const int* __restrict__ xtab, int* __restrict__ blowup, const int* __restrict__ active,
+    int* __restrict__ lastcopy, unsigned* __restrict__ bar, int* __restrict__ err,
+    long long* __restrict__ step_ctr, int nsteps, int advance, long long timeout_ticks) {
+    batch_steps<PREC, NPT>(base, copy_elems, desc, run, xtab, blowup, active, lastcopy, bar, err, step_ctr, nsteps, advance, timeout_ticks);
+}
+
+template <int NPT, int PREC = kF64>
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_num_sgpr(112))) void k_batch64(
+    typename Store<PREC>::S* __restrict__ base, long long copy_elems,
+    const BDesc<typename Store<PREC>::R>* __restrict__ desc, const int2* __restrict__ run,
+    const int* __restrict__ xtab, int* __restrict__ blowup, const int* __restrict__ active,
+    int* __restrict__ lastcopy, unsigned* __restrict__ bar, int* __restrict__ err,
+    long long* __restrict__ step_ctr, int nsteps, int advance, long long timeout_ticks) {
+    batch_steps<PREC, NPT>(base, copy_elems, desc, run, xtab, blowup, active, lastcopy, bar, err, step_ctr, nsteps, advance, timeout_ticks);
+}
+
+// The one-step kernel of a precision.
+template <int PREC, int NPT>
+const void* batch1_fn() {
+    if constexpr (PREC == kF64)
+        return reinterpret_cast<const void*>(&k_batch64<NPT>);
+    else
+        return reinterpret_cast<const void*>(&k_batch<PREC, NPT>);
+}
+
 // Two steps per pass: the same persistent grid and XCD-local barriers as k_batch, one barrier
 // per pair of steps, over strips of kStripW columns and `hs` rows of the instances (the strip
 // body of the plain two-step kernel, with loads that bypass L1 and plain stores).  Pair p of a
@@ -209,7 +261,7 @@ __global__ __launch_bounds__(kTileThreads) void k_batch(
 // parity.  Whether a strip is skipped (its instance blew up before the pair, or was retired)
 // is decided once per workgroup: the strip body contains block barriers.
 template <int PREC, int RING>
-__global__ __launch_bounds__(kTileThreads) void k_batch2(
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_num_sgpr(112))) void k_batch2(
     typename Store<PREC>::S* __restrict__ base, long long copy_elems,
     const BDesc<typename Store<PREC>::R>* __restrict__ desc, const int2* __restrict__ run,
     const int* __restrict__ xtab, int* __restrict__ blowup, const int* __restrict__ active,
@@ -222,10 +274,10 @@ __global__ __launch_bounds__(kTileThreads) void k_batch2(
     const int tid = threadIdx.x;
     const unsigned xcc = xcc_id();
     unsigned rank, count;
-    if (!register_group(bar, xtab, err, timeout_ticks, xcc, rank, count)) return;
+    long long n0;
+    if (!register_group(bar, xtab, err, timeout_ticks, xcc, step_ctr, rank, count, n0)) return;
     const int first_strip = xtab[2 * xcc], nstrips = xtab[2 * xcc + 1];
     unsigned* xbar = bar + kLine * (1 + kMaxXcc + xcc);
-    const long long n0 = *step_ctr;
     for (int p = 0; p < npairs; ++p) {
         const long long n = n0 + (advance ? 2 * p : 0);
         const int sc = (int)(n0 & 1) ^ (advance ? (p & 1) : 0);
@@ -268,7 +320,7 @@ constexpr int kBatchNarrowW = 48;
 // first step's parity (the copy of the launch start, flipped p times) and any number of triples
 // keeps every live state in the copy of its step's parity.
 template <int PREC, int RING>
-__global__ __launch_bounds__(kTileThreads) void k_batch3(
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_num_sgpr(112))) void k_batch3(
     typename Store<PREC>::S* __restrict__ base, long long copy_elems,
     const BDesc<typename Store<PREC>::R>* __restrict__ desc, const int2* __restrict__ run,
     const int* __restrict__ xtab, int* __restrict__ blowup, const int* __restrict__ active,
@@ -284,10 +336,10 @@ __global__ __launch_bounds__(kTileThreads) void k_batch3(
     const int tid = threadIdx.x;
     const unsigned xcc = xcc_id();
     unsigned rank, count;
-    if (!register_group(bar, xtab, err, timeout_ticks, xcc, rank, count)) return;
+    long long n0;
+    if (!register_group(bar, xtab, err, timeout_ticks, xcc, step_ctr, rank, count, n0)) return;
     const int first_strip = xtab[2 * xcc], nstrips = xtab[2 * xcc + 1];
     unsigned* xbar = bar + kLine * (1 + kMaxXcc + xcc);
-    const long long n0 = *step_ctr;
     for (int p = 0; p < ntriples; ++p) {
         const long long n = n0 + (advance ? 3 * p : 0);
         const int sc = (int)(n0 & 1) ^ (advance ? (p & 1) : 0);
@@ -446,6 +498,7 @@ struct lbm_batch {
     // steps per pass over strips; 4 = three steps per pass over the same strips (shape 3's run
     // table)
     int cus = 0, occ[5] = {0, 0, 0, 0, 0};     // CUs, occupancy limit per shape (runtime query)
+    int res_fit[5] = {0, 0, 0, 0, 0};          // groups per CU the kernel's own resources allow
     int resident[5] = {0, 0, 0, 0, 0};         // groups per CU confirmed co-resident (0 = not probed)
     int npt = 1, gpc = 0;              // launch shape (gpc 0 = occupancy limit)
     // fused passes over strips of hs rows (64: on the 512-instance FP64 sweep with three steps per
@@ -472,6 +525,7 @@ struct lbm_batch {
     long long* d_step = nullptr;
     long long timeout_ticks = 0;
     long long probe_ticks = 0;
+    int probe_stepdowns = 0;           // residency probes that had to lower a shape's groups per CU
 };
 
 namespace {
@@ -481,9 +535,9 @@ int npt_index(int npt) { return npt == 4 ? 2 : (npt == 2 ? 1 : 0); }
 template <int PREC>
 const void* batch_kernel(int npt) {
     switch (npt) {
-        case 4: return reinterpret_cast<const void*>(&k_batch<PREC, 4>);
-        case 2: return reinterpret_cast<const void*>(&k_batch<PREC, 2>);
-        default: return reinterpret_cast<const void*>(&k_batch<PREC, 1>);
+        case 4: return batch1_fn<PREC, 4>();
+        case 2: return batch1_fn<PREC, 2>();
+        default: return batch1_fn<PREC, 1>();
     }
 }
 
@@ -495,9 +549,10 @@ const void* batch_kernel_p(int prec, int npt) {
     }
 }
 
-// The persistent kernel is launched cooperatively: the runtime then either makes all G
-// workgroups resident at once or refuses the launch (hipErrorCooperativeLaunchTooLarge), so the
-// grid barrier never waits on a workgroup that cannot start.
+// The persistent kernel is launched cooperatively, at a grid size from its resources
+// (resources_fit) that all CUs hold at once.  The runtime's own check of a cooperative launch uses
+// its occupancy figure, which can be larger than what is resident (see sgpr_waves), so it does not
+// replace that sizing; the bounded barrier waits are the safety net.
 template <int PREC, int NPT>
 hipError_t launch_batch_t(lbm_batch* b, hipStream_t s, int G, int nsteps, int advance) {
     using S = typename Store<PREC>::S;
@@ -517,7 +572,7 @@ hipError_t launch_batch_t(lbm_batch* b, hipStream_t s, int G, int nsteps, int ad
     long long timeout = b->timeout_ticks;
     void* args[] = {&base, &copy_elems, &desc, &tiles, &xtab, &blowup, &active, &lastcopy, &bar, &err, &step,
                     &nsteps, &advance, &timeout};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_batch<PREC, NPT>), dim3(G),
+    return hipLaunchCooperativeKernel(batch1_fn<PREC, NPT>(), dim3(G),
                                       dim3(kTileThreads), args, 0, s);
 }
 
@@ -654,7 +709,39 @@ int deal_tables(lbm_batch* b, const std::vector<char>& live) {
 
 int shape_of(const lbm_batch* b, bool fused) { return fused ? (b->depth == 3 ? 4 : 3) : npt_index(b->npt); }
 
-int groups_limit(lbm_batch* b, int k) { return b->resident[k] > 0 ? b->resident[k] : b->occ[k]; }
+// Workgroups of `threads` threads that one CU holds at once for kernel fn, from the kernel's own
+// resources and the CU's: every SIMD (four per CU) has 512 VGPRs per lane, allocated in granules of
+// 8, at most 8 waves, and room for the waves that sgpr_waves gives for the kernel's SGPR bound; a
+// workgroup's waves are spread over the SIMDs; the CU's LDS and thread slots are shared by its
+// workgroups.
+int resources_fit(const void* fn, int threads, int sgprs, int* out) {
+    hipFuncAttributes a{};
+    int dev = 0, lds_cu = 0, thr_cu = 0;
+    int rc = check_hip(hipFuncGetAttributes(&a, fn), "hipFuncGetAttributes");
+    if (rc == LBM_OK) rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (rc == LBM_OK)
+        rc = check_hip(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev),
+                       "LDS per CU");
+    if (rc == LBM_OK)
+        rc = check_hip(hipDeviceGetAttribute(&thr_cu, hipDeviceAttributeMaxThreadsPerMultiProcessor, dev),
+                       "threads per CU");
+    if (rc != LBM_OK) return rc;
+    const int waves = (threads + 63) / 64;
+    const int vgpr = std::max(8, (a.numRegs + 7) / 8 * 8);
+    const int waves_per_simd = std::min(std::min(8, 512 / vgpr), sgpr_waves(sgprs));
+    int fit = waves_per_simd * 4 / waves;
+    if (a.sharedSizeBytes > 0) fit = std::min(fit, lds_cu / (int)a.sharedSizeBytes);
+    if (thr_cu > 0) fit = std::min(fit, thr_cu / threads);
+    *out = fit;
+    return fit >= 1 ? LBM_OK : set_error(LBM_EHIP, "persistent kernel does not fit a CU");
+}
+
+// Groups per CU of a launch of shape k: the probed figure once known, else the smaller of the
+// kernel's resource figure and the runtime's occupancy query.
+int groups_limit(lbm_batch* b, int k) {
+    if (b->resident[k] > 0) return b->resident[k];
+    return b->res_fit[k] > 0 ? std::min(b->res_fit[k], b->occ[k]) : b->occ[k];
+}
 
 int grid_size(lbm_batch* b, int k) {
     const int lim = groups_limit(b, k);
@@ -698,16 +785,16 @@ int run_persistent(lbm_batch* b, int k, int units, int advance) {
     return run_persistent_on(b, k, grid_size(b, k), units, advance, b->timeout_ticks);
 }
 
-// The occupancy query can promise more resident workgroups per CU than the hardware actually
-// co-schedules for a kernel (measured on MI355X: 8 reported, 7 resident for the FP32 and FP16
-// kernels), and a persistent grid larger than what is resident cannot pass its first barrier.
-// Before the first run of each launch shape, a probe runs two non-advancing steps (or pairs;
-// they recompute from the same copy: state, counters and records unchanged) with a short
-// barrier bound, at `per` groups per CU from the query's value down, and keeps the first `per`
-// whose grid passed every barrier.  A failed probe ends by its bound: every wave exits.
+// A persistent grid larger than what the CUs hold at once cannot pass its first barrier.  The
+// grid is sized from the kernel's own resources (resources_fit, no larger than the runtime's
+// occupancy query).  As a safety net, before the first run of each launch shape a probe runs two
+// non-advancing steps (or pairs or triples; they recompute from the same copy: state, counters and
+// records unchanged) with a short barrier bound, and steps the figure down only if that grid did
+// not pass every barrier (counted in probe_stepdowns).  A failed probe ends by its bound: every
+// wave exits.
 int ensure_resident(lbm_batch* b, int k) {
     if (b->resident[k] > 0) return LBM_OK;
-    for (int per = b->occ[k]; per >= 1; --per) {
+    for (int per = groups_limit(b, k); per >= 1; --per) {
         int rc = run_persistent_on(b, k, b->cus * per, 2, 0, b->probe_ticks);
         if (rc == LBM_OK) rc = check_hip(hipStreamSynchronize(b->stream), "synchronise (residency probe)");
         int err = 0;
@@ -717,6 +804,7 @@ int ensure_resident(lbm_batch* b, int k) {
             b->resident[k] = per;
             return LBM_OK;
         }
+        ++b->probe_stepdowns;
         if (err == 2) return set_error(LBM_EHIP, "an XCD that owns instances got no workgroup");
         hipLaunchKernelGGL(k_clear_i32, dim3(1), dim3(64), 0, b->stream, b->d_err);
         rc = check_hip(hipGetLastError(), "clear err");
@@ -895,6 +983,9 @@ int lbm_batch_create(lbm_batch** out, const lbm_instance_desc* desc, int n, int 
                                                                     kTileThreads, 0),
                        "occupancy");
         if (rc == LBM_OK && b->occ[k] < 1) rc = set_error(LBM_EHIP, "persistent kernel does not fit a CU");
+        if (rc == LBM_OK)
+            rc = resources_fit(batch_kernel_p(prec, npts[k]), kTileThreads, prec == LBM_F64 ? batch1_sgprs<kF64>() :
+                               batch1_sgprs<kF32>(), &b->res_fit[k]);
         // tile table and descriptors for this NPT
         const int tile_nodes = kTileThreads * npts[k];
         std::vector<int> tiles, tile0((size_t)n, 0);
@@ -946,11 +1037,14 @@ int lbm_batch_create(lbm_batch** out, const lbm_instance_desc* desc, int n, int 
         rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[3], batch2_kernel_p(prec), kTileThreads, 0),
                        "occupancy");
     if (rc == LBM_OK && b->occ[3] < 1) rc = set_error(LBM_EHIP, "persistent two-step kernel does not fit a CU");
+    if (rc == LBM_OK) rc = resources_fit(batch2_kernel_p(prec), kTileThreads, kBatchFusedSgprs, &b->res_fit[3]);
     if (rc == LBM_OK && batch3_kernel_p(prec))
         rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[4], batch3_kernel_p(prec), kTileThreads, 0),
                        "occupancy");
     if (rc == LBM_OK && batch3_kernel_p(prec) && b->occ[4] < 1)
         rc = set_error(LBM_EHIP, "persistent three-step kernel does not fit a CU");
+    if (rc == LBM_OK && batch3_kernel_p(prec))
+        rc = resources_fit(batch3_kernel_p(prec), kTileThreads, kBatchFusedSgprs, &b->res_fit[4]);
     if (rc == LBM_OK) rc = check_hip(hipMalloc(&b->d_xtab[3], sizeof(int) * 2 * kMaxXcc), "hipMalloc(xtab)");
     if (rc == LBM_OK && batch3_kernel_p(prec))
         rc = check_hip(hipMalloc(&b->d_xtab[4], sizeof(int) * 2 * kMaxXcc), "hipMalloc(xtab)");
@@ -1129,6 +1223,17 @@ int lbm_batch_rebalance(lbm_batch* b) {
     std::vector<char> live;
     const int rc = live_set(b, live);
     return rc != LBM_OK ? rc : deal_tables(b, live);
+}
+
+int lbm_batch_residency(lbm_batch* b, int shape, int* from_resources, int* occupancy_query, int* resident,
+                        int* probe_stepdowns) {
+    if (!b) return set_error(LBM_ESTATE, "batch is NULL");
+    if (shape < 0 || shape > 4) return set_error(LBM_EINVAL, "shape %d not in 0..4", shape);
+    if (from_resources) *from_resources = b->res_fit[shape];
+    if (occupancy_query) *occupancy_query = b->occ[shape];
+    if (resident) *resident = b->resident[shape];
+    if (probe_stepdowns) *probe_stepdowns = b->probe_stepdowns;
+    return LBM_OK;
 }
 
 int lbm_batch_set_fusion(lbm_batch* b, int strip_rows) {

@@ -211,3 +211,24 @@ def test_full_sweep_bit_identical_to_plain(gpu):
         s.close()
         assert blow[k] == st and same, (k, d["model"], d["nx"], blow[k], st)
     b.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_residency_from_resources(gpu, prec):
+    """Every persistent launch shape is sized from its kernel's own resources (VGPRs, SGPR bound,
+    LDS, threads) and the runtime's occupancy figure, and the bounded residency probe of its first
+    run confirms that size (no step down)."""
+    rng = np.random.default_rng(5)
+    insts = [{"nx": 64 + 16 * (k % 3), "ny": 64, "model": m, "eq_order": 4,
+              "omega": list(inputs.rates(1e-4, "REG")), "rho0": 1.0, "mach": float(rng.uniform(0.1, 0.4))}
+             for k, m in enumerate(list(inputs.MODEL_NAMES) * 2)]
+    fields = [fields_of(d, k) for k, d in enumerate(insts)]
+    b = Batch(insts, fields, prec=prec, device=gpu)
+    b.autotune(1)  # times every launch shape, probing each one's residency first
+    shapes = range(5) if prec != "f16" else range(4)
+    for shape in shapes:
+        fit, occ, res, down = b.residency(shape)
+        print(f"residency {prec} shape {shape}: resources {fit}, runtime {occ}, confirmed {res}", flush=True)
+        assert fit >= 1 and res == min(fit, occ), (shape, fit, occ, res)
+    assert b.residency(0)[3] == 0  # no probe had to lower a figure
+    b.close()
