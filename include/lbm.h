@@ -174,9 +174,12 @@ int lbm_set_launch(lbm_ctx* ctx, int model, int rows, int xcd);
  * except where an FP32 model's measured best setting on 128-column strips, (ring_rows, strip_rows)
  * = (8, 8) for BGK and (4, 20) for the others, gives at least 1024 such strips: it starts with that;
  * and an FP32 or FP64 context starts every model with three steps per launch
- * (lbm_set_fusion_depth) and ring_rows 4 when its 64-column strips of strip_rows rows number at
- * least 512, strip_rows being ceil(nx / 64) ny / sqrt(nx ny) rounded to a multiple of 8 and
- * clamped to [8, 64] (n / 64 on an n x n grid), and 80 instead of 64 in FP32.
+ * (lbm_set_fusion_depth) when its 64-column strips of h rows number at least 512, h being
+ * ceil(nx / 64) ny / sqrt(nx ny) rounded to a multiple of 8 and clamped to [8, 64] (n / 64 on an
+ * n x n grid), and 80 instead of 64 in FP32: FP32 with ring_rows 8 and strip_rows h, raised in
+ * steps of 8 while the strips number more than one round of workgroups (3 per CU) but no more than
+ * 1.5 rounds; FP64 with ring_rows 8 and strip_rows h (96 instead of 64), except BGK: ring_rows 4,
+ * strip_rows h.
  * Results are bit-identical to single steps (same arithmetic per node; the LDS ring holds the
  * stored type).  Returns LBM_EINVAL for other values. */
 int lbm_set_fusion(lbm_ctx* ctx, int model, int ring_rows, int strip_rows);
@@ -188,8 +191,9 @@ int lbm_get_fusion(lbm_ctx* ctx, int model, int* ring_rows, int* strip_rows);
  * lbm_set_fusion, lbm_step advances three steps per launch (then pairs, then single steps), each
  * the step of eq. StreamCollide: a second LDS ring holds the second step's values, so each
  * population is read and written once per three steps; the first step covers two halo rows and
- * columns on each side of the strip, the second one.  Strips are 64 columns wide, except FP64 with
- * ring_rows 4: 48, so that the strip and its halo columns fit one wave.  Bit-identical to single
+ * columns on each side of the strip, the second one.  Strips are 64 columns wide in FP32 and 48 in
+ * FP64 (the strip and its halo columns fit one wave); with ring_rows 8 a workgroup runs 8 waves, one
+ * row each per pass.  Bit-identical to single
  * steps.  LBM_EUNSUPPORTED for 3 on an FP16 context or on a grid narrower or lower than
  * 2; LBM_EINVAL for other values. */
 int lbm_set_fusion_depth(lbm_ctx* ctx, int model, int steps);

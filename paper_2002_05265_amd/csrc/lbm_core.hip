@@ -213,13 +213,38 @@ constexpr FusionPick wide_default(int model) { return model == LBM_BGK ? FusionP
 // (118 / 117k), 3072^2 hs 48 180 / 162k, 4096^2 hs 80 186 / 169k (hs 64: 1.5% less; two steps:
 // 145 / 138k); FP64 2048^2 75 / 72k (61 / 62k), 4096^2 hs 64 86 / 83k (75 / 74k).
 constexpr long long kDeepMinStrips = 512;
-constexpr int kDeepRing = 4;
 
 int deep_strip(int nx, int ny, int prec) {
     const double gsx = (double)((nx + kStripW - 1) / kStripW);
     const int h = 8 * (int)(gsx * ny / std::sqrt((double)nx * ny) / 8.0 + 0.5);
     const int hs = h < 8 ? 8 : (h > 64 ? 64 : h);
     return (prec == LBM_F32_SHIFTED && hs == 64) ? 80 : hs;
+}
+
+// Ring and strip height of a model's three-step launches on a new context (deep_strip's count of
+// 64-column strips is at least kDeepMinStrips).  Measured on MI355X (double shear layer, MLUPS):
+// - FP32: a ring of 8 rows (8 waves, 48 KiB of LDS, three workgroups per CU) for every model, at
+//   4096^2 with 80-row strips 174-191k against 170-185k with a ring of 4 (K / BGK), at 2048^2 152 /
+//   166k against 145 / 160k, at 512^2 78 / 91k against 67 / 78k.  Where the strip count lies just
+//   above one round of workgroups (three per CU), up to 1.5 rounds, the strips are made taller until
+//   they fit one round: at 1024^2, 24-row strips 118 / 131k against 106 / 120k with 16 rows (a ring
+//   of 4 rows on 16-row strips: 118 / 129k).
+// - FP64: a ring of 8 rows on 48-column strips (74 KiB, two workgroups of 8 waves per CU) for every
+//   model but BGK, 96 rows where deep_strip gives 64: at 4096^2 RM 98k, CM 92k, K 90k, PR 102k
+//   against 92k, 86k, 85k, 97k with a ring of 4 rows; BGK keeps the ring of 4 (98k against 96k).
+FusionPick deep_pick(int model, int nx, int ny, int prec, int cus) {
+    const int hs = deep_strip(nx, ny, prec);
+    if (prec == LBM_F64) {
+        if (model == LBM_BGK) return FusionPick{4, hs};
+        return FusionPick{8, hs == 64 ? 96 : hs};
+    }
+    const long long gsx = (nx + kStripW - 1) / kStripW;
+    const long long round = 3LL * cus;
+    int h = hs;
+    auto strips = [&](int r) { return gsx * ((ny + r - 1) / r); };
+    if (cus > 0 && strips(h) > round && 2 * strips(h) <= 3 * round)
+        while (strips(h) > round && h < 256) h += 8;
+    return FusionPick{8, h};
 }
 
 // Widest strip for a model and precision; the launch uses it only while it still gives at least
@@ -285,7 +310,7 @@ __global__ __launch_bounds__(64 * step3_waves<RING>()) void k_step3(const typena
 // Three steps per launch on strips of WP columns whose halo columns fit the wave (FP64: WP = 48;
 // measured at 4096^2 against 64-column strips: BGK 96 against 86k MLUPS, K 82 against 80k).
 template <int MODEL, int PREC, int RING, int WP>
-__global__ __launch_bounds__(256) void k_step3n(const typename Store<PREC>::S* __restrict__ src,
+__global__ __launch_bounds__(64 * step3_waves<RING>()) void k_step3n(const typename Store<PREC>::S* __restrict__ src,
                                                 typename Store<PREC>::S* __restrict__ dst, Geom g,
                                                 Coef<typename Store<PREC>::R> c,
                                                 Ref<typename Store<PREC>::R> ref, int N, int step,
@@ -299,8 +324,9 @@ __global__ __launch_bounds__(256) void k_step3n(const typename Store<PREC>::S* _
     tile_of_block(blockIdx.x, gsx, gridDim.x, 1, sx, sy);
     const int x0 = (int)sx * WP;
     const int ys = (int)sy * hs;
-    strip_three_steps_narrow<RING, WP>(ring1, ring2, src, dst, g, ref, x0, ys, min(ys + hs, g.ny), step, blowup,
-                                       [&](R(&h)[9], const Macro<R>& m) { collide<MODEL>(h, m, ref, c, N); });
+    strip_three_steps_narrow<RING, WP, false, true, step3_waves<RING>()>(
+        ring1, ring2, src, dst, g, ref, x0, ys, min(ys + hs, g.ny), step, blowup,
+        [&](R(&h)[9], const Macro<R>& m) { collide<MODEL>(h, m, ref, c, N); });
 }
 
 // Macroscopic fields of the state f(., n) (pulled from the post-collision copy) and per-block
@@ -566,24 +592,23 @@ void launch_step3n_w(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int h
     using S = typename Store<PREC>::S;
     const unsigned gsx = (unsigned)((ctx->nx + WP - 1) / WP);
     const unsigned gsy = (unsigned)((ctx->ny + hs - 1) / hs);
-    hipLaunchKernelGGL((k_step3n<MODEL, PREC, RING, WP>), dim3(gsx * gsy), dim3(256), 0, ctx->stream,
+    hipLaunchKernelGGL((k_step3n<MODEL, PREC, RING, WP>), dim3(gsx * gsy), dim3(64 * step3_waves<RING>()), 0, ctx->stream,
                        reinterpret_cast<const S*>(ctx->copy(src_copy)), reinterpret_cast<S*>(ctx->copy(src_copy ^ 1)),
                        ctx->geom(), c, ref_as<typename Store<PREC>::R>(ctx->ref), ctx->eq_order, (int)ctx->step,
                        ctx->d_flag, gsx, hs);
 }
 
-// Three steps per launch (FP32 and FP64), 64-column strips, except FP64 with a ring of 4 rows
-// (48-column narrow strips): the two rings of 128-column strips take 56 KiB of LDS in FP32 with a
-// ring of 4 rows, two workgroups per CU, and measured 10-25% slower.
+// Three steps per launch: FP32 on 64-column strips (the two rings of 128-column strips take 56 KiB
+// of LDS with a ring of 4 rows, two workgroups per CU, and measured 10-25% slower), FP64 on 48-column
+// narrow strips with either ring.
 template <int MODEL, int PREC>
 void launch_step3_t(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int ring, int hs, int src_copy) {
     if constexpr (PREC == kF64) {
-        if (ring == 4) {
+        if (ring == 4)
             launch_step3n_w<MODEL, PREC, 4, kNarrowW>(ctx, c, hs, src_copy);
-            return;
-        }
-    }
-    if constexpr (PREC != kF16) {
+        else
+            launch_step3n_w<MODEL, PREC, 8, kNarrowW>(ctx, c, hs, src_copy);
+    } else if constexpr (PREC == kF32) {
         if (ring == 4)
             launch_step3_w<MODEL, PREC, 4, kStripW>(ctx, c, hs, src_copy);
         else
@@ -761,11 +786,19 @@ int lbm_init_shifted(lbm_ctx** out, int nx, int ny, int prec, int eq_order, doub
     const int dstrip = deep_strip(nx, ny, prec);
     const bool deep = prec != LBM_F16_SHIFTED && nx >= 2 && ny >= 2 &&
                       (long long)((nx + kStripW - 1) / kStripW) * ((ny + dstrip - 1) / dstrip) >= kDeepMinStrips;
+    int cus = 0;
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 0;
+    }
     if (deep)
         for (int k = 0; k < 9; ++k) {
+            const FusionPick pick = deep_pick(k < 8 ? k : LBM_STREAM_ONLY, nx, ny, prec, cus);
             ctx->fuse_depth[k] = 3;
-            ctx->fuse_ring[k] = kDeepRing;
-            ctx->fuse_strip[k] = dstrip;
+            ctx->fuse_ring[k] = pick.ring;
+            ctx->fuse_strip[k] = pick.strip;
         }
     else if (fstrip > 0)
         for (int k = 0; k < 9; ++k) {

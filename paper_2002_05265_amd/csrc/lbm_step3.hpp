@@ -210,17 +210,17 @@ namespace lbm {
 // halo columns each side), the second on lanes 1 .. WP + 2, the third on lanes 2 .. WP + 1, which
 // write; there are no halo passes.  With WP = 48 in FP64 an output row segment is three whole
 // 128-byte lines and the rings take 44 KiB (three workgroups per CU against two for 64 columns).
-// Same rows, ring slots and barriers as strip_three_steps; one wave per row.  VIA_L2 selects
-// L1-bypassing loads, NT streaming stores.
-template <int RING, int WP, bool VIA_L2 = false, bool NT = true, typename S, typename R, typename Coll>
+// Same rows, ring slots and barriers as strip_three_steps; one wave per row, NW waves (4, or 8 with
+// a ring of 8 rows).  VIA_L2 selects L1-bypassing loads, NT streaming stores.
+template <int RING, int WP, bool VIA_L2 = false, bool NT = true, int NW = 4, typename S, typename R, typename Coll>
 __device__ __forceinline__ void strip_three_steps_narrow(S (&ring1)[9][RING + 2][WP + 4],
                                                          S (&ring2)[9][RING + 2][WP + 3],
                                                          const S* __restrict__ src, S* __restrict__ dst,
                                                          const Geom& g, const Ref<R>& ref, int x0, int ys, int ye,
                                                          int step, int* __restrict__ blowup, Coll&& coll) {
     constexpr int NR = RING + 2;
-    constexpr int KR = RING / 4;  // rows per wave and pass
-    static_assert(RING % 4 == 0 && WP + 4 <= 64, "ring rows: a multiple of 4; the strip and its halo fit a wave");
+    constexpr int KR = RING / NW;  // rows per wave and pass
+    static_assert(RING % NW == 0 && WP + 4 <= 64, "ring rows: a multiple of the waves; the strip and its halo fit a wave");
     const int lane = (int)(threadIdx.x & 63u);
     const int rl = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int w = min(WP, g.nx - x0);            // output columns of this strip
@@ -283,16 +283,16 @@ __device__ __forceinline__ void strip_three_steps_narrow(S (&ring1)[9][RING + 2]
         const int top = min(yb + RING + 1, ye + 1);
 #pragma unroll
         for (int k = 0; k < KR; ++k) {
-            const int a = yb + 2 + rl + 4 * k;
+            const int a = yb + 2 + rl + NW * k;
             if (a <= top && on1) load_own(a, hn[k]);
         }
     };
     // prologue: first step on rows ys - 2 .. ys + 1 (ring1 slots 0..3), second on ys - 1, ys
     {
         R hp[9];
-        if (on1) load_own(ys - 2 + rl, hp);
+        if (on1 && rl < 4) load_own(ys - 2 + rl, hp);
         prefetch(ys);
-        if (on1) finish1(rl, hp);
+        if (on1 && rl < 4) finish1(rl, hp);
     }
     __syncthreads();
     if (rl < 2 && on2) second(1 + rl, rl);
@@ -304,22 +304,22 @@ __device__ __forceinline__ void strip_three_steps_narrow(S (&ring1)[9][RING + 2]
         const int sb2 = (yb - ys + 1) % NR;
 #pragma unroll
         for (int k = 0; k < KR; ++k) {
-            const int a = yb + 2 + rl + 4 * k;
-            if (a <= top1 && on1) finish1(wrap(sb1 + 2 + rl + 4 * k), hn[k]);
+            const int a = yb + 2 + rl + NW * k;
+            if (a <= top1 && on1) finish1(wrap(sb1 + 2 + rl + NW * k), hn[k]);
         }
         __syncthreads();
         if (yb + RING < ye) prefetch(yb + RING);
 #pragma unroll
         for (int k = 0; k < KR; ++k) {
-            const int off = 1 + rl + 4 * k;
+            const int off = 1 + rl + NW * k;
             if (yb + off <= top2 && on2) second(sb1 + off, wrap(sb2 + off));
         }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < KR; ++k) {
-            const int y = yb + rl + 4 * k;
+            const int y = yb + rl + NW * k;
             if (y < ye && on3) {
-                const int s0 = sb2 + rl + 4 * k;
+                const int s0 = sb2 + rl + NW * k;
                 R h[9];
 #pragma unroll
                 for (int i = 0; i < 9; ++i) h[i] = R(ring2[i][wrap(s0 - cy(i))][lane - cx(i)]);

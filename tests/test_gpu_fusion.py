@@ -7,6 +7,7 @@ against the oracle directly.
 """
 import numpy as np
 import pytest
+import torch
 
 import oracle
 from paper_2002_05265_amd import inputs
@@ -115,11 +116,29 @@ def test_rejects_bad_shapes(gpu):
 
 
 def deep_strip(nx, ny, prec):
-    """Strip height of a new context's three-step launches (include/lbm.h)."""
+    """Base strip height of a new context's three-step launches (include/lbm.h)."""
     gsx = (nx + 63) // 64
     h = 8 * int(gsx * ny / (nx * ny) ** 0.5 / 8.0 + 0.5)
     hs = min(max(h, 8), 64)
     return 80 if (prec == "f32" and hs == 64) else hs
+
+
+def deep_pick(model, nx, ny, prec, cus):
+    """(ring_rows, strip_rows) of a model's default three-step launches (include/lbm.h)."""
+    hs = deep_strip(nx, ny, prec)
+    if prec == "f64":
+        return (4, hs) if model == "BGK" else (8, 96 if hs == 64 else hs)
+    gsx = (nx + 63) // 64
+    rnd = 3 * cus
+
+    def strips(r):
+        return gsx * (-(-ny // r))
+
+    h = hs
+    if strips(h) > rnd and 2 * strips(h) <= 3 * rnd:
+        while strips(h) > rnd and h < 256:
+            h += 8
+    return (8, h)
 
 
 def test_defaults_and_autotune(gpu):
@@ -129,7 +148,7 @@ def test_defaults_and_autotune(gpu):
                                  (4096, 1024, "f16"): (8, 40), (512, 512, "f32"): (8, 16),
                                  (256, 256, "f32"): (0, 0), (2048, 1000, "f64"): (8, 16),
                                  (512, 512, "f16"): (0, 0), (448, 512, "f64"): (0, 0),
-                                 (2048, 1024, "f32"): (8, 16), (1024, 2048, "f32"): (8, 16),
+                                 (2048, 1024, "f32"): (8, 16), (1024, 2048, "f32"): (8, 16), (1024, 1024, "f32"): (8, 16),
                                  (4096, 4096, "f32"): (8, 16), (4096, 4096, "f64"): (8, 64),
                                  (4096, 4096, "f16"): (8, 40), (320, 256, "f32"): (0, 0),
                                  (3072, 1536, "f32"): (8, 16)}.items():
@@ -140,9 +159,10 @@ def test_defaults_and_autotune(gpu):
         hs = deep_strip(nx, ny, prec)
         deep = prec != "f16" and (nx + 63) // 64 * (-(-ny // hs)) >= 512
         exp = []
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
         for m in MODELS:
             if deep:
-                exp.append((3, (4, hs)))
+                exp.append((3, deep_pick(m, nx, ny, prec, cus)))
                 continue
             # two steps: FP32 models take their 128-column setting where it gives >= 1024 strips
             wr, ws = (8, 8) if m == "BGK" else (4, 20)
@@ -150,7 +170,9 @@ def test_defaults_and_autotune(gpu):
             exp.append((2, (wr, ws) if wide else want))
         assert got == exp, (nx, ny, prec, got)
         if (nx, ny, prec) == (4096, 4096, "f32"):
-            assert exp[0] == (3, (4, 80))
+            assert exp[0] == (3, (8, 80))
+        if (nx, ny, prec) == (4096, 4096, "f64"):
+            assert exp[0] == (3, (4, 64)) and exp[5] == (3, (8, 96))
         if (nx, ny, prec) in ((256, 256, "f32"), (448, 512, "f64")):
             assert not deep
     # autotune leaves state and counter alone, keeps a valid choice, and results do not change
