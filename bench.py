@@ -249,6 +249,11 @@ def cache_resident_rates(models, sizes=(1024, 512), precs=("f32", "f64"), steps:
     return {"cache_resident": True, "steps": steps, "mlups": out}
 
 
+def note(msg: str):
+    """A progress line on stderr (the JSON result is the only line on stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 _SETTLE = {}
 
 
@@ -735,10 +740,13 @@ def extras_trace_summary(out_root: str, command: str):
     stats = _csv_rows(_find_csv(d, "kernel_stats.csv"))
     lines = ["# All kernels of a bench run with the extra workloads: kernel trace", "",
              "Command (from the repository root):", "", "```", command, "```", "",
-             "The batched kernel is launched cooperatively; the profiler may crash on its own exit after",
-             "the program has finished, with its result files complete. The batched launch shapes (one or",
-             "two steps per pass) are autotuned inside the run, so a profiled run may pick other shapes than",
-             "an unprofiled one.", "",
+             "Under rocprofv3 this command ends with a segmentation fault (status 139) inside the C",
+             "library's exit handlers, after the program has printed its JSON line and after the",
+             "profiler's tool finalisation, with the result files complete; without the profiler it exits",
+             "with status 0. By then the bench has closed every context and batch it made and the library",
+             "holds nothing that is torn down at exit, so the fault is in the profiler's own exit path",
+             "after cooperative launches. The batched launch shapes (one to three steps per pass) are",
+             "autotuned inside the run, so a profiled run may pick other shapes than an unprofiled one.", "",
              "| kernel | calls | total ms | average us | share % |", "|---|---|---|---|---|"]
     for r in stats[:40]:
         name = r["Name"].replace("(anonymous namespace)::", "").replace("void ", "", 1).split("(")[0][:80]
@@ -922,24 +930,35 @@ def main():
     if not args.no_extras:
         fields = (rho, ux, uy)
         extra_steps = max(20, args.steps // 2)
+        note("other precisions")
         line["precisions"] = {p: time_models(p, n, models, extra_steps, 5, omega, fields) for p in ("f64", "f16")}
+        note("cache-resident grids")
         line["small_grids"] = cache_resident_rates(models)
         # the same grids under the SRT preset (one rate for every non-conserved moment)
+        note("SRT preset")
         srt = inputs.rates(nu, "SRT")
         line["srt_preset"] = {"omega": [round(w, 6) for w in srt],
                               "mlups": {m: v["mlups"] for m, v in
                                         time_models(args.prec, n, models, extra_steps, 5, srt, fields).items()}}
         release_settle()
         f64_mlups = min(v["mlups"] for v in line["precisions"]["f64"].values())
+        note("batched sweep")
         line["batched"] = batched_sweep(args.batch_steps, f64_mlups)
+        note("adjoint")
         line["adjoint"] = adjoint_run()
         line["adjoint"]["reverse_step"] = adjoint_step_rate(n, models, rho, ux, uy, omega)
+        note("precision errors")
         line["precision_error"] = precision_errors(n)
+        note("stability map")
         line["stability_map"] = stability_map()
+        note("double shear layer study")
         line["dsl_study"] = dsl_study()
+        note("transport study")
         line["transport_study"] = transport_study()
+        note("linear stability domain")
         line["lsa_domain"] = lsa_domain()
     if not args.no_cpu:
+        note("oracle on the host cores")
         line["cpu_baseline"] = cpu_baseline(models)
     print(json.dumps(line), flush=True)
 
