@@ -554,14 +554,16 @@ def adjoint_run(n: int = 512, steps: int = 2000, prec: str = "f32"):
             "mlups_forward_plus_backward": round(cells * steps / total / 1e6, 1),
             "plain_mlups": round(cells * steps / plain_s / 1e6, 1),
             "vs_plain": round(plain_s / total, 3),
-            "expected_vs_plain_from_bytes": round(18 / (18 + 18 + 27), 3),
+            "expected_vs_plain_from_bytes": round(18 / (18 + 18 + 18), 3),
             "cache_resident": True, **stats}
 
 
 def adjoint_step_rate(n: int, models, rho, ux, uy, omega, prec: str = "f32", steps: int = 20):
-    """Throughput of the reverse step alone at the bench grid: one node of lambda_n = J_C^T S^T
-    lambda_{n+1} reads 9 stored populations and gathers 9 adjoint values and writes 9 (27 values,
-    9 s + 18 a bytes), against the same HBM peak as the forward step."""
+    """Throughput of the reverse steps alone at the bench grid.  One step per launch: a node of
+    lambda_n = J_C^T S^T lambda_{n+1} reads 9 stored populations, gathers 9 adjoint values and
+    writes 9 (27 values, 9 s + 18 a bytes).  Two per launch (three adjoint buffers in rotation):
+    per node and pair, f_n, f_{n-1} and lambda_{n+1} read and lambda_{n-1} written (18 s + 18 a
+    bytes, 9 s + 9 a per step).  Both against the same HBM peak as the forward step."""
     import torch
 
     from paper_2002_05265_amd import binding as B
@@ -572,29 +574,36 @@ def adjoint_step_rate(n: int, models, rho, ux, uy, omega, prec: str = "f32", ste
     dev = torch.device("cuda:0")
     sim = Sim(rho, ux, uy, prec=prec, eq_order=4, device=dev)
     sim.step("CM", omega, 3)
-    st = torch.empty(B.lbm_state_bytes(sim.ctx), dtype=torch.uint8, device=dev)
-    B.lbm_save_state(sim.ctx, st.data_ptr())
-    lam = [torch.zeros(B.lbm_adjoint_bytes(sim.ctx), dtype=torch.uint8, device=dev) for _ in range(2)]
-    states = [st.data_ptr()] * steps
-    ptrs = [lam[k % 2].data_ptr() for k in range(steps + 1)]
+    st = [torch.empty(B.lbm_state_bytes(sim.ctx), dtype=torch.uint8, device=dev) for _ in range(2)]
+    B.lbm_save_state(sim.ctx, st[0].data_ptr())
+    sim.step("CM", omega, 1)
+    B.lbm_save_state(sim.ctx, st[1].data_ptr())
+    lam = [torch.zeros(B.lbm_adjoint_bytes(sim.ctx), dtype=torch.uint8, device=dev) for _ in range(3)]
+    states = [st[k % 2].data_ptr() for k in range(steps)]
     dw = torch.zeros(5, dtype=torch.float64, device=dev)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     out = {}
-    for m in models:
-        code = inputs.MODEL_CODES[m]
-        B.lbm_adjoint_many(sim.ctx, code, omega, states[:2], ptrs[:3], dw.data_ptr())
-        torch.cuda.synchronize()
-        e0.record()
-        B.lbm_adjoint_many(sim.ctx, code, omega, states, ptrs, dw.data_ptr())
-        e1.record()
-        torch.cuda.synchronize()
-        us = e0.elapsed_time(e1) * 1e3 / steps
-        gbs = n * n * (9 * sb + 18 * ab) / us / 1e3
-        out[m] = {"us_per_step": round(us, 1), "mlups": round(n * n / us, 1), "gbs": round(gbs, 1),
-                  "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    for depth, nbuf, key, bpn in ((1, 2, "one_step_per_launch", 9 * sb + 18 * ab),
+                                  (2, 3, "two_steps_per_launch", 9 * sb + 9 * ab)):
+        B.lbm_set_adjoint_depth(sim.ctx, depth)
+        ptrs = [lam[k % nbuf].data_ptr() for k in range(steps + 1)]
+        res = {}
+        for m in models:
+            code = inputs.MODEL_CODES[m]
+            B.lbm_adjoint_many(sim.ctx, code, omega, states[:2], ptrs[:3], dw.data_ptr())
+            torch.cuda.synchronize()
+            e0.record()
+            B.lbm_adjoint_many(sim.ctx, code, omega, states, ptrs, dw.data_ptr())
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / steps
+            gbs = n * n * bpn / us / 1e3
+            res[m] = {"us_per_step": round(us, 1), "mlups": round(n * n / us, 1), "gbs": round(gbs, 1),
+                      "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        out[key] = {"bytes_per_node_and_step": bpn, "models": res}
     sim.close()
-    return {"workload": f"reverse step alone, {n}x{n} double shear layer state, {prec}, {steps} steps",
-            "bytes_per_node": 9 * sb + 18 * ab, "models": out}
+    return {"workload": f"reverse steps alone, {n}x{n} double shear layer states, {prec}, {steps} steps",
+            **out}
 
 
 def _csv_rows(path):
@@ -756,6 +765,83 @@ def extras_trace_summary(out_root: str, command: str):
         fh.write("\n".join(lines) + "\n")
 
 
+def reverse_profile_commands(prec: str) -> dict:
+    """The rocprofv3 commands behind the reverse-step summaries (bench.py --reverse-only)."""
+    d = "gpurun_out" if prec == "f32" else f"gpurun_out/p_{prec}"
+    cmd = f"python bench.py --reverse-only --prec {prec}"
+    out = {k: f"rocprofv3 --pmc {c} --output-format csv -d {d}/rp_rev_{k} -o rev -- {cmd}"
+           for k, c in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE"), ("valu", "VALUBusy"),
+                        ("flops", " ".join(flop_counters(prec))))}
+    out["trace"] = f"rocprofv3 --kernel-trace --stats --output-format csv -d {d}/rp_rev_trace -o rev -- {cmd}"
+    out["copy_fetch"], out["copy_write"] = PROFILE_COMMANDS["copy_fetch"], PROFILE_COMMANDS["copy_write"]
+    return out
+
+
+def reverse_profile_summary(out_root: str, prec: str, n: int = 4096):
+    """Kernel trace and counters of the reverse-step kernels (one and two steps per launch) from
+    the output of reverse_profile_commands(prec) under out_root (rp_copy_* calibration beside it)."""
+    import re
+
+    cmds = reverse_profile_commands(prec)
+    d = lambda k: os.path.join(out_root, f"rp_rev_{k}")
+    if not os.path.isdir(d("trace")):
+        return
+    sb, ab = (8, 8) if prec == "f64" else (4, 4)
+    cells = n * n
+    alg = {"1": cells * (9 * sb + 18 * ab), "2": cells * (18 * sb + 18 * ab)}
+    stats = _csv_rows(_find_csv(d("trace"), "kernel_stats.csv"))
+    fetch = _csv_rows(_find_csv(d("fetch"), "counter_collection.csv"))
+    write = _csv_rows(_find_csv(d("write"), "counter_collection.csv"))
+    valu = _csv_rows(_find_csv(d("valu"), "counter_collection.csv"))
+    flops = _csv_rows(_find_csv(d("flops"), "counter_collection.csv"))
+    cf, _ = _per_dispatch(_csv_rows(_find_csv(os.path.join(out_root, "rp_copy_fetch"), "counter_collection.csv")),
+                          "copyBuffer")
+    cw, _ = _per_dispatch(_csv_rows(_find_csv(os.path.join(out_root, "rp_copy_write"), "counter_collection.csv")),
+                          "copyBuffer")
+    gib_kib = (1 << 30) / 1024
+    fscale, wscale = gib_kib / cf, gib_kib / cw
+    rows = ["| kernel | steps per launch | calls | average us | us per step | HBM bytes (scaled) | / algorithmic "
+            "| GB/s at algorithmic bytes | frac of 8 TB/s | VALUBusy % | flops per node and step |",
+            "|---|---|---|---|---|---|---|---|---|---|---|"]
+    blob = {"prec": prec, "n": n, "algorithmic_bytes": alg, "kernels": {}}
+    for r in stats:
+        m = re.search(r"k_adjoint_strip([12])<(\d+), (\d+)>", r["Name"])
+        if not m:
+            continue
+        depth, model = m.group(1), int(m.group(2))
+        key = f"k_adjoint_strip{depth}<{model}, {m.group(3)}>"
+        label = f"k_adjoint_strip{depth}<{MODEL_ORDER[model] if model < 8 else model}, {prec}>"
+        avg = float(r["AverageNs"]) * 1e-3
+        f_kib, _ = _per_dispatch(fetch, key)
+        w_kib, _ = _per_dispatch(write, key)
+        hbm = None if f_kib is None or w_kib is None else f_kib * 1024 * fscale + w_kib * 1024 * wscale
+        vb, _ = _per_dispatch(valu, key)
+        fl = _flops_per_dispatch(flops, key, prec)
+        st = int(depth)
+        gbs = alg[depth] / (avg * 1e-6) / 1e9
+        fpn = None if fl is None else fl / (cells * st)
+        rows.append(f"| {label} | {st} | {r['Calls']} | {avg:.1f} | {avg / st:.1f} | "
+                    f"{'' if hbm is None else f'{hbm:.4g}'} | {'' if hbm is None else f'{hbm / alg[depth]:.4f}'} | "
+                    f"{gbs:.1f} | {gbs / HBM_PEAK_GBS:.4f} | {'' if vb is None else f'{vb:.1f}'} | "
+                    f"{'' if fpn is None else f'{fpn:.1f}'} |")
+        blob["kernels"][label] = {"avg_us": round(avg, 2), "hbm_bytes": None if hbm is None else int(hbm),
+                                  "valu_busy": None if vb is None else round(vb / 100, 4),
+                                  "flops_per_node_step": None if fpn is None else round(fpn, 1),
+                                  "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+    text = [f"# Adjoint reverse steps ({prec}, {n}x{n} double shear layer states): trace and counters", "",
+            "Commands (from the repository root; each counter in a run of its own):", "", "```",
+            *(cmds[k] for k in ("trace", "fetch", "write", "valu", "flops", "copy_fetch", "copy_write")), "```", "",
+            f"Algorithmic bytes per launch: one reverse step per launch {n}*{n} * (9 s + 18 a) = {alg['1']} B "
+            f"(f_n pulled, lambda_n+1 gathered, lambda_n written); two per launch {n}*{n} * (18 s + 18 a) = "
+            f"{alg['2']} B (f_n, f_n-1 and lambda_n+1 read, lambda_n-1 written; s = a = {sb} B). HBM bytes: "
+            f"FETCH_SIZE x {fscale:.4f} + WRITE_SIZE x {wscale:.4f} (the same 1 GiB copy calibration as the "
+            "step-kernel counters). Flops: 64 lanes x (ADD + MUL + TRANS + 2 FMA) VALU instructions per "
+            "dispatch over the node updates it makes (the two-step kernel's include its halo).", "", *rows, "",
+            "```json", json.dumps(blob, indent=1), "```", ""]
+    with open(os.path.join(PROFILE_DIR, f"adjoint_reverse_{prec}_dsl4096.md"), "w") as fh:
+        fh.write("\n".join(text))
+
+
 PROFILE_ARGS = "--steps 40 --warmup 4 --no-cpu --no-extras"
 EXTRAS_PROFILE_COMMAND = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/rp_trace_all -o bench -- "
                           "python bench.py --steps 20 --warmup 2 --no-cpu --batch-steps 2000")
@@ -808,13 +894,21 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FP64/FP16, batched and adjoint measurements")
     ap.add_argument("--batch-steps", type=int, default=20000)
+    ap.add_argument("--reverse-only", action="store_true",
+                    help="only time the adjoint's reverse steps (one and two per launch) at the bench grid")
     ap.add_argument("--stability-map", type=int, metavar="L",
                     help="only run the stability-domain map on L x L vortices (Section 5b; L = 256 is "
                          "the paper's resolution, minutes of GPU time) and print it as JSON")
     ap.add_argument("--profile-summary", metavar="DIR",
                     help="summarise the rocprofv3 csv output of PROFILE_COMMANDS found under DIR "
                          "into profiles/ (no GPU use)")
+    ap.add_argument("--reverse-profile-summary", metavar="DIR",
+                    help="summarise the rocprofv3 csv output of reverse_profile_commands(prec) found under "
+                         "DIR (with the copy calibration beside it) into profiles/ (no GPU use)")
     args = ap.parse_args()
+    if args.reverse_profile_summary:
+        reverse_profile_summary(args.reverse_profile_summary, args.prec, args.n)
+        return
     if args.profile_summary:
         profile_summary(args.profile_summary, args.prec, args.n, profile_commands(args.prec))
         if args.prec == "f32":
@@ -840,6 +934,12 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 1 << 30, "copy_probe_bytes_written": 1 << 30,
                           "launches": 5}), flush=True)
+        return
+    if args.reverse_only:
+        nu = inputs.dsl_nu(args.n, 0.1)
+        rho, ux, uy = inputs.dsl_fields(args.n, args.n, 0.1)
+        out = adjoint_step_rate(args.n, args.models.split(","), rho, ux, uy, inputs.rates(nu, "REG"), args.prec)
+        print(json.dumps({"reverse_step": out}), flush=True)
         return
     if args.stability_map:
         L = args.stability_map

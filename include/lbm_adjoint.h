@@ -92,13 +92,27 @@ int lbm_adjoint_step(lbm_ctx* ctx, int model, const double* omega, const void* s
 /* count (>= 0) reverse steps in one call: step k applies the adjoint at raw state states[k]
  * to lam[k] and writes lam[k + 1] (host arrays of device pointers; lam has count + 1 entries,
  * lam[k] != lam[k + 1]).  Same arithmetic as lbm_adjoint_step, without one host call per step.
- * Rate gradients: each block of the grid keeps a running FP64 sum of its contributions, in
- * step order, across calls.  With domega != NULL the pending sums are added to domega (device,
+ * With two reverse steps per launch (lbm_set_adjoint_depth), steps k and k + 1 run as one
+ * launch wherever lam[k + 2] != lam[k] (taking steps in pairs from k = 0): lambda at step k + 1
+ * then stays on chip and lam[k + 1] is NOT written; the values written to lam[k + 2] (and to
+ * every lam that is written) are bit-identical to one step per launch.  A caller that cycles
+ * through three buffers (lam[k] = buffer k mod 3) gets pairs; two alternating buffers give one
+ * step per launch.
+ * Rate gradients: each strip of the grid (64 columns by a fixed number of rows per context)
+ * keeps a running FP64 sum of its contributions, in step order, across calls, whether steps run
+ * one or two per launch.  With domega != NULL the pending sums are added to domega (device,
  * 5 doubles) at the end of the call and cleared; with domega == NULL they stay pending, so
  * that a whole reverse sweep issued in any grouping of calls sums in the same order
  * (bit-identical gradients).  lbm_adjoint_step is this function with count = 1. */
 int lbm_adjoint_many(lbm_ctx* ctx, int model, const double* omega, const void* const* states,
                      int count, void* const* lam, double* domega);
+
+/* Reverse steps per launch of lbm_adjoint_many: 1 (the default) or 2 (pairs of reverse steps
+ * as one pass that keeps the intermediate adjoint in LDS: 18 s + 18 a bytes per node and pair
+ * against 2 (9 s + 18 a), s and a the stored and adjoint value sizes).  Other values give
+ * LBM_EINVAL.  lbm_get_adjoint_depth writes the setting to *steps. */
+int lbm_set_adjoint_depth(lbm_ctx* ctx, int steps);
+int lbm_get_adjoint_depth(lbm_ctx* ctx, int* steps);
 
 /* Add the pending rate-gradient sums (see lbm_adjoint_many) to domega (device, 5 doubles) and
  * clear them; nothing to add leaves domega unchanged.  Asynchronous. */

@@ -121,7 +121,7 @@ class _Run:
     current buffer."""
 
     def __init__(self, u0, omega, rho0, target, model, nsteps, prec, eq_order, schedule, slots,
-                 ref_velocity):
+                 ref_velocity, reverse_depth: int = 2):
         self.model = MODEL_CODES[model] if isinstance(model, str) else int(model)
         self.omega = [float(w) for w in omega]
         self.nsteps = int(nsteps)
@@ -136,6 +136,9 @@ class _Run:
         self.sim = Sim(self.rho0, self.ux0, self.uy0, prec=prec, eq_order=eq_order, device=dev,
                        ref_velocity=ref_velocity)
         self.ctx = self.sim.ctx
+        # reverse steps in pairs, one launch each (the adjoint between them stays on chip); the
+        # gradients are bit-identical to one reverse step per launch
+        B.lbm_set_adjoint_depth(self.ctx, reverse_depth)
         self.sbytes = B.lbm_state_bytes(self.ctx)
         self.abytes = B.lbm_adjoint_bytes(self.ctx)
         self.dev = dev
@@ -226,14 +229,20 @@ class _Run:
             B.lbm_step_raw_many(self.ctx, self.model, self.omega, self.q_src, self.q_dst, self.q_step0)
             self.q_src, self.q_dst = [], []
 
+    def _reverse(self, states):
+        """Reverse steps at the raw states `states` (device pointers, in reverse-step order) from
+        the adjoint in self.lam[0], which then holds the result.  Three buffers in rotation let
+        lbm_adjoint_many take the steps in pairs; gradients stay pending in the per-strip sums
+        until the end of the sweep, so every schedule sums them in the same (step) order."""
+        m = len(states)
+        ptrs = [self.lam[k % 3].data_ptr() for k in range(m + 1)]
+        B.lbm_adjoint_many(self.ctx, self.model, self.omega, states, ptrs, None)
+        r = m % 3
+        self.lam = self.lam[r:] + self.lam[:r]
+
     def _flush_adjoints(self):
         if self.a_states:
-            lam = [self.lam[k % 2].data_ptr() for k in range(len(self.a_states) + 1)]
-            # gradients stay pending in the per-block sums until the end of the sweep, so every
-            # schedule sums them in the same (step) order
-            B.lbm_adjoint_many(self.ctx, self.model, self.omega, self.a_states, lam, None)
-            if len(self.a_states) % 2:
-                self.lam.reverse()
+            self._reverse(self.a_states)
             self.a_states, self.a_keep = [], []
 
     def _flush(self):
@@ -241,8 +250,9 @@ class _Run:
         self._flush_adjoints()
 
     # Fast paths: the sqrt(n) and store-all sweeps issue whole segments with two host calls
-    # (lbm_step_raw_many / lbm_adjoint_many); they run exactly the kernels, in exactly the order,
-    # that the generic action executor (used for "revolve") would.
+    # (lbm_step_raw_many / lbm_adjoint_many); they compute, bit for bit, what the generic action
+    # executor (used for "revolve") would: the same forward steps in the same order, and the same
+    # reverse steps, whose grouping into one- and two-step launches changes no value.
     def _two_step(self) -> bool:
         """Whether the context runs this model fused, two or three steps per launch (then pairs of
         forward steps go through lbm_step2_raw_many; the states written are the same bit for bit)."""
@@ -316,13 +326,8 @@ class _Run:
 
     def _backward_fast(self):
         n = self.nsteps
-        lam = self.lam
         if self.schedule == "store_all":
-            states = [self.saved[("s", t)].data_ptr() for t in range(n - 1, -1, -1)]
-            ptrs = [lam[k % 2].data_ptr() for k in range(n + 1)]
-            B.lbm_adjoint_many(self.ctx, self.model, self.omega, states, ptrs, None)
-            if n % 2:
-                lam.reverse()
+            self._reverse([self.saved[("s", t)].data_ptr() for t in range(n - 1, -1, -1)])
             return
         K = sqrt_interval(n)
         ring = [self._free_buffer() for _ in range(K - 1)]
@@ -332,11 +337,7 @@ class _Run:
             seg = [self.saved[("c", s0)]] + ring[:m - 1]
             if m > 1:
                 self._run_chain(seg, s0)
-            states = [b.data_ptr() for b in reversed(seg)]
-            ptrs = [lam[k % 2].data_ptr() for k in range(m + 1)]
-            B.lbm_adjoint_many(self.ctx, self.model, self.omega, states, ptrs, None)
-            if m % 2:
-                lam.reverse()
+            self._reverse([b.data_ptr() for b in reversed(seg)])
         self.pool.extend(ring)
         self.nbuf -= len(ring)
 
@@ -353,7 +354,7 @@ class _Run:
         self.final = self.cur
         self.refs[id(self.final)] = self.refs.get(id(self.final), 0) + 1  # keep it
         B.lbm_load_state(self.ctx, self.final.data_ptr(), self.nsteps)
-        self.lam = [torch.empty(self.abytes, dtype=torch.uint8, device=self.dev) for _ in range(2)]
+        self.lam = [torch.empty(self.abytes, dtype=torch.uint8, device=self.dev) for _ in range(3)]
         self.loss = B.lbm_adjoint_seed_velocity_l2(self.ctx, self.tx.data_ptr(), self.ty.data_ptr(),
                                                    self.lam[0].data_ptr())
         return self.loss

@@ -33,6 +33,7 @@ EXPORTS = (
     "lbm_batch_autotune", "lbm_batch_residency", "lbm_batch_destroy",
     "lbm_state_bytes", "lbm_adjoint_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_raw",
     "lbm_step_raw_many", "lbm_step2_raw_many", "lbm_adjoint_many", "lbm_adjoint_flush",
+    "lbm_set_adjoint_depth", "lbm_get_adjoint_depth",
     "lbm_adjoint_seed_velocity_l2", "lbm_adjoint_step", "lbm_eq_vjp",
     "lbm_lsa_jacobian", "lbm_lsa_eigenvalues", "lbm_lsa_radius", "lbm_lsa_dvbe_growth",
 )
@@ -113,6 +114,8 @@ def _declare(L: ctypes.CDLL):
                                     _ll]),
         "lbm_adjoint_many": (_i, [_vp, _i, _dp, ctypes.POINTER(_vp), _i, ctypes.POINTER(_vp), _vp]),
         "lbm_adjoint_flush": (_i, [_vp, _vp]),
+        "lbm_set_adjoint_depth": (_i, [_vp, _i]),
+        "lbm_get_adjoint_depth": (_i, [_vp, ctypes.POINTER(_i)]),
         "lbm_adjoint_seed_velocity_l2": (_i, [_vp, _vp, _vp, _vp, _dp]),
         "lbm_adjoint_step": (_i, [_vp, _i, _dp, _vp, _vp, _vp, _vp]),
         "lbm_eq_vjp": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -378,6 +381,16 @@ def lbm_adjoint_many(ctx: int, model: int, omega, states, lam, domega: int | Non
 
 def lbm_adjoint_flush(ctx: int, domega: int):
     _check(lib().lbm_adjoint_flush(ctx, domega), "lbm_adjoint_flush")
+
+
+def lbm_set_adjoint_depth(ctx: int, steps: int):
+    _check(lib().lbm_set_adjoint_depth(ctx, steps), "lbm_set_adjoint_depth")
+
+
+def lbm_get_adjoint_depth(ctx: int) -> int:
+    steps = ctypes.c_int(0)
+    _check(lib().lbm_get_adjoint_depth(ctx, ctypes.byref(steps)), "lbm_get_adjoint_depth")
+    return steps.value
 
 
 def lbm_adjoint_seed_velocity_l2(ctx: int, ux_t: int, uy_t: int, lam: int) -> float:

@@ -2,9 +2,10 @@
 //
 // One reverse step reads f_n (pull from the raw state, exactly as the forward step does),
 // lambda_{n+1} at x + xi_i (transpose of the streaming permutation) and writes lambda_n at x:
-// 27 stored values per node, no atomics.  The rate gradients are reduced per block in FP64,
-// accumulated per block over the steps of one call, and summed into the caller's accumulator
-// in a fixed order at the end of the call.
+// 27 stored values per node, no atomics.  Two reverse steps in one launch keep lambda_n in LDS:
+// 36 stored values per node and pair.  The rate gradients are reduced per strip in FP64,
+// accumulated per strip over the steps of a sweep, and summed into the caller's accumulator in a
+// fixed order at the end.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -20,18 +21,48 @@ using namespace lbm;
 
 namespace {
 
-// Every reverse step of a context uses this one launch shape, so the launches that feed one set
-// of rate-gradient slots (block b writes slot b) have the same blocks.  Two nodes per thread
-// halve the per-block gradient reductions; at 4096^2 that is 4-7% faster with 4-byte adjoint
-// values and 2% slower with 8-byte ones (one node per thread there).
-StepShape adjoint_shape(const lbm_ctx* ctx) {
-    return step_shape(ctx->nx, ctx->ny, ctx->prec == LBM_F64 ? 1 : 2, LBM_DEFAULT_XCD);
+// Every reverse step walks the grid in strips of 64 columns and AdjShape::hs rows, one
+// workgroup of kAdjWaves waves per strip (lane l takes column x0 + l), and the strip is the unit
+// of the rate-gradient sums: the workgroup of block b adds its strip's FP64 sum to slot b.  Wave w
+// takes rows ys + w, ys + w + kAdjWaves, ... of its strip in increasing order, in the one-step
+// and the two-step kernel alike, so both add up every step's terms of a slot in the same order and
+// the gradients do not depend on which reverse steps were paired in one launch.
+#ifndef LBM_ADJ_WAVES
+#define LBM_ADJ_WAVES 4
+#endif
+#ifndef LBM_ADJ_UNROLL
+#define LBM_ADJ_UNROLL 1
+#endif
+#ifndef LBM_ADJ_STRIPS
+#define LBM_ADJ_STRIPS 2048
+#endif
+#ifndef LBM_ADJ_MAX_ROWS
+#define LBM_ADJ_MAX_ROWS 64
+#endif
+#ifndef LBM_ADJ_XCD
+#define LBM_ADJ_XCD 0
+#endif
+constexpr int kAdjWaves = LBM_ADJ_WAVES;
+constexpr int kAdjRing = 8;  // rows per pass of the two-step kernel (a multiple of kAdjWaves)
+constexpr int kAdjUnroll = LBM_ADJ_UNROLL;  // rows per wave and iteration of the one-step kernel
+
+struct AdjShape {
+    int hs;           // strip rows, a multiple of kAdjRing
+    unsigned sx, nb;  // strips across, strips in all
+};
+
+AdjShape adjoint_shape(const lbm_ctx* ctx) {
+    AdjShape a;
+    a.sx = (unsigned)((ctx->nx + 63) / 64);
+    // about LBM_ADJ_STRIPS strips where the grid has them, 8 to LBM_ADJ_MAX_ROWS rows each
+    const long long target = (long long)ctx->ny * a.sx / LBM_ADJ_STRIPS;
+    const long long h = (target + kAdjRing / 2) / kAdjRing * kAdjRing;
+    a.hs = (int)(h < kAdjRing ? kAdjRing : (h > LBM_ADJ_MAX_ROWS ? LBM_ADJ_MAX_ROWS : h));
+    a.nb = a.sx * (unsigned)((ctx->ny + a.hs - 1) / a.hs);
+    return a;
 }
 
-unsigned adjoint_blocks(const lbm_ctx* ctx) {
-    const StepShape sh = adjoint_shape(ctx);
-    return sh.gx * sh.gy;
-}
+unsigned adjoint_blocks(const lbm_ctx* ctx) { return adjoint_shape(ctx).nb; }
 
 template <int PREC> struct AdjT;
 template <> struct AdjT<kF64> { using T = double; };
@@ -56,16 +87,28 @@ __device__ __forceinline__ void push_gather(const T* __restrict__ lam, long long
     mu[8] = R(*plane_at(lam, plane, 8, rm + xp));
 }
 
-// Per-block rate-gradient slots: block b adds (accumulate = 1) or writes (0) its FP64 block sum
-// to slot b.  A slot is touched by one block per launch and launches are stream-ordered, so no
-// atomics or fences are needed; one k_finalize_add per host call folds the slots into domega.
-__device__ __forceinline__ void block_accumulate(double (&v)[5], double* __restrict__ slots, int accumulate) {
-    __shared__ double tot[5];
-    block_sum<5>(v, tot);
+// Rate-gradient slots: block b adds (accumulate = 1) or writes (0) its strip's FP64 sums to slot
+// b, the first reverse step's before the second's (two reverse steps per launch: a, then b), as
+// two one-step launches would.  A slot is touched by one block per launch and launches are
+// stream-ordered, so no atomics or fences are needed; one k_finalize_add per host call folds the
+// slots into domega.
+template <bool TWO>
+__device__ __forceinline__ void slots_add(double (&a)[5], double (&b)[5], double* __restrict__ slots,
+                                          int accumulate) {
+    __shared__ double ta[5], tb[5];
+    block_sum<5>(a, ta);
     __syncthreads();
-    if (threadIdx.x == 0 && threadIdx.y == 0) {
+    if constexpr (TWO) {
+        block_sum<5>(b, tb);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
         double* p = slots + 5 * (size_t)blockIdx.x;
-        for (int k = 0; k < 5; ++k) p[k] = (accumulate ? p[k] : 0.0) + tot[k];
+        for (int k = 0; k < 5; ++k) {
+            double v = (accumulate ? p[k] : 0.0) + ta[k];
+            if constexpr (TWO) v += tb[k];
+            p[k] = v;
+        }
     }
 }
 
@@ -82,49 +125,174 @@ __global__ __launch_bounds__(256) void k_finalize_add(const double* __restrict__
         for (int k = 0; k < 5; ++k) out[k] += tot[k];
 }
 
-template <int MODEL, int PREC, int ROWS>
-__global__ __launch_bounds__(256) void k_adjoint_step(const typename Store<PREC>::S* __restrict__ state,
-                                                      const typename AdjT<PREC>::T* __restrict__ lam_next,
-                                                      typename AdjT<PREC>::T* __restrict__ lam, Geom g,
-                                                      Coef<typename Store<PREC>::R> c,
-                                                      Ref<typename Store<PREC>::R> ref, int N,
-                                                      double* __restrict__ slots, int accumulate,
-                                                      unsigned gx, unsigned nb, int xcd) {
+// One node of a reverse step: hb = lambda_n(x, y) = J_C(h)^T mu for the pulled state h of f_n and
+// mu_i = lambda_{n+1}(x + xi_i); when `count`, the node's rate-gradient terms are added to ws.
+template <int MODEL, int PREC>
+__device__ __forceinline__ void reverse_core(const typename Store<PREC>::R (&h)[9],
+                                             const typename Store<PREC>::R (&mu)[9],
+                                             const Coef<typename Store<PREC>::R>& c,
+                                             const Ref<typename Store<PREC>::R>& ref, int N,
+                                             typename Store<PREC>::R (&hb)[9], double (&ws)[5], bool count) {
     using R = typename Store<PREC>::R;
-    using T = typename AdjT<PREC>::T;
+    double rho_d;
+    const Macro<R> m = macro_of<typename Store<PREC>::S>(h, ref, rho_d);
+    R cb[7] = {R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
+    collide_adjoint<MODEL>(h, m, ref, c, N, mu, hb, cb);
+    if (count) {
+        double wn[5];
+        omega_adjoint(cb, wn);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) ws[k] += wn[k];
+    }
+}
+
+// The same node with f_n pulled from `state` and mu gathered from lam_next in memory.
+template <int MODEL, int PREC>
+__device__ __forceinline__ void reverse_node(const typename Store<PREC>::S* __restrict__ state,
+                                             const typename AdjT<PREC>::T* __restrict__ lam_next, const Geom& g,
+                                             int x, int y, const Coef<typename Store<PREC>::R>& c,
+                                             const Ref<typename Store<PREC>::R>& ref, int N,
+                                             typename Store<PREC>::R (&hb)[9], double (&ws)[5], bool count) {
+    using R = typename Store<PREC>::R;
+    const Nbr n = neighbours(x, y, g.nx, g.ny);
+    R h[9], mu[9];
+    pull_load(state, g.plane, n, h);
+    push_gather(lam_next, g.plane, n, mu);
+    reverse_core<MODEL, PREC>(h, mu, c, ref, N, hb, ws, count);
+}
+
+template <typename T, typename R>
+__device__ __forceinline__ void store_lam(T* __restrict__ lam, const Geom& g, int x, int y, const R (&hb)[9]) {
+    // lambda is read back only by the next reverse step, as a gather over the whole grid:
+    // streaming stores keep it from displacing reusable lines
+    const unsigned o = ((unsigned)y * (unsigned)g.nx + (unsigned)x) * (unsigned)sizeof(T);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) st<T>(plane_at(lam, g.plane, i, o), T(hb[i]));
+}
+
+// One reverse step (lambda_{n+1} -> lambda_n at state f_n) over one strip per workgroup.
+template <int MODEL, int PREC>
+__global__ __launch_bounds__(64 * kAdjWaves) void k_adjoint_strip1(
+    const typename Store<PREC>::S* __restrict__ state, const typename AdjT<PREC>::T* __restrict__ lam_next,
+    typename AdjT<PREC>::T* __restrict__ lam, Geom g, Coef<typename Store<PREC>::R> c,
+    Ref<typename Store<PREC>::R> ref, int N, double* __restrict__ slots, int accumulate, int hs, unsigned sx,
+    unsigned nb, int xcd) {
+    using R = typename Store<PREC>::R;
     unsigned bx, by;
-    tile_of_block(blockIdx.x, gx, nb, xcd, bx, by);
-    const int x = bx * blockDim.x + threadIdx.x;
-    const int y0 = by * blockDim.y * ROWS + threadIdx.y;
-    double wb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    tile_of_block(blockIdx.x, sx, nb, xcd, bx, by);
+    const int x = (int)bx * 64 + (int)(threadIdx.x & 63u);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int ys = (int)by * hs, ye = min(ys + hs, g.ny);
+    double ws[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (x < g.nx) {
+        for (int yb = ys + wave; yb < ye; yb += kAdjWaves * kAdjUnroll) {
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
-            const int y = y0 + r * (int)blockDim.y;
-            if (y < g.ny) {
-                const Nbr n = neighbours(x, y, g.nx, g.ny);
-                R h[9], mu[9], hb[9];
-                pull_load(state, g.plane, n, h);
-                push_gather(lam_next, g.plane, n, mu);
-                double rho_d;
-                const Macro<R> m = macro_of<typename Store<PREC>::S>(h, ref, rho_d);
-                R cb[7] = {R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
-                collide_adjoint<MODEL>(h, m, ref, c, N, mu, hb, cb);
-                const unsigned o = (n.r0 + (unsigned)x) * (unsigned)sizeof(T);
-                // lambda_n is read back only by the next reverse step, as a gather over the
-                // whole grid: streaming stores keep it from displacing reusable lines
-#pragma unroll
-                for (int i = 0; i < 9; ++i) st<T>(plane_at(lam, g.plane, i, o), T(hb[i]));
-                double wn[5];
-                omega_adjoint(cb, wn);
-#pragma unroll
-                for (int k = 0; k < 5; ++k) wb[k] += wn[k];
+            for (int u = 0; u < kAdjUnroll; ++u) {
+                const int y = yb + u * kAdjWaves;
+                if (y < ye) {
+                    R hb[9];
+                    reverse_node<MODEL, PREC>(state, lam_next, g, x, y, c, ref, N, hb, ws, true);
+                    store_lam(lam, g, x, y, hb);
+                }
             }
         }
     }
-    block_accumulate(wb, slots, accumulate);
+    slots_add<false>(ws, ws, slots, accumulate);
 }
 
+// Two reverse steps per pass over one strip per workgroup: lambda_{n+1} -> lambda_n at f_n (the
+// first, on the strip plus one halo row and column on each side, kept in an LDS ring of
+// kAdjRing + 2 rows of 66 columns) -> lambda_{n-1} at f_{n-1} (the second, gathered from the
+// ring, written to memory).  lambda_n never goes to memory: per node and pair of steps the
+// launch reads f_n, f_{n-1} and lambda_{n+1} and writes lambda_{n-1}, 18 s + 18 a bytes against
+// 2 (9 s + 18 a) for two one-step launches.  A pass computes the first step on rows yb + 1 ..
+// yb + kAdjRing and the second on rows yb .. yb + kAdjRing - 1, with a barrier after each.  The
+// ring holds the adjoint type, as memory would, and every node runs the arithmetic of
+// k_adjoint_strip1, so lambda_{n-1} and the gradient sums are bit-identical to two one-step
+// launches.  Wave kAdjWaves - 1 also takes the halo columns (two lanes per row).
+template <int MODEL, int PREC>
+__global__ __launch_bounds__(64 * kAdjWaves) void k_adjoint_strip2(
+    const typename Store<PREC>::S* __restrict__ state_n, const typename Store<PREC>::S* __restrict__ state_m,
+    const typename AdjT<PREC>::T* __restrict__ lam_next, typename AdjT<PREC>::T* __restrict__ lam, Geom g,
+    Coef<typename Store<PREC>::R> c, Ref<typename Store<PREC>::R> ref, int N, double* __restrict__ slots,
+    int accumulate, int hs, unsigned sx, unsigned nb, int xcd) {
+    using R = typename Store<PREC>::R;
+    using T = typename AdjT<PREC>::T;
+    constexpr int NR = kAdjRing + 2;
+    constexpr int KR = kAdjRing / kAdjWaves;
+    static_assert(kAdjRing % kAdjWaves == 0 && 2 * kAdjRing <= 64, "ring rows");
+    __shared__ T ring[9][NR][66];
+    unsigned bx, by;
+    tile_of_block(blockIdx.x, sx, nb, xcd, bx, by);
+    const int x0 = (int)bx * 64;
+    const int lane = (int)(threadIdx.x & 63u);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int ys = (int)by * hs, ye = min(ys + hs, g.ny);
+    const int w = min(64, g.nx - x0);
+    const bool in = lane < w;
+    const int x = x0 + lane;
+    // ring column 0 holds grid column x0 - 1, column 1 + l column x0 + l, column w + 1 x0 + w
+    const int xl = x0 == 0 ? g.nx - 1 : x0 - 1;
+    const int xr = x0 + w == g.nx ? 0 : x0 + w;
+    double wa[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, wb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    // first step at grid column xg and strip row r (ys - 1 <= r <= ye, wrapped here) into ring
+    // column cc
+    auto first = [&](int xg, int r, int cc, bool count) {
+        R hb[9];
+        const int yw = r < 0 ? r + g.ny : (r >= g.ny ? r - g.ny : r);
+        reverse_node<MODEL, PREC>(state_n, lam_next, g, xg, yw, c, ref, N, hb, wa, count);
+        const int s = (r - ys + 1) % NR;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) ring[i][s][cc] = T(hb[i]);
+    };
+    // the halo columns of rows r0 .. r1
+    auto halo = [&](int r0, int r1) {
+        if (wave == kAdjWaves - 1) {
+            const int r = r0 + (lane >> 1);
+            if (lane < 2 * kAdjRing && r <= r1) first((lane & 1) ? xr : xl, r, (lane & 1) ? w + 1 : 0, false);
+        }
+    };
+    // prologue: rows ys - 1 (halo) and ys (wave 0's first row)
+    if (in) {
+        if (wave == 0)
+            first(x, ys, lane + 1, true);
+        else if (wave == 1)
+            first(x, ys - 1, lane + 1, false);
+    }
+    halo(ys - 1, ys);
+    __syncthreads();
+    // wave w's first-step rows in a pass: yb + m0 + kAdjWaves k (the rows w mod kAdjWaves from ys)
+    const int m0 = (wave + kAdjWaves - 1) % kAdjWaves + 1;
+    for (int yb = ys; yb < ye; yb += kAdjRing) {
+        const int top = min(yb + kAdjRing, ye);  // first step: rows yb + 1 .. top (row ye: halo)
+        if (in) {
+#pragma unroll
+            for (int k = 0; k < KR; ++k) {
+                const int r = yb + m0 + kAdjWaves * k;
+                if (r <= top) first(x, r, lane + 1, r < ye);
+            }
+        }
+        halo(yb + 1, top);
+        __syncthreads();
+        if (in) {
+#pragma unroll
+            for (int k = 0; k < KR; ++k) {
+                const int y = yb + wave + kAdjWaves * k;
+                if (y < ye) {
+                    const int s0 = y - ys + 1;  // ring slot of row y, before wrapping
+                    R h[9], mu[9], hb[9];
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) mu[i] = R(ring[i][(s0 + cy(i)) % NR][lane + 1 + cx(i)]);
+                    pull_load(state_m, g.plane, neighbours(x, y, g.nx, g.ny), h);
+                    reverse_core<MODEL, PREC>(h, mu, c, ref, N, hb, wb, true);
+                    store_lam(lam, g, x, y, hb);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    slots_add<true>(wa, wb, slots, accumulate);
+}
 
 // Velocity of the current state in FP64 (pull).
 template <int PREC>
@@ -203,42 +371,41 @@ __global__ __launch_bounds__(256) void k_eq_vjp(Geom g, Ref<double> ref, int N, 
     duy[c] = mb.uy + mb.duy + m.rho * mb.jy;
 }
 
-template <int MODEL, int PREC, int ROWS>
-void launch_adj_r(lbm_ctx* ctx, const StepShape& sh, const double* w, const void* state, const void* lam_next,
+// One reverse step (state_m == NULL: lambda_{n+1} = lam_next -> lambda_n = lam at f_n = state_n)
+// or two (lam_next -> lambda_{n-1} = lam through f_n = state_n and f_{n-1} = state_m).
+template <int MODEL, int PREC>
+void launch_adj_t(lbm_ctx* ctx, const double* w, const void* state_n, const void* state_m, const void* lam_next,
                   void* lam, int accumulate) {
     using S = typename Store<PREC>::S;
     using R = typename Store<PREC>::R;
     using T = typename AdjT<PREC>::T;
-    const unsigned nb = sh.gx * sh.gy;
-    hipLaunchKernelGGL((k_adjoint_step<MODEL, PREC, ROWS>), dim3(nb), dim3(sh.bw, sh.bh), 0, ctx->stream,
-                       reinterpret_cast<const S*>(state), reinterpret_cast<const T*>(lam_next),
-                       reinterpret_cast<T*>(lam), ctx->geom(), make_coef<R>(w), ref_as<R>(ctx->ref),
-                       ctx->eq_order, ctx->d_wslots, accumulate, sh.gx, nb, sh.xcd);
-}
-
-template <int MODEL, int PREC>
-void launch_adj_t(lbm_ctx* ctx, const double* w, const void* state, const void* lam_next, void* lam,
-                  int accumulate) {
-    const StepShape sh = adjoint_shape(ctx);
-    if (sh.rows == 2)
-        launch_adj_r<MODEL, PREC, 2>(ctx, sh, w, state, lam_next, lam, accumulate);
+    const AdjShape a = adjoint_shape(ctx);
+    if (state_m)
+        hipLaunchKernelGGL((k_adjoint_strip2<MODEL, PREC>), dim3(a.nb), dim3(64 * kAdjWaves), 0, ctx->stream,
+                           reinterpret_cast<const S*>(state_n), reinterpret_cast<const S*>(state_m),
+                           reinterpret_cast<const T*>(lam_next), reinterpret_cast<T*>(lam), ctx->geom(),
+                           make_coef<R>(w), ref_as<R>(ctx->ref), ctx->eq_order, ctx->d_wslots, accumulate, a.hs,
+                           a.sx, a.nb, LBM_ADJ_XCD);
     else
-        launch_adj_r<MODEL, PREC, 1>(ctx, sh, w, state, lam_next, lam, accumulate);
+        hipLaunchKernelGGL((k_adjoint_strip1<MODEL, PREC>), dim3(a.nb), dim3(64 * kAdjWaves), 0, ctx->stream,
+                           reinterpret_cast<const S*>(state_n), reinterpret_cast<const T*>(lam_next),
+                           reinterpret_cast<T*>(lam), ctx->geom(), make_coef<R>(w), ref_as<R>(ctx->ref),
+                           ctx->eq_order, ctx->d_wslots, accumulate, a.hs, a.sx, a.nb, LBM_ADJ_XCD);
 }
 
 template <int PREC>
-void launch_adj_p(lbm_ctx* ctx, int model, const double* w, const void* state, const void* lam_next,
-                  void* lam, int accumulate) {
+void launch_adj_p(lbm_ctx* ctx, int model, const double* w, const void* sn, const void* sm, const void* lam_next,
+                  void* lam, int acc) {
     switch (model) {
-        case LBM_BGK: launch_adj_t<kBGK, PREC>(ctx, w, state, lam_next, lam, accumulate); break;
-        case LBM_RM: launch_adj_t<kRM, PREC>(ctx, w, state, lam_next, lam, accumulate); break;
-        case LBM_HM: launch_adj_t<kHM, PREC>(ctx, w, state, lam_next, lam, accumulate); break;
-        case LBM_CM: launch_adj_t<kCM, PREC>(ctx, w, state, lam_next, lam, accumulate); break;
-        case LBM_CHM: launch_adj_t<kCHM, PREC>(ctx, w, state, lam_next, lam, accumulate); break;
-        case LBM_K: launch_adj_t<kK, PREC>(ctx, w, state, lam_next, lam, accumulate); break;
-        case LBM_PR: launch_adj_t<kPR, PREC>(ctx, w, state, lam_next, lam, accumulate); break;
-        case LBM_RR: launch_adj_t<kRR, PREC>(ctx, w, state, lam_next, lam, accumulate); break;
-        default: launch_adj_t<kStreamOnly, PREC>(ctx, w, state, lam_next, lam, accumulate); break;
+        case LBM_BGK: launch_adj_t<kBGK, PREC>(ctx, w, sn, sm, lam_next, lam, acc); break;
+        case LBM_RM: launch_adj_t<kRM, PREC>(ctx, w, sn, sm, lam_next, lam, acc); break;
+        case LBM_HM: launch_adj_t<kHM, PREC>(ctx, w, sn, sm, lam_next, lam, acc); break;
+        case LBM_CM: launch_adj_t<kCM, PREC>(ctx, w, sn, sm, lam_next, lam, acc); break;
+        case LBM_CHM: launch_adj_t<kCHM, PREC>(ctx, w, sn, sm, lam_next, lam, acc); break;
+        case LBM_K: launch_adj_t<kK, PREC>(ctx, w, sn, sm, lam_next, lam, acc); break;
+        case LBM_PR: launch_adj_t<kPR, PREC>(ctx, w, sn, sm, lam_next, lam, acc); break;
+        case LBM_RR: launch_adj_t<kRR, PREC>(ctx, w, sn, sm, lam_next, lam, acc); break;
+        default: launch_adj_t<kStreamOnly, PREC>(ctx, w, sn, sm, lam_next, lam, acc); break;
     }
 }
 
@@ -347,18 +514,38 @@ int lbm_adjoint_many(lbm_ctx* ctx, int model, const double* omega, const void* c
         rc = check_hip(hipMalloc(&ctx->d_wslots, sizeof(double) * 5 * (size_t)adjoint_blocks(ctx)), "hipMalloc(slots)");
         if (rc != LBM_OK) return rc;
     }
-    for (int k = 0; k < count; ++k) {
+    for (int k = 0; k < count;) {
         const int acc = ctx->wslots_live ? 1 : 0;
+        // two reverse steps in one launch when the context asks for it and the pair's output
+        // buffer is not its input (other workgroups still gather lambda_{n+1} around their strips
+        // while one writes lambda_{n-1}); lam[k + 1] is then not written
+        const bool pair = ctx->adj_depth == 2 && k + 1 < count && lam[k + 2] != lam[k];
+        const void* sm = pair ? states[k + 1] : nullptr;
+        void* out = pair ? lam[k + 2] : lam[k + 1];
         switch (ctx->prec) {
-            case LBM_F64: launch_adj_p<kF64>(ctx, model, omega, states[k], lam[k], lam[k + 1], acc); break;
-            case LBM_F32_SHIFTED: launch_adj_p<kF32>(ctx, model, omega, states[k], lam[k], lam[k + 1], acc); break;
-            default: launch_adj_p<kF16>(ctx, model, omega, states[k], lam[k], lam[k + 1], acc); break;
+            case LBM_F64: launch_adj_p<kF64>(ctx, model, omega, states[k], sm, lam[k], out, acc); break;
+            case LBM_F32_SHIFTED: launch_adj_p<kF32>(ctx, model, omega, states[k], sm, lam[k], out, acc); break;
+            default: launch_adj_p<kF16>(ctx, model, omega, states[k], sm, lam[k], out, acc); break;
         }
         ctx->wslots_live = true;
+        k += pair ? 2 : 1;
     }
     rc = check_hip(hipGetLastError(), "adjoint kernel launch");
     if (rc != LBM_OK || !domega) return rc;
     return lbm_adjoint_flush(ctx, domega);
+}
+
+int lbm_set_adjoint_depth(lbm_ctx* ctx, int steps) {
+    if (!ctx) return set_error(LBM_ESTATE, "context is NULL");
+    if (steps != 1 && steps != 2) return set_error(LBM_EINVAL, "reverse steps per launch %d not in {1, 2}", steps);
+    ctx->adj_depth = steps;
+    return LBM_OK;
+}
+
+int lbm_get_adjoint_depth(lbm_ctx* ctx, int* steps) {
+    if (!ctx) return set_error(LBM_ESTATE, "context is NULL");
+    if (steps) *steps = ctx->adj_depth;
+    return LBM_OK;
 }
 
 int lbm_adjoint_flush(lbm_ctx* ctx, double* domega) {

@@ -319,6 +319,7 @@ struct lbm_ctx {
     double* d_static = nullptr;   // this device's address of the library's static reduction scratch
     double* d_wslots = nullptr;   // adjoint: per-block pending rate-gradient sums, 5 per block
     bool wslots_live = false;     // d_wslots holds pending sums
+    int adj_depth = 1;            // reverse steps per launch in lbm_adjoint_many (1 or 2)
 
     int rows[9] = {LBM_DEFAULT_ROWS, LBM_DEFAULT_ROWS, LBM_DEFAULT_ROWS, LBM_DEFAULT_ROWS,
                    LBM_DEFAULT_ROWS, LBM_DEFAULT_ROWS, LBM_DEFAULT_ROWS, LBM_DEFAULT_ROWS,
