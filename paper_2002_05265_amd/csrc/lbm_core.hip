@@ -12,6 +12,7 @@
 // pre-streamed backwards (stored_i(x) = f^eq_i(x + xi_i)) so that the first pull yields f^eq(x).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstdarg>
@@ -793,23 +794,33 @@ int lbm_init_shifted(lbm_ctx** out, int nx, int ny, int prec, int eq_order, doub
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             cus = 0;
     }
+    // the two-step shape of slot k: 128-column strips where they give at least kWideMinStrips
+    // strips (the launch takes them then), else 64-column strips of fstrip rows, ring of 8
+    auto two_step_pick = [&](int k) {
+        const int model = k < 8 ? k : LBM_STREAM_ONLY;  // slot 8: the pure pull
+        const FusionPick w = wide_default(model);
+        const bool wide = wide_strips(model, prec) && (long long)((nx + 2 * kStripW - 1) / (2 * kStripW)) *
+                                                              ((ny + w.strip - 1) / w.strip) >= kWideMinStrips;
+        return wide ? w : FusionPick{8, fstrip};
+    };
     if (deep)
         for (int k = 0; k < 9; ++k) {
             const FusionPick pick = deep_pick(k < 8 ? k : LBM_STREAM_ONLY, nx, ny, prec, cus);
             ctx->fuse_depth[k] = 3;
             ctx->fuse_ring[k] = pick.ring;
             ctx->fuse_strip[k] = pick.strip;
+            // a two-step launch on the three-step shape costs about what a three-step launch does
+            // (measured at 4096^2 FP32, BGK: 275 us on 80-row strips against 238 us on 16-row
+            // ones; at 512^2 8-row strips beat 16), so two steps left over run on 64-column strips
+            // of at most the two-step default height, ring of 8 rows
+            ctx->tail_ring[k] = 8;
+            ctx->tail_strip[k] = fstrip > 0 ? std::min(fstrip, pick.strip) : pick.strip;
         }
     else if (fstrip > 0)
         for (int k = 0; k < 9; ++k) {
-            // slot k is model k (slot 8: the pure pull); 128-column strips where they give at
-            // least kWideMinStrips strips (the launch takes them then)
-            const int model = k < 8 ? k : LBM_STREAM_ONLY;
-            const FusionPick w = wide_default(model);
-            const bool wide = wide_strips(model, prec) && (long long)((nx + 2 * kStripW - 1) / (2 * kStripW)) *
-                                                                  ((ny + w.strip - 1) / w.strip) >= kWideMinStrips;
-            ctx->fuse_ring[k] = wide ? w.ring : 8;
-            ctx->fuse_strip[k] = wide ? w.strip : fstrip;
+            const FusionPick t = two_step_pick(k);
+            ctx->fuse_ring[k] = t.ring;
+            ctx->fuse_strip[k] = t.strip;
         }
     int rc = check_hip(hipGetDevice(&ctx->device), "hipGetDevice");
     if (rc == LBM_OK) rc = scratch_address(ctx->device, &ctx->d_static);
@@ -847,12 +858,17 @@ int lbm_step(lbm_ctx* ctx, int model, const double* omega, int nsteps) {
             ctx->cur ^= 1;
             ctx->step += 3;
         }
-    if (ring > 0)
+    if (ring > 0) {
+        // two steps left over by three-step launches (or asked for alone): the tail shape, if any
+        const bool tail = ctx->fuse_depth[lbm_ctx::slot(model)] == 3 && ctx->tail_ring[lbm_ctx::slot(model)] > 0;
+        const int ring2 = tail ? ctx->tail_ring[lbm_ctx::slot(model)] : ring;
+        const int hs2 = tail ? ctx->tail_strip[lbm_ctx::slot(model)] : hs;
         for (; s + 2 <= nsteps; s += 2) {
-            LBM_DISPATCH_PREC(ctx->prec, launch_step2_p, ctx, model, omega, ring, hs, ctx->cur);
+            LBM_DISPATCH_PREC(ctx->prec, launch_step2_p, ctx, model, omega, ring2, hs2, ctx->cur);
             ctx->cur ^= 1;
             ctx->step += 2;
         }
+    }
     for (; s < nsteps; ++s) {
         LBM_DISPATCH_PREC(ctx->prec, launch_step_p, ctx, model, omega, sh, ctx->cur);
         ctx->cur ^= 1;
@@ -909,7 +925,10 @@ int lbm_step2_raw_many(lbm_ctx* ctx, int model, const double* omega, const void*
     int rc = validate_model(model, ctx->eq_order);
     if (rc == LBM_OK) rc = validate_omega(omega);
     if (rc != LBM_OK) return rc;
-    const int fs = ctx->fuse_strip[lbm_ctx::slot(model)];
+    // the raw pairs run with a ring of 8 rows: the tail strip height where the tail shape has that
+    // ring, else the model's strip height
+    const int slot = lbm_ctx::slot(model);
+    const int fs = ctx->tail_ring[slot] == 8 ? ctx->tail_strip[slot] : ctx->fuse_strip[slot];
     const int hs = fs > 0 ? fs : 16;
     for (int k = 0; k < count; ++k)
         LBM_DISPATCH_PREC(ctx->prec, launch_step2_raw_p, ctx, model, omega, hs, src[k], mid ? mid[k] : nullptr,
@@ -1008,6 +1027,8 @@ int lbm_set_fusion(lbm_ctx* ctx, int model, int ring_rows, int strip_rows) {
                          ring_rows);
     ctx->fuse_ring[lbm_ctx::slot(model)] = ring_rows;
     ctx->fuse_strip[lbm_ctx::slot(model)] = ring_rows ? strip_rows : 0;
+    ctx->tail_ring[lbm_ctx::slot(model)] = 0;  // an explicit shape also takes the leftover steps
+    ctx->tail_strip[lbm_ctx::slot(model)] = 0;
     return LBM_OK;
 }
 
@@ -1083,9 +1104,12 @@ int lbm_autotune(lbm_ctx* ctx, int model, const double* omega, int trials, int* 
                 best_xcd = xi;
             }
         }
+    const float best1 = best;  // the best single-step shape, per step
     // two-step shapes, per step
     const int fuse_c[8][2] = {{8, 8}, {8, 16}, {8, 40}, {8, 64}, {16, 16}, {4, 16}, {4, 20}, {4, 64}};
     int best_ring = 0, best_strip = 0, best_depth = 2;
+    float best2 = 0.f;  // the fastest two-step shape: the tail shape of three-step runs
+    int tail_ring = 0, tail_strip = 0;
     for (int k = 0; k < 8 && rc == LBM_OK; ++k) {
         const int ring = fuse_c[k][0], hs = fuse_c[k][1];
         const float ms = 0.5f * timed([&] { LBM_DISPATCH_PREC(ctx->prec, launch_step2_p, ctx, model, omega, ring, hs, ctx->cur); });
@@ -1093,6 +1117,11 @@ int lbm_autotune(lbm_ctx* ctx, int model, const double* omega, int trials, int* 
             best = ms;
             best_ring = ring;
             best_strip = hs;
+        }
+        if (rc == LBM_OK && (best2 == 0.f || ms < best2)) {
+            best2 = ms;
+            tail_ring = ring;
+            tail_strip = hs;
         }
     }
     // three-step shapes, per step (not for FP16 or grids below 2 x 2)
@@ -1119,6 +1148,11 @@ int lbm_autotune(lbm_ctx* ctx, int model, const double* omega, int trials, int* 
     ctx->fuse_ring[lbm_ctx::slot(model)] = best_ring;
     ctx->fuse_strip[lbm_ctx::slot(model)] = best_strip;
     ctx->fuse_depth[lbm_ctx::slot(model)] = best_depth;
+    // the fastest two-step shape takes the two steps left after three-step launches, if it beats
+    // one step per launch
+    const bool tail = best_depth == 3 && best_ring > 0 && tail_ring > 0 && best2 < best1;
+    ctx->tail_ring[lbm_ctx::slot(model)] = tail ? tail_ring : 0;
+    ctx->tail_strip[lbm_ctx::slot(model)] = tail ? tail_strip : 0;
     if (rows_out) *rows_out = best_rows;
     if (xcd_out) *xcd_out = best_xcd;
     if (us_per_step) *us_per_step = 1e3 * (double)best / trials;

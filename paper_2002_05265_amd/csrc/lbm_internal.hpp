@@ -331,6 +331,10 @@ struct lbm_ctx {
     int fuse_ring[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // two steps per pass: ring rows (0 = off)
     int fuse_strip[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // and strip height, per model
     int fuse_depth[9] = {2, 2, 2, 2, 2, 2, 2, 2, 2};  // steps per fused launch (2 or 3)
+    // the two-step launch that ends a run of three-step launches (two steps left): its own ring
+    // and strip height (0: those of fuse_ring / fuse_strip)
+    int tail_ring[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    int tail_strip[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 
     static int slot(int model) { return (model >= 0 && model < 8) ? model : 8; }
     lbm::StepShape shape_of(int model) const {

@@ -70,6 +70,28 @@ def test_three_steps_large_grid(gpu):
         assert ta == tb
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_default_three_steps_with_a_two_step_tail(gpu, prec):
+    # a new context on 768 x 512 runs three steps per launch; the two steps left over at the end of
+    # a call run as one two-step launch on the two-step default shape
+    nx, ny = 768, 512
+    rho, ux, uy = perturbed(nx, ny, 5)
+    omega = inputs.rates(1e-4, "REG")
+    for model in ("BGK", "K"):
+        a = Sim(rho, ux, uy, prec=prec, device=gpu)
+        b = Sim(rho, ux, uy, prec=prec, device=gpu)
+        assert b.fusion_depth(model) == 3
+        a.set_fusion(model, 0)
+        for n in (8, 5):
+            a.step(model, omega, n)
+            b.step(model, omega, n)
+        print(f"three steps with a tail {prec} {model} {nx}x{ny}", flush=True)
+        np.testing.assert_array_equal(a.state().cpu().numpy(), b.state().cpu().numpy())
+        assert a.status() == b.status()
+        a.close()
+        b.close()
+
+
 def test_three_steps_blowup_step(gpu):
     # zero rates: populations only stream.  Plant A (f_1 = 5, f_3 = -4 at one node) gives a
     # negative density one step later at the left neighbour, plant B (f_3 = -0.6 two nodes right
