@@ -835,8 +835,11 @@ def reverse_profile_summary(out_root: str, prec: str, n: int = 4096):
             f"(f_n pulled, lambda_n+1 gathered, lambda_n written); two per launch {n}*{n} * (18 s + 18 a) = "
             f"{alg['2']} B (f_n, f_n-1 and lambda_n+1 read, lambda_n-1 written; s = a = {sb} B). HBM bytes: "
             f"FETCH_SIZE x {fscale:.4f} + WRITE_SIZE x {wscale:.4f} (the same 1 GiB copy calibration as the "
-            "step-kernel counters). Flops: 64 lanes x (ADD + MUL + TRANS + 2 FMA) VALU instructions per "
-            "dispatch over the node updates it makes (the two-step kernel's include its halo).", "", *rows, "",
+            "step-kernel counters). The copy kernel, which reads whole lines, shows half its true bytes in "
+            "FETCH_SIZE; requests for parts of lines, which these gathers make at strip edges, need not be "
+            "undercounted the same way, so here the scaled figure is an upper bound. Flops: 64 lanes x (ADD + MUL + TRANS + 2 FMA) "
+            "VALU instructions per dispatch over the node updates it makes (the two-step kernel's include "
+            "its halo).", "", *rows, "",
             "```json", json.dumps(blob, indent=1), "```", ""]
     with open(os.path.join(PROFILE_DIR, f"adjoint_reverse_{prec}_dsl4096.md"), "w") as fh:
         fh.write("\n".join(text))
