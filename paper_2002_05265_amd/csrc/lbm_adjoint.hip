@@ -67,11 +67,8 @@ AdjShape adjoint_shape(const lbm_ctx* ctx) {
 
 unsigned adjoint_blocks(const lbm_ctx* ctx) { return adjoint_shape(ctx).nb; }
 
-// Strip (bx, by) of block b.  With G > 0 the strips are ordered by groups of G adjacent strip
-// columns (group-major, then row-major inside a group) and that order is dealt to the XCDs in
-// contiguous bands (the hardware hands block b to XCD b mod 8): each XCD walks whole column
-// groups from top to bottom, so neighbouring strips run at the same time on one XCD and find the
-// edge lines they share in its L2, while the XCDs together still sweep the same rows.  Measured at
+// Strip (bx, by) of block b: in FP32 and FP16 by groups of LBM_ADJ_GROUP strip columns
+// (strip_of_block_grouped), so that neighbouring strips share their edge lines in one L2.  Measured at
 // 4096^2: FP32 two reverse steps per launch 5% faster with G = 16 than in hardware order (G = 8:
 // 4%; 4 and 2: 12-24% slower), FP64 2-6% slower, so FP64 keeps the hardware order (G = 0, or
 // tile_of_block's bands when xcd is set).
@@ -79,14 +76,7 @@ template <int PREC>
 __device__ __forceinline__ void strip_of_block(unsigned b, unsigned sx, unsigned nb, int xcd, unsigned& bx,
                                                unsigned& by) {
     if constexpr (PREC != kF64 && LBM_ADJ_GROUP > 0) {
-        constexpr unsigned G = LBM_ADJ_GROUP;
-        const unsigned per = nb >> 3, rem = nb & 7u, k = b & 7u, j = b >> 3;
-        const unsigned t = k * per + (k < rem ? k : rem) + j;  // position in group-major order
-        const unsigned sy = nb / sx;
-        const unsigned g = t / (G * sy), r = t - g * (G * sy);
-        const unsigned gw = min(G, sx - g * G);
-        by = r / gw;
-        bx = g * G + (r - by * gw);
+        strip_of_block_grouped(b, sx, nb, LBM_ADJ_GROUP, bx, by);
     } else {
         tile_of_block(b, sx, nb, xcd, bx, by);
     }

@@ -296,11 +296,16 @@ __global__ __launch_bounds__(64 * step3_waves<RING>()) void k_step3(const typena
     using R = typename Store<PREC>::R;
     __shared__ S ring1[9][RING + 2][W + 4];
     __shared__ S ring2[9][RING + 2][W + 2];
-    // FP32: strips dealt to the XCDs in contiguous bands, so neighbouring strips share their edge
-    // lines in one L2 (measured traffic 1.05x the algorithmic bytes against 1.57x in hardware
-    // order, +2-3%); FP64, bound by latency, measured 2% slower so and keeps the hardware order
+    // FP32: strips dealt to the XCDs by groups of 16 strip columns, so that neighbouring strips
+    // share their edge lines in one L2 (in hardware order the traffic was 1.57x the algorithmic
+    // bytes; bands of whole strip rows: 1.05x and 2-3% faster; column groups of 16 another 1-4%
+    // over bands, groups of 8 and 32 slightly less); FP64, bound by latency, measured 2% slower in
+    // bands and keeps the hardware order
     unsigned sx, sy;
-    tile_of_block(blockIdx.x, gsx, gridDim.x, PREC == kF32 ? 1 : 0, sx, sy);
+    if constexpr (PREC == kF32)
+        strip_of_block_grouped(blockIdx.x, gsx, gridDim.x, 16, sx, sy);
+    else
+        tile_of_block(blockIdx.x, gsx, gridDim.x, 0, sx, sy);
     const int x0 = (int)sx * W;
     const int ys = (int)sy * hs;
     strip_three_steps<RING, W, false, true, step3_waves<RING>()>(

@@ -152,6 +152,22 @@ __device__ __forceinline__ void tile_of_block(unsigned b, unsigned gx, unsigned 
     bx = b - by * gx;
 }
 
+// Strip (bx, by) of block b of a launch over nb = sx * sy strips, the strips taken in groups of G
+// adjacent strip columns (group-major, row-major inside a group) and that order dealt to the XCDs
+// in contiguous bands (the hardware hands block b to XCD b mod 8): each XCD walks whole column
+// groups from top to bottom, so neighbouring strips run at the same time on one XCD and share the
+// lines at their common edge in its L2, while the XCDs together sweep the same rows of the grid.
+__device__ __forceinline__ void strip_of_block_grouped(unsigned b, unsigned sx, unsigned nb, unsigned G,
+                                                       unsigned& bx, unsigned& by) {
+    const unsigned per = nb >> 3, rem = nb & 7u, k = b & 7u, j = b >> 3;
+    const unsigned t = k * per + (k < rem ? k : rem) + j;  // position in group-major order
+    const unsigned sy = nb / sx;
+    const unsigned g = t / (G * sy), r = t - g * (G * sy);
+    const unsigned gw = min(G, sx - g * G);
+    by = r / gw;
+    bx = g * G + (r - by * gw);
+}
+
 // Store value i of node (x, y) where the next pull of node (x, y) reads it, i.e. at node
 // (x, y) - xi_i: the buffer then holds the state pre-streamed backwards by one step.
 template <typename S, typename R>
