@@ -70,6 +70,16 @@ int lbm_step_raw_many(lbm_ctx* ctx, int model, const double* omega, const void* 
 int lbm_step2_raw_many(lbm_ctx* ctx, int model, const double* omega, const void* const* src,
                        void* const* mid, void* const* dst, int count, long long step0);
 
+/* count (>= 0) triples of raw steps in one call, in order, each as one launch of the three-step
+ * kernel on the model's three-step shape: triple k reads src[k] (state step0 + 3k) and writes dst[k]
+ * (state step0 + 3k + 3); the two states between are not written.  The states written are
+ * bit-identical to those of three lbm_step_raw calls.  src and dst are host arrays of device
+ * pointers, src[k] != dst[k].  LBM_EUNSUPPORTED unless the context runs the model three steps per
+ * launch (lbm_set_fusion_depth 3 with a ring of 4 or 8 rows, the default on large FP32 and FP64
+ * grids). */
+int lbm_step3_raw_many(lbm_ctx* ctx, int model, const double* omega, const void* const* src,
+                       void* const* dst, int count, long long step0);
+
 /* Seed of the velocity loss L = || u(f) - u_target ||_2 (sum over nodes and both
  * components) for the current state f:
  *   ux_t, uy_t  device, nx*ny FP64 [y][x]: the target velocity

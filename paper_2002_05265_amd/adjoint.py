@@ -258,16 +258,24 @@ class _Run:
         forward steps go through lbm_step2_raw_many; the states written are the same bit for bit)."""
         return B.lbm_get_fusion(self.ctx, self.model)[0] > 0
 
+    def _three_step(self) -> bool:
+        """Whether the context runs this model three steps per launch (then three forward steps
+        whose first two states are not kept go through lbm_step3_raw_many)."""
+        return (B.lbm_get_fusion_depth(self.ctx, self.model) == 3 and
+                B.lbm_get_fusion(self.ctx, self.model)[0] in (4, 8))
+
     def _run_chain(self, chain, step0: int):
         """Advance along chain = [b_0, b_1, ..., b_m] (b_t receives state step0 + t; None = not
-        kept, a scratch buffer is used): pairs of steps as one two-step launch each (writing the
-        state between them only when it is kept), the rest one step per launch.  Returns the
-        buffer holding the last state."""
-        ops = []  # ("1", src, dst, step) or ("2", src, mid, dst, step)
+        kept, a scratch buffer is used): three steps as one three-step launch where the two states
+        between are not kept, pairs of steps as one two-step launch (writing the state between
+        them only when it is kept), the rest one step per launch.  Returns the buffer holding the
+        last state."""
+        ops = []  # ("1", src, dst, step), ("2", src, mid, dst, step) or ("3", src, dst, step)
         cur = chain[0]
         scratch = self._scratch
         t, m = 1, len(chain) - 1
         pairs = self._two_step()
+        triples = self._three_step()
 
         def place(b):
             if b is not None:
@@ -275,7 +283,11 @@ class _Run:
             return scratch[0] if cur is not scratch[0] else scratch[1]
 
         while t <= m:
-            if pairs and t + 1 <= m:
+            if triples and t + 2 <= m and chain[t] is None and chain[t + 1] is None:
+                dst = place(chain[t + 2])
+                ops.append(("3", cur, dst, step0 + t - 1))
+                cur, t = dst, t + 3
+            elif pairs and t + 1 <= m:
                 dst = place(chain[t + 1])
                 ops.append(("2", cur, chain[t], dst, step0 + t - 1))
                 cur, t = dst, t + 2
@@ -293,6 +305,9 @@ class _Run:
             if run[0][0] == "1":
                 B.lbm_step_raw_many(self.ctx, self.model, self.omega, [o[1].data_ptr() for o in run],
                                     [o[2].data_ptr() for o in run], run[0][3])
+            elif run[0][0] == "3":
+                B.lbm_step3_raw_many(self.ctx, self.model, self.omega, [o[1].data_ptr() for o in run],
+                                     [o[2].data_ptr() for o in run], run[0][3])
             else:
                 B.lbm_step2_raw_many(self.ctx, self.model, self.omega, [o[1].data_ptr() for o in run],
                                      [0 if o[2] is None else o[2].data_ptr() for o in run],

@@ -32,7 +32,7 @@ EXPORTS = (
     "lbm_batch_set_fusion_depth", "lbm_batch_get_fusion_depth",
     "lbm_batch_autotune", "lbm_batch_residency", "lbm_batch_destroy",
     "lbm_state_bytes", "lbm_adjoint_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_raw",
-    "lbm_step_raw_many", "lbm_step2_raw_many", "lbm_adjoint_many", "lbm_adjoint_flush",
+    "lbm_step_raw_many", "lbm_step2_raw_many", "lbm_step3_raw_many", "lbm_adjoint_many", "lbm_adjoint_flush",
     "lbm_set_adjoint_depth", "lbm_get_adjoint_depth",
     "lbm_adjoint_seed_velocity_l2", "lbm_adjoint_step", "lbm_eq_vjp",
     "lbm_lsa_jacobian", "lbm_lsa_eigenvalues", "lbm_lsa_radius", "lbm_lsa_dvbe_growth",
@@ -112,6 +112,7 @@ def _declare(L: ctypes.CDLL):
         "lbm_step_raw_many": (_i, [_vp, _i, _dp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i, _ll]),
         "lbm_step2_raw_many": (_i, [_vp, _i, _dp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i,
                                     _ll]),
+        "lbm_step3_raw_many": (_i, [_vp, _i, _dp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i, _ll]),
         "lbm_adjoint_many": (_i, [_vp, _i, _dp, ctypes.POINTER(_vp), _i, ctypes.POINTER(_vp), _vp]),
         "lbm_adjoint_flush": (_i, [_vp, _vp]),
         "lbm_set_adjoint_depth": (_i, [_vp, _i]),
@@ -372,6 +373,12 @@ def lbm_step2_raw_many(ctx: int, model: int, omega, src, mid, dst, step0: int):
     mids = None if mid is None else _ptrs([m or 0 for m in mid])
     _check(lib().lbm_step2_raw_many(ctx, model, _omega(omega), _ptrs(src), mids, _ptrs(dst), len(src), step0),
            "lbm_step2_raw_many")
+
+
+def lbm_step3_raw_many(ctx: int, model: int, omega, src, dst, step0: int):
+    """Triples of raw steps src[k] -> dst[k] (the two states between are not written)."""
+    _check(lib().lbm_step3_raw_many(ctx, model, _omega(omega), _ptrs(src), _ptrs(dst), len(src), step0),
+           "lbm_step3_raw_many")
 
 
 def lbm_adjoint_many(ctx: int, model: int, omega, states, lam, domega: int | None):

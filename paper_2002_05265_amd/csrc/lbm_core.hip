@@ -576,65 +576,68 @@ void launch_step2_p(lbm_ctx* ctx, int model, const double* w, int ring, int hs, 
     }
 }
 
-// One launch of k_step3 (three steps) with strips of W columns from copy src_copy to the other.
+// One launch of k_step3 (three steps, steps step .. step + 2) with strips of W columns from the
+// state src to dst.
 template <int MODEL, int PREC, int RING, int W>
-void launch_step3_w(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int hs, int src_copy) {
+void launch_step3_w(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int hs, const void* src, void* dst,
+                    int step) {
     using S = typename Store<PREC>::S;
     const unsigned gsx = (unsigned)((ctx->nx + W - 1) / W);
     const unsigned gsy = (unsigned)((ctx->ny + hs - 1) / hs);
     hipLaunchKernelGGL((k_step3<MODEL, PREC, RING, W>), dim3(gsx * gsy), dim3(64 * step3_waves<RING>()), 0, ctx->stream,
-                       reinterpret_cast<const S*>(ctx->copy(src_copy)), reinterpret_cast<S*>(ctx->copy(src_copy ^ 1)),
-                       ctx->geom(), c, ref_as<typename Store<PREC>::R>(ctx->ref), ctx->eq_order, (int)ctx->step,
-                       ctx->d_flag, gsx, hs);
+                       reinterpret_cast<const S*>(src), reinterpret_cast<S*>(dst), ctx->geom(), c,
+                       ref_as<typename Store<PREC>::R>(ctx->ref), ctx->eq_order, step, ctx->d_flag, gsx, hs);
 }
 
 // FP64 three-step strips with a ring of 4 rows: 48 columns, the halo columns inside the wave (no halo
 // passes, 44 KiB of LDS: three workgroups per CU), each row segment three whole 128-byte lines.
 constexpr int kNarrowW = 48;
 
-// One launch of k_step3n (FP64 narrow strips) from copy src_copy to the other.
+// One launch of k_step3n (FP64 narrow strips) from the state src to dst.
 template <int MODEL, int PREC, int RING, int WP>
-void launch_step3n_w(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int hs, int src_copy) {
+void launch_step3n_w(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int hs, const void* src, void* dst,
+                     int step) {
     using S = typename Store<PREC>::S;
     const unsigned gsx = (unsigned)((ctx->nx + WP - 1) / WP);
     const unsigned gsy = (unsigned)((ctx->ny + hs - 1) / hs);
     hipLaunchKernelGGL((k_step3n<MODEL, PREC, RING, WP>), dim3(gsx * gsy), dim3(64 * step3_waves<RING>()), 0, ctx->stream,
-                       reinterpret_cast<const S*>(ctx->copy(src_copy)), reinterpret_cast<S*>(ctx->copy(src_copy ^ 1)),
-                       ctx->geom(), c, ref_as<typename Store<PREC>::R>(ctx->ref), ctx->eq_order, (int)ctx->step,
-                       ctx->d_flag, gsx, hs);
+                       reinterpret_cast<const S*>(src), reinterpret_cast<S*>(dst), ctx->geom(), c,
+                       ref_as<typename Store<PREC>::R>(ctx->ref), ctx->eq_order, step, ctx->d_flag, gsx, hs);
 }
 
 // Three steps per launch: FP32 on 64-column strips (the two rings of 128-column strips take 56 KiB
 // of LDS with a ring of 4 rows, two workgroups per CU, and measured 10-25% slower), FP64 on 48-column
 // narrow strips with either ring.
 template <int MODEL, int PREC>
-void launch_step3_t(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int ring, int hs, int src_copy) {
+void launch_step3_t(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int ring, int hs, const void* src,
+                    void* dst, int step) {
     if constexpr (PREC == kF64) {
         if (ring == 4)
-            launch_step3n_w<MODEL, PREC, 4, kNarrowW>(ctx, c, hs, src_copy);
+            launch_step3n_w<MODEL, PREC, 4, kNarrowW>(ctx, c, hs, src, dst, step);
         else
-            launch_step3n_w<MODEL, PREC, 8, kNarrowW>(ctx, c, hs, src_copy);
+            launch_step3n_w<MODEL, PREC, 8, kNarrowW>(ctx, c, hs, src, dst, step);
     } else if constexpr (PREC == kF32) {
         if (ring == 4)
-            launch_step3_w<MODEL, PREC, 4, kStripW>(ctx, c, hs, src_copy);
+            launch_step3_w<MODEL, PREC, 4, kStripW>(ctx, c, hs, src, dst, step);
         else
-            launch_step3_w<MODEL, PREC, 8, kStripW>(ctx, c, hs, src_copy);
+            launch_step3_w<MODEL, PREC, 8, kStripW>(ctx, c, hs, src, dst, step);
     }
 }
 
 template <int PREC>
-void launch_step3_p(lbm_ctx* ctx, int model, const double* w, int ring, int hs, int src_copy) {
+void launch_step3_p(lbm_ctx* ctx, int model, const double* w, int ring, int hs, const void* src, void* dst,
+                    int step) {
     const Coef<typename Store<PREC>::R> c = make_coef<typename Store<PREC>::R>(w);
     switch (model) {
-        case LBM_BGK: launch_step3_t<kBGK, PREC>(ctx, c, ring, hs, src_copy); break;
-        case LBM_RM: launch_step3_t<kRM, PREC>(ctx, c, ring, hs, src_copy); break;
-        case LBM_HM: launch_step3_t<kHM, PREC>(ctx, c, ring, hs, src_copy); break;
-        case LBM_CM: launch_step3_t<kCM, PREC>(ctx, c, ring, hs, src_copy); break;
-        case LBM_CHM: launch_step3_t<kCHM, PREC>(ctx, c, ring, hs, src_copy); break;
-        case LBM_K: launch_step3_t<kK, PREC>(ctx, c, ring, hs, src_copy); break;
-        case LBM_PR: launch_step3_t<kPR, PREC>(ctx, c, ring, hs, src_copy); break;
-        case LBM_RR: launch_step3_t<kRR, PREC>(ctx, c, ring, hs, src_copy); break;
-        default: launch_step3_t<kStreamOnly, PREC>(ctx, c, ring, hs, src_copy); break;
+        case LBM_BGK: launch_step3_t<kBGK, PREC>(ctx, c, ring, hs, src, dst, step); break;
+        case LBM_RM: launch_step3_t<kRM, PREC>(ctx, c, ring, hs, src, dst, step); break;
+        case LBM_HM: launch_step3_t<kHM, PREC>(ctx, c, ring, hs, src, dst, step); break;
+        case LBM_CM: launch_step3_t<kCM, PREC>(ctx, c, ring, hs, src, dst, step); break;
+        case LBM_CHM: launch_step3_t<kCHM, PREC>(ctx, c, ring, hs, src, dst, step); break;
+        case LBM_K: launch_step3_t<kK, PREC>(ctx, c, ring, hs, src, dst, step); break;
+        case LBM_PR: launch_step3_t<kPR, PREC>(ctx, c, ring, hs, src, dst, step); break;
+        case LBM_RR: launch_step3_t<kRR, PREC>(ctx, c, ring, hs, src, dst, step); break;
+        default: launch_step3_t<kStreamOnly, PREC>(ctx, c, ring, hs, src, dst, step); break;
     }
 }
 
@@ -859,7 +862,8 @@ int lbm_step(lbm_ctx* ctx, int model, const double* omega, int nsteps) {
     int s = 0;
     if ((ring == 4 || ring == 8) && ctx->fuse_depth[lbm_ctx::slot(model)] == 3)
         for (; s + 3 <= nsteps; s += 3) {
-            LBM_DISPATCH_PREC(ctx->prec, launch_step3_p, ctx, model, omega, ring, hs, ctx->cur);
+            LBM_DISPATCH_PREC(ctx->prec, launch_step3_p, ctx, model, omega, ring, hs, ctx->copy(ctx->cur),
+                              ctx->copy(ctx->cur ^ 1), (int)ctx->step);
             ctx->cur ^= 1;
             ctx->step += 3;
         }
@@ -939,6 +943,28 @@ int lbm_step2_raw_many(lbm_ctx* ctx, int model, const double* omega, const void*
         LBM_DISPATCH_PREC(ctx->prec, launch_step2_raw_p, ctx, model, omega, hs, src[k], mid ? mid[k] : nullptr,
                           dst[k], (int)(step0 + 2LL * k));
     return check_hip(hipGetLastError(), "raw two-step kernel launch");
+}
+
+int lbm_step3_raw_many(lbm_ctx* ctx, int model, const double* omega, const void* const* src, void* const* dst,
+                       int count, long long step0) {
+    if (!ctx) return set_error(LBM_ESTATE, "context is NULL");
+    if (count < 0) return set_error(LBM_EINVAL, "count %d < 0", count);
+    if (count == 0) return LBM_OK;
+    if (!src || !dst) return set_error(LBM_EINVAL, "NULL pointer array");
+    if (step0 < 0 || step0 + 3LL * count >= INT_MAX) return set_error(LBM_EINVAL, "step %lld out of range", step0);
+    for (int k = 0; k < count; ++k)
+        if (!src[k] || !dst[k] || src[k] == dst[k]) return set_error(LBM_EINVAL, "bad state pointer at triple %d", k);
+    int rc = validate_model(model, ctx->eq_order);
+    if (rc == LBM_OK) rc = validate_omega(omega);
+    if (rc != LBM_OK) return rc;
+    const int slot = lbm_ctx::slot(model);
+    const int ring = ctx->fuse_ring[slot], hs = ctx->fuse_strip[slot];
+    if (ctx->fuse_depth[slot] != 3 || (ring != 4 && ring != 8))
+        return set_error(LBM_EUNSUPPORTED, "model %d does not take three steps per launch on this context", model);
+    for (int k = 0; k < count; ++k)
+        LBM_DISPATCH_PREC(ctx->prec, launch_step3_p, ctx, model, omega, ring, hs, src[k], dst[k],
+                          (int)(step0 + 3LL * k));
+    return check_hip(hipGetLastError(), "raw three-step kernel launch");
 }
 
 int lbm_moments(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* totals) {
@@ -1133,7 +1159,10 @@ int lbm_autotune(lbm_ctx* ctx, int model, const double* omega, int trials, int* 
     const int deep_c[10][2] = {{4, 8}, {4, 16}, {4, 24}, {4, 32}, {4, 40}, {4, 48}, {4, 64}, {4, 80}, {8, 40}, {8, 64}};
     for (int k = 0; k < 10 && rc == LBM_OK && ctx->prec != LBM_F16_SHIFTED && ctx->nx >= 2 && ctx->ny >= 2; ++k) {
         const int ring = deep_c[k][0], hs = deep_c[k][1];
-        const float ms = timed([&] { LBM_DISPATCH_PREC(ctx->prec, launch_step3_p, ctx, model, omega, ring, hs, ctx->cur); }) / 3.f;
+        const float ms = timed([&] {
+            LBM_DISPATCH_PREC(ctx->prec, launch_step3_p, ctx, model, omega, ring, hs, ctx->copy(ctx->cur),
+                              ctx->copy(ctx->cur ^ 1), (int)ctx->step);
+        }) / 3.f;
         if (rc == LBM_OK && ms < best) {
             best = ms;
             best_ring = ring;

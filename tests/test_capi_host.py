@@ -69,7 +69,8 @@ def test_null_context_errors(B):
     with pytest.raises(B.LbmError) as e:
         B.lbm_moments_noalloc(0, None, None, None, None)
     assert e.value.code == -4
-    for call in (lambda: B.lbm_set_adjoint_depth(0, 2), lambda: B.lbm_get_adjoint_depth(0)):
+    for call in (lambda: B.lbm_set_adjoint_depth(0, 2), lambda: B.lbm_get_adjoint_depth(0),
+                 lambda: B.lbm_step3_raw_many(0, B.LBM_BGK, [1.0] * 5, [1], [2], 0)):
         with pytest.raises(B.LbmError) as e:
             call()
         assert e.value.code == -4

@@ -196,8 +196,9 @@ def c5_loss(gpu, omega, steps=2000):
 @pytest.mark.parametrize("name", ["CM", "RR"])
 def test_two_step_launches_give_identical_gradients(gpu, name):
     """The checkpointed sweeps with pairs of forward steps as two-step launches (lbm_step2_raw_many,
-    with and without the state between them) give the same loss and gradients bit for bit as one
-    step per launch, for the sqrt(n) and store-all schedules and an odd step count."""
+    with and without the state between them) and triples as three-step launches
+    (lbm_step3_raw_many) give the same loss and gradients bit for bit as one step per launch, for
+    the sqrt(n) and store-all schedules and an odd step count."""
     from paper_2002_05265_amd import binding as B
     from paper_2002_05265_amd.adjoint import _Run
 
@@ -206,19 +207,24 @@ def test_two_step_launches_give_identical_gradients(gpu, name):
     omega = [1.99, 1.7, 1.3, 1.1, 0.9]
     out = {}
     for schedule in ("sqrt", "store_all"):
-        for fused in (False, True):
+        # one step per launch; pairs (two-step launches); triples where the states between are not
+        # kept (three-step launches of the sqrt(n) forward sweep), pairs elsewhere
+        for mode in ("single", "pairs", "triples"):
             u0 = torch.tensor(np.stack([ux, uy]), device=gpu)
             run = _Run(u0, omega, torch.tensor(rho, device=gpu), torch.tensor(np.stack([tx, ty]), device=gpu), name,
                        steps, "f64", 4, schedule, 0, (0.0, 0.0))
-            B.lbm_set_fusion(run.ctx, inputs.MODEL_CODES[name], 8 if fused else 0, 16)
+            code = inputs.MODEL_CODES[name]
+            B.lbm_set_fusion(run.ctx, code, 0 if mode == "single" else 8, 16)
+            B.lbm_set_fusion_depth(run.ctx, code, 3 if mode == "triples" else 2)
+            assert run._three_step() == (mode == "triples")
             loss = run.forward()
             du, dw = run.backward()
-            out[(schedule, fused)] = (loss, du.cpu().numpy(), dw.cpu().numpy(), run.steps_run)
+            out[(schedule, mode)] = (loss, du.cpu().numpy(), dw.cpu().numpy(), run.steps_run)
             run.close()
-    ref = out[("sqrt", False)]
+    ref = out[("sqrt", "single")]
     for key, val in out.items():
         print(key, "loss", val[0], "steps run", val[3], flush=True)
         assert val[0] == ref[0], key
         np.testing.assert_array_equal(val[1], ref[1])
         np.testing.assert_array_equal(val[2], ref[2])
-    assert out[("sqrt", True)][3] == out[("sqrt", False)][3]
+    assert out[("sqrt", "pairs")][3] == out[("sqrt", "single")][3] == out[("sqrt", "triples")][3]

@@ -92,6 +92,42 @@ def test_default_three_steps_with_a_two_step_tail(gpu, prec):
         b.close()
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_raw_triples_bit_identical(gpu, prec):
+    # lbm_step3_raw_many between caller buffers against single lbm_step_raw calls
+    import torch
+
+    import paper_2002_05265_amd.binding as B
+
+    nx, ny = 131, 70
+    rho, ux, uy = perturbed(nx, ny, 9)
+    omega = inputs.rates(1e-4, "REG")
+    for model in ("BGK", "K", "RR"):
+        code = inputs.MODEL_CODES[model]
+        s = Sim(rho, ux, uy, prec=prec, device=gpu)
+        s.set_fusion(model, 8, 16)
+        s.set_fusion_depth(model, 3)
+        nb = B.lbm_state_bytes(s.ctx)
+        # zero-filled, so the plane padding (never written) agrees between the two chains
+        a = [torch.zeros(nb, dtype=torch.uint8, device=gpu) for _ in range(7)]
+        t = [torch.zeros(nb, dtype=torch.uint8, device=gpu) for _ in range(2)]
+        B.lbm_save_state(s.ctx, a[0].data_ptr())
+        for k in range(6):
+            B.lbm_step_raw(s.ctx, code, omega, a[k].data_ptr(), a[k + 1].data_ptr(), 5 + k)
+        B.lbm_step3_raw_many(s.ctx, code, omega, [a[0].data_ptr(), t[0].data_ptr()],
+                             [t[0].data_ptr(), t[1].data_ptr()], 5)
+        torch.cuda.synchronize()
+        print(f"raw triples {prec} {model}", flush=True)
+        assert torch.equal(t[0], a[3]) and torch.equal(t[1], a[6]), (prec, model)
+        with pytest.raises(LbmError):  # source and destination must differ
+            B.lbm_step3_raw_many(s.ctx, code, omega, [a[0].data_ptr()], [a[0].data_ptr()], 0)
+        s.set_fusion_depth(model, 2)
+        with pytest.raises(LbmError) as e:  # the model no longer takes three steps per launch
+            B.lbm_step3_raw_many(s.ctx, code, omega, [a[0].data_ptr()], [t[0].data_ptr()], 0)
+        assert e.value.code == -2
+        s.close()
+
+
 def test_three_steps_blowup_step(gpu):
     # zero rates: populations only stream.  Plant A (f_1 = 5, f_3 = -4 at one node) gives a
     # negative density one step later at the left neighbour, plant B (f_3 = -0.6 two nodes right
