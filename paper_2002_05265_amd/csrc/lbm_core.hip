@@ -269,11 +269,16 @@ __global__ __launch_bounds__(256) void k_step2(const typename Store<PREC>::S* __
     using S = typename Store<PREC>::S;
     using R = typename Store<PREC>::R;
     __shared__ S ring[9][RING + 2][W + 2];
-    // FP16 (64-column strips, one 128-byte line per plane and row): strips dealt to the XCDs in
-    // contiguous bands, so neighbouring strips share their edge lines in one L2 (+2-7%); FP32 (128
-    // columns) and FP64 measured 2-6% slower so and keep the hardware order
+    // FP16 (64-column strips, one 128-byte line per plane and row): strips dealt to the XCDs by
+    // groups of 8 strip columns, so neighbouring strips share their edge lines in one L2 (bands of
+    // whole strip rows: +2-7% over the hardware order; column groups of 8 another 1-4%, of 16
+    // 0-2%); FP32 (128 columns) and FP64 measured 2-6% slower in bands and within 3% either way in
+    // column groups, and keep the hardware order
     unsigned sx, sy;
-    tile_of_block(blockIdx.x, gsx, gridDim.x, PREC == kF16 ? 1 : 0, sx, sy);
+    if constexpr (PREC == kF16)
+        strip_of_block_grouped(blockIdx.x, gsx, gridDim.x, 8, sx, sy);
+    else
+        tile_of_block(blockIdx.x, gsx, gridDim.x, 0, sx, sy);
     const int x0 = (int)sx * W;
     const int ys = (int)sy * hs;
     strip_two_steps<RING, W, false, true, MID>(
