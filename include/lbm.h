@@ -176,7 +176,7 @@ int lbm_set_launch(lbm_ctx* ctx, int model, int rows, int xcd);
  * and an FP32 or FP64 context starts every model with three steps per launch
  * (lbm_set_fusion_depth) when its 64-column strips of h rows number at least 512, h being
  * ceil(nx / 64) ny / sqrt(nx ny) rounded to a multiple of 8 and clamped to [8, 64] (n / 64 on an
- * n x n grid), and 80 instead of 64 in FP32: FP32 with ring_rows 8 and strip_rows h, raised in
+ * n x n grid), and 128 instead of 64 in FP32: FP32 with ring_rows 8 and strip_rows h, raised in
  * steps of 8 while the strips number more than one round of workgroups (3 per CU) but no more than
  * 1.5 rounds; FP64 with ring_rows 8 and strip_rows h (96 instead of 64), except BGK: ring_rows 4,
  * strip_rows h.

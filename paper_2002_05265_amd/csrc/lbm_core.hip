@@ -219,13 +219,15 @@ int deep_strip(int nx, int ny, int prec) {
     const double gsx = (double)((nx + kStripW - 1) / kStripW);
     const int h = 8 * (int)(gsx * ny / std::sqrt((double)nx * ny) / 8.0 + 0.5);
     const int hs = h < 8 ? 8 : (h > 64 ? 64 : h);
-    return (prec == LBM_F32_SHIFTED && hs == 64) ? 80 : hs;
+    return (prec == LBM_F32_SHIFTED && hs == 64) ? 128 : hs;
 }
 
 // Ring and strip height of a model's three-step launches on a new context (deep_strip's count of
 // 64-column strips is at least kDeepMinStrips).  Measured on MI355X (double shear layer, MLUPS):
 // - FP32: a ring of 8 rows (8 waves, 48 KiB of LDS, three workgroups per CU) for every model, at
-//   4096^2 with 80-row strips 174-191k against 170-185k with a ring of 4 (K / BGK), at 2048^2 152 /
+//   4096^2 with 80-row strips 174-191k against 170-185k with a ring of 4 (K / BGK); with the strips
+//   dealt to the XCDs by column groups, 128-row strips (where deep_strip reaches 64) run another
+//   1-2.5% faster than 80 (96, 112 and 160-256 rows slower) and are the default; at 2048^2 152 /
 //   166k against 145 / 160k, at 512^2 78 / 91k against 67 / 78k.  Where the strip count lies just
 //   above one round of workgroups (three per CU), up to 1.5 rounds, the strips are made taller until
 //   they fit one round: at 1024^2, 24-row strips 118 / 131k against 106 / 120k with 16 rows (a ring

@@ -120,7 +120,7 @@ def deep_strip(nx, ny, prec):
     gsx = (nx + 63) // 64
     h = 8 * int(gsx * ny / (nx * ny) ** 0.5 / 8.0 + 0.5)
     hs = min(max(h, 8), 64)
-    return 80 if (prec == "f32" and hs == 64) else hs
+    return 128 if (prec == "f32" and hs == 64) else hs
 
 
 def deep_pick(model, nx, ny, prec, cus):
@@ -170,7 +170,7 @@ def test_defaults_and_autotune(gpu):
             exp.append((2, (wr, ws) if wide else want))
         assert got == exp, (nx, ny, prec, got)
         if (nx, ny, prec) == (4096, 4096, "f32"):
-            assert exp[0] == (3, (8, 80))
+            assert exp[0] == (3, (8, 128))
         if (nx, ny, prec) == (4096, 4096, "f64"):
             assert exp[0] == (3, (4, 64)) and exp[5] == (3, (8, 96))
         if (nx, ny, prec) in ((256, 256, "f32"), (448, 512, "f64")):
