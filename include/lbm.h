@@ -204,8 +204,8 @@ int lbm_get_fusion_depth(lbm_ctx* ctx, int model, int* steps);
 /* Autotune the launches of `model` on this context's grid: every single-step shape
  * (rows in {1, 2, 4} x xcd in {0, 1}), the two-step shapes (ring_rows, strip_rows) in
  * {(8, 8), (8, 16), (8, 40), (8, 64), (16, 16), (4, 16), (4, 20), (4, 64)} and, except for FP16,
- * the three-step shapes {(4, 8), (4, 16), (4, 24), (4, 32), (4, 40), (4, 48), (4, 64), (4, 80),
- * (8, 40), (8, 64)} are timed with HIP
+ * the three-step shapes {(4, 8), (4, 16), (4, 32), (4, 64), (8, 8), (8, 16), (8, 24), (8, 32),
+ * (8, 64), (8, 80), (8, 96), (8, 128)} are timed with HIP
  * events over `trials` (>= 1) launches that recompute from the same input copy, so the state, the
  * step counter and the blow-up record are unchanged.  The fastest single-step shape is kept (it
  * also takes the last steps that do not fill a fused launch) and returned through rows_out /

@@ -1163,8 +1163,9 @@ int lbm_autotune(lbm_ctx* ctx, int model, const double* omega, int trials, int* 
         }
     }
     // three-step shapes, per step (not for FP16 or grids below 2 x 2)
-    const int deep_c[10][2] = {{4, 8}, {4, 16}, {4, 24}, {4, 32}, {4, 40}, {4, 48}, {4, 64}, {4, 80}, {8, 40}, {8, 64}};
-    for (int k = 0; k < 10 && rc == LBM_OK && ctx->prec != LBM_F16_SHIFTED && ctx->nx >= 2 && ctx->ny >= 2; ++k) {
+    const int deep_c[12][2] = {{4, 8}, {4, 16}, {4, 32}, {4, 64}, {8, 8}, {8, 16}, {8, 24}, {8, 32},
+                               {8, 64}, {8, 80}, {8, 96}, {8, 128}};
+    for (int k = 0; k < 12 && rc == LBM_OK && ctx->prec != LBM_F16_SHIFTED && ctx->nx >= 2 && ctx->ny >= 2; ++k) {
         const int ring = deep_c[k][0], hs = deep_c[k][1];
         const float ms = timed([&] {
             LBM_DISPATCH_PREC(ctx->prec, launch_step3_p, ctx, model, omega, ring, hs, ctx->copy(ctx->cur),

@@ -192,8 +192,8 @@ def test_defaults_and_autotune(gpu):
     if depth == 2:
         assert (ring, strip) in ((0, 0), (8, 8), (8, 16), (8, 40), (8, 64), (16, 16), (4, 16), (4, 20), (4, 64))
     else:
-        assert depth == 3 and (ring, strip) in ((4, 8), (4, 16), (4, 24), (4, 32), (4, 40), (4, 48), (4, 64),
-                                                (4, 80), (8, 40), (8, 64))
+        assert depth == 3 and (ring, strip) in ((4, 8), (4, 16), (4, 32), (4, 64), (8, 8), (8, 16), (8, 24),
+                                                (8, 32), (8, 64), (8, 80), (8, 96), (8, 128))
     np.testing.assert_array_equal(a.state().cpu().numpy(), before)
     assert a.status() == (3, -1)
     a.step("RR", omega, 9)
