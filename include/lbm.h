@@ -178,8 +178,7 @@ int lbm_set_launch(lbm_ctx* ctx, int model, int rows, int xcd);
  * ceil(nx / 64) ny / sqrt(nx ny) rounded to a multiple of 8 and clamped to [8, 64] (n / 64 on an
  * n x n grid), and 128 instead of 64 in FP32: FP32 with ring_rows 8 and strip_rows h, raised in
  * steps of 8 while the strips number more than one round of workgroups (3 per CU) but no more than
- * 1.5 rounds; FP64 with ring_rows 8 and strip_rows h (96 instead of 64), except BGK: ring_rows 4,
- * strip_rows h.
+ * 1.5 rounds; FP64 with ring_rows 8 and strip_rows h (128 instead of 64).
  * Results are bit-identical to single steps (same arithmetic per node; the LDS ring holds the
  * stored type).  Returns LBM_EINVAL for other values. */
 int lbm_set_fusion(lbm_ctx* ctx, int model, int ring_rows, int strip_rows);

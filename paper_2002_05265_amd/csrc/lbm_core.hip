@@ -233,14 +233,12 @@ int deep_strip(int nx, int ny, int prec) {
 //   they fit one round: at 1024^2, 24-row strips 118 / 131k against 106 / 120k with 16 rows (a ring
 //   of 4 rows on 16-row strips: 118 / 129k).
 // - FP64: a ring of 8 rows on 48-column strips (74 KiB, two workgroups of 8 waves per CU) for every
-//   model but BGK, 96 rows where deep_strip gives 64: at 4096^2 RM 98k, CM 92k, K 90k, PR 102k
-//   against 92k, 86k, 85k, 97k with a ring of 4 rows; BGK keeps the ring of 4 (98k against 96k).
+//   model, 128 rows where deep_strip gives 64: at 4096^2 with the strips dealt to the XCDs by column
+//   groups BGK 98k, RM 98k, K 91k, PR 103k (ring of 4 rows on 64-row strips: 98k, 91k, 84k, 96k;
+//   in bands of strip rows, 96-row strips: 95k, 97k, 90k, 100k).
 FusionPick deep_pick(int model, int nx, int ny, int prec, int cus) {
     const int hs = deep_strip(nx, ny, prec);
-    if (prec == LBM_F64) {
-        if (model == LBM_BGK) return FusionPick{4, hs};
-        return FusionPick{8, hs == 64 ? 96 : hs};
-    }
+    if (prec == LBM_F64) return FusionPick{8, hs == 64 ? 128 : hs};
     const long long gsx = (nx + kStripW - 1) / kStripW;
     const long long round = 3LL * cus;
     int h = hs;
@@ -332,9 +330,11 @@ __global__ __launch_bounds__(64 * step3_waves<RING>()) void k_step3n(const typen
     using R = typename Store<PREC>::R;
     __shared__ S ring1[9][RING + 2][WP + 4];
     __shared__ S ring2[9][RING + 2][WP + 3];
-    // strips dealt to the XCDs in contiguous bands (measured 1-4% faster than hardware order here)
+    // strips dealt to the XCDs by groups of 16 strip columns (bands of whole strip rows measured 1-4%
+    // faster than the hardware order; column groups with 128-row strips another 1-3%, and less
+    // sensitive to the strip height)
     unsigned sx, sy;
-    tile_of_block(blockIdx.x, gsx, gridDim.x, 1, sx, sy);
+    strip_of_block_grouped(blockIdx.x, gsx, gridDim.x, 16, sx, sy);
     const int x0 = (int)sx * WP;
     const int ys = (int)sy * hs;
     strip_three_steps_narrow<RING, WP, false, true, step3_waves<RING>()>(

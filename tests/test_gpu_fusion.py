@@ -127,7 +127,7 @@ def deep_pick(model, nx, ny, prec, cus):
     """(ring_rows, strip_rows) of a model's default three-step launches (include/lbm.h)."""
     hs = deep_strip(nx, ny, prec)
     if prec == "f64":
-        return (4, hs) if model == "BGK" else (8, 96 if hs == 64 else hs)
+        return (8, 128 if hs == 64 else hs)
     gsx = (nx + 63) // 64
     rnd = 3 * cus
 
@@ -172,7 +172,7 @@ def test_defaults_and_autotune(gpu):
         if (nx, ny, prec) == (4096, 4096, "f32"):
             assert exp[0] == (3, (8, 128))
         if (nx, ny, prec) == (4096, 4096, "f64"):
-            assert exp[0] == (3, (4, 64)) and exp[5] == (3, (8, 96))
+            assert exp[0] == (3, (8, 128)) and exp[5] == (3, (8, 128))
         if (nx, ny, prec) in ((256, 256, "f32"), (448, 512, "f64")):
             assert not deep
     # autotune leaves state and counter alone, keeps a valid choice, and results do not change
