@@ -72,15 +72,15 @@ def test_three_steps_large_grid(gpu):
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_default_three_steps_with_a_two_step_tail(gpu, prec):
-    # a new context on 768 x 512 runs three steps per launch; the two steps left over at the end of
-    # a call run as one two-step launch on the two-step default shape
-    nx, ny = 768, 512
+    # a new context on 2048 x 1024 runs three steps per launch on 24-row strips; the two steps left
+    # over at the end of a call run as one two-step launch on 16-row strips (the two-step default)
+    nx, ny = 2048, 1024
     rho, ux, uy = perturbed(nx, ny, 5)
     omega = inputs.rates(1e-4, "REG")
     for model in ("BGK", "K"):
         a = Sim(rho, ux, uy, prec=prec, device=gpu)
         b = Sim(rho, ux, uy, prec=prec, device=gpu)
-        assert b.fusion_depth(model) == 3
+        assert b.fusion_depth(model) == 3 and b.fusion(model) == (8, 24)
         a.set_fusion(model, 0)
         for n in (8, 5):
             a.step(model, omega, n)
