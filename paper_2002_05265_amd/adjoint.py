@@ -139,6 +139,9 @@ class _Run:
         # reverse steps in pairs, one launch each (the adjoint between them stays on chip); the
         # gradients are bit-identical to one reverse step per launch
         B.lbm_set_adjoint_depth(self.ctx, reverse_depth)
+        self.reverse_depth = reverse_depth
+        self.s = {"f64": 8, "f32": 4, "f16": 2}[prec]  # bytes per stored population
+        self.a = 8 if prec == "f64" else 4              # bytes per adjoint value
         self.sbytes = B.lbm_state_bytes(self.ctx)
         self.abytes = B.lbm_adjoint_bytes(self.ctx)
         self.dev = dev
@@ -163,6 +166,7 @@ class _Run:
         self.a_states, self.a_keep = [], []                # queued reverse steps
         self.steps_run = 0       # forward steps, including recomputation
         self.peak_states = 0     # most state buffers allocated at once
+        self.node_bytes = 0      # bytes per node read and written by the sweeps' step launches
 
     def _free_buffer(self):
         self.nbuf += 1
@@ -227,6 +231,7 @@ class _Run:
     def _flush_steps(self):
         if self.q_src:
             B.lbm_step_raw_many(self.ctx, self.model, self.omega, self.q_src, self.q_dst, self.q_step0)
+            self.node_bytes += 18 * self.s * len(self.q_src)
             self.q_src, self.q_dst = [], []
 
     def _reverse(self, states):
@@ -237,6 +242,10 @@ class _Run:
         m = len(states)
         ptrs = [self.lam[k % 3].data_ptr() for k in range(m + 1)]
         B.lbm_adjoint_many(self.ctx, self.model, self.omega, states, ptrs, None)
+        # a pair reads both states, gathers lambda_{n+1} and writes lambda_{n-1}; a single step
+        # reads one state, gathers lambda_{n+1} and writes lambda_n
+        pairs = m // 2 if self.reverse_depth == 2 else 0
+        self.node_bytes += pairs * 18 * (self.s + self.a) + (m - 2 * pairs) * (9 * self.s + 18 * self.a)
         r = m % 3
         self.lam = self.lam[r:] + self.lam[:r]
 
@@ -295,6 +304,8 @@ class _Run:
                 dst = place(chain[t])
                 ops.append(("1", cur, dst, step0 + t - 1))
                 cur, t = dst, t + 1
+        for o in ops:  # every launch reads and writes each population once; a pair may also write
+            self.node_bytes += (27 if o[0] == "2" and o[2] is not None else 18) * self.s
         # issue consecutive ops of one kind with one host call
         k = 0
         while k < len(ops):

@@ -68,3 +68,53 @@ def test_revolve_split_respects_binomial_bound():
         for free in range(1, 6):
             m = revolve_split(length, free)
             assert 1 <= m < length
+
+
+def fake_run(monkeypatch, n, schedule, s, a, depth, pairs=True, triples=True):
+    """A _Run whose launches are no-ops: only its host logic runs (which steps go into one-, two-
+    and three-step launches, which reverse steps are paired, the byte count of each launch)."""
+    import torch
+
+    import paper_2002_05265_amd.adjoint as A
+
+    for name in ("lbm_step_raw_many", "lbm_step2_raw_many", "lbm_step3_raw_many", "lbm_adjoint_many"):
+        monkeypatch.setattr(A.B, name, lambda *args, **kw: None)
+    r = A._Run.__new__(A._Run)
+    r.ctx, r.model, r.omega = None, 3, [1.0] * 5
+    r.s, r.a, r.reverse_depth = s, a, depth
+    r.node_bytes = r.steps_run = r.nbuf = r.peak_states = 0
+    r.schedule, r.nsteps = schedule, n
+    r.saved, r.refs = {}, {}
+    r.pool = [torch.empty(1, dtype=torch.uint8) for _ in range(n + 8)]
+    r._two_step = lambda: pairs
+    r._three_step = lambda: triples
+    r.cur = r._free_buffer()
+    r.lam = [torch.empty(1) for _ in range(3)]
+    return r
+
+
+@pytest.mark.parametrize("s,a", [(4, 4), (8, 8), (2, 4)])
+def test_sweep_bytes(monkeypatch, s, a):
+    # sqrt(n), n = 9: checkpoints every 3 steps.  Forward: three three-step launches, no state
+    # between kept (3 x 18 s).  Backward, per segment: one two-step launch that also writes the
+    # state between (27 s), then a pair of reverse steps (both states, lambda_{n+1} gathered,
+    # lambda_{n-1} written: 18 s + 18 a) and one reverse step (9 s + 18 a).
+    r = fake_run(monkeypatch, 9, "sqrt", s, a, 2)
+    r._forward_fast()
+    assert r.node_bytes == 3 * 18 * s
+    r._backward_fast()
+    assert r.steps_run == 9 + 6
+    assert r.node_bytes == 3 * 18 * s + 3 * (27 * s + (18 * s + 18 * a) + (9 * s + 18 * a))
+    # store-all, n = 9: every state kept, so four two-step launches writing the state between and
+    # one single step; reverse: four pairs and one single, or nine singles with one per launch
+    for depth, reverse in ((2, 4 * 18 * (s + a) + 9 * s + 18 * a), (1, 9 * (9 * s + 18 * a))):
+        r = fake_run(monkeypatch, 9, "store_all", s, a, depth)
+        r._forward_fast()
+        assert r.node_bytes == 4 * 27 * s + 18 * s
+        r._backward_fast()
+        assert r.node_bytes == 4 * 27 * s + 18 * s + reverse
+    # one step per launch: 18 s per step in both sweeps
+    r = fake_run(monkeypatch, 9, "sqrt", s, a, 1, pairs=False, triples=False)
+    r._forward_fast()
+    r._backward_fast()
+    assert r.node_bytes == (9 + 6) * 18 * s + 9 * (9 * s + 18 * a)
