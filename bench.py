@@ -52,6 +52,29 @@ def step_kernel_keys(model: str, prec: str):
             ("k_step", f"k_step<{args}")]
 
 
+def repeated_windows(sims, models, omega, cells: int, steps: int, k: int = 5):
+    """Each model's rate over k more windows of `steps` steps, back to back on its own grid (the
+    grids keep advancing; the rate does not depend on the data): median and relative spread,
+    next to the one timed window of the headline figure."""
+    import statistics
+
+    import torch
+
+    out = {}
+    for m in models:
+        rates = []
+        for _ in range(k):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            sims[m].step(m, omega, steps)
+            e1.record()
+            torch.cuda.synchronize()
+            rates.append(cells * steps / (e0.elapsed_time(e1) * 1e-3) / 1e6)
+        med = statistics.median(rates)
+        out[m] = {"median_mlups": round(med, 1), "spread": round((max(rates) - min(rates)) / med, 4)}
+    return {"windows": k, "steps": steps, "per_model": out}
+
+
 def launch_steps(sim, model: str) -> int:
     """Steps one launch of `model` advances on `sim`: 3, 2 or 1."""
     ring = sim.fusion(model)[0]
@@ -999,6 +1022,8 @@ def main():
     ev1.record()
     torch.cuda.synchronize()
     stream_launch_us = ev0.elapsed_time(ev1) * 1e3 / args.steps * launch_steps(ref_sim, "STREAM_ONLY")
+    # before single_step_rates, whose restoring lbm_set_fusion drops the contexts' two-step tail shape
+    repeats = repeated_windows(sims, models, omega, cells, args.steps)
     single = single_step_rates(sims, models, omega, cells, bpc, max(10, args.steps // 10))
     value = cells * args.steps * len(models) / wall / 1e6
     dominant = max(models, key=lambda m: per_model[m]["us_per_step"])
@@ -1031,6 +1056,7 @@ def main():
         "roofline": roofline_block(dominant, args.prec, kname, cells, bpc, spl, launch_us, stream_launch_us, n),
         "single_step": single,
         "per_model": per_model,
+        "repeats": repeats,
         "blowup": {m: st[1] for m, st in status.items()},
     }
     for s in sims.values():
