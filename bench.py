@@ -191,11 +191,23 @@ def _oracle_rate(job):
 
 
 def host_cpu():
-    """(CPU model name from /proc/cpuinfo, logical CPUs of the host, CPUs this process may use)."""
+    """(CPU model name from /proc/cpuinfo with its family / model / stepping numbers, clock and
+    cache size, which identify the generation where a virtual machine shows only a generic
+    name; logical CPUs of the host; CPUs this process may use)."""
     cpu = "unknown"
     try:
+        fields = {}
         with open("/proc/cpuinfo") as fh:
-            cpu = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), cpu)
+            for ln in fh:
+                if not ln.strip():
+                    break  # the first processor's block
+                k, _, v = ln.partition(":")
+                fields[k.strip()] = v.strip()
+        cpu = fields.get("model name", cpu)
+        extra = [f"{k} {fields[k]}" for k in ("vendor_id", "cpu family", "model", "stepping", "cpu MHz",
+                                              "cache size") if k in fields]
+        if extra:
+            cpu += " (" + ", ".join(extra) + ")"
     except OSError:
         pass
     try:
