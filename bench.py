@@ -75,6 +75,20 @@ def repeated_windows(sims, models, omega, cells: int, steps: int, k: int = 5):
     return {"windows": k, "steps": steps, "per_model": out}
 
 
+def fused_launch_us(sim, model: str, omega, launches: int) -> float:
+    """Average duration of `model`'s own launches on `sim`: `launches` whole fused launches (no
+    leftover launch of fewer steps) in one call, between two HIP events on the stream."""
+    import torch
+
+    spl = launch_steps(sim, model)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sim.step(model, omega, launches * spl)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / launches
+
+
 def launch_steps(sim, model: str) -> int:
     """Steps one launch of `model` advances on `sim`: 3, 2 or 1."""
     ring = sim.fusion(model)[0]
@@ -1012,6 +1026,10 @@ def main():
         ev[m][1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # each model's own launch duration: whole fused launches only, in a window right after the
+    # timed region (an event between the launches inside it costs ~1.5% of the rate; the leftover
+    # launch of a window, two steps of a 20-step window, is not one of these launches)
+    launch_us = {m: fused_launch_us(s, m, omega, max(4, args.steps // launch_steps(s, m))) for m, s in sims.items()}
 
     cells = n * n
     bpc = bytes_per_cell(args.prec)
@@ -1024,27 +1042,30 @@ def main():
         gbs = mlups * 1e6 * bpc / spl / 1e9
         per_model[m] = {"mlups": round(mlups, 1), "us_per_step": round(ms * 1e3 / args.steps, 2),
                         "steps_per_launch": spl, "ring_rows": ring, "strip_rows": strip,
-                        "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+                        "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "launch_us": round(launch_us[m], 2)}
     status = {m: s.status() for m, s in sims.items()}
     # the same grid, layout and launches with the collision left out: the rate of this access pattern
     ref_sim = next(iter(sims.values()))
+    sspl = launch_steps(ref_sim, "STREAM_ONLY")
+    nl = max(4, args.steps // sspl)  # whole fused launches only
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
-    ref_sim.step("STREAM_ONLY", omega, args.steps)
+    ref_sim.step("STREAM_ONLY", omega, nl * sspl)
     ev1.record()
     torch.cuda.synchronize()
-    stream_launch_us = ev0.elapsed_time(ev1) * 1e3 / args.steps * launch_steps(ref_sim, "STREAM_ONLY")
+    stream_launch_us = ev0.elapsed_time(ev1) * 1e3 / nl
     # before single_step_rates, whose restoring lbm_set_fusion drops the contexts' two-step tail shape
     repeats = repeated_windows(sims, models, omega, cells, args.steps)
     single = single_step_rates(sims, models, omega, cells, bpc, max(10, args.steps // 10))
     value = cells * args.steps * len(models) / wall / 1e6
     dominant = max(models, key=lambda m: per_model[m]["us_per_step"])
     spl = per_model[dominant]["steps_per_launch"]
-    launch_us = per_model[dominant]["us_per_step"] * spl
+    dom_launch_us = per_model[dominant]["launch_us"]
     kname = {3: "k_step3n" if args.prec == "f64" else "k_step3", 2: "k_step2", 1: "k_step"}[spl]
     for m in models:
         rec = counter_record(m, args.prec) if n == 4096 else None
-        lu = per_model[m]["us_per_step"] * per_model[m]["steps_per_launch"]
+        lu = per_model[m]["launch_us"]
         mf = None if rec is None else rec["hbm_bytes"] / (lu * 1e-6) / 1e9 / HBM_PEAK_GBS
         per_model[m]["valu_busy"] = None if rec is None else rec.get("valu_busy")
         per_model[m]["limiter"] = limiter(rec, mf)
@@ -1065,7 +1086,7 @@ def main():
                                f"{'shifted ' if args.prec != 'f64' else ''}{args.prec} populations, "
                                f"REG rates, 8 collision models (one grid each)",
                    "nx": n, "ny": n, "models": models, "omega": [round(w, 6) for w in omega]},
-        "roofline": roofline_block(dominant, args.prec, kname, cells, bpc, spl, launch_us, stream_launch_us, n),
+        "roofline": roofline_block(dominant, args.prec, kname, cells, bpc, spl, dom_launch_us, stream_launch_us, n),
         "single_step": single,
         "per_model": per_model,
         "repeats": repeats,
