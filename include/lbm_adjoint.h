@@ -62,8 +62,10 @@ int lbm_step_raw_many(lbm_ctx* ctx, int model, const double* omega, const void* 
                       void* const* dst, int count, long long step0);
 
 /* count (>= 0) pairs of raw steps in one call, in order, each as one launch of the two-step
- * kernel (lbm_set_fusion; strips of the model's strip height, 16 rows if two steps per launch
- * are off): pair k reads src[k] (state step0 + 2k) and writes dst[k] (state step0 + 2k + 2);
+ * kernel with a ring of 8 rows (strips as in lbm_set_fusion, of the height of the model's two-step
+ * tail shape where the context has one (lbm_set_fusion_depth), else of its lbm_set_fusion strip
+ * height, 16 rows if fused launches are off): pair k reads src[k] (state step0 + 2k) and writes
+ * dst[k] (state step0 + 2k + 2);
  * when mid is non-NULL and mid[k] is non-NULL, the state step0 + 2k + 1 is also written to
  * mid[k].  The states written are bit-identical to those of two lbm_step_raw calls.  src, mid
  * and dst are host arrays of device pointers; the three buffers of a pair must differ. */
