@@ -193,8 +193,8 @@ int lbm_get_fusion(lbm_ctx* ctx, int model, int* ring_rows, int* strip_rows);
  * columns on each side of the strip, the second one.  Strips are 64 columns wide in FP32 and 48 in
  * FP64 (the strip and its halo columns fit one wave); with ring_rows 8 a workgroup runs 8 waves, one
  * row each per pass.  Two steps left over by the three-step launches of a new context's default
- * setting run as one two-step launch on a shape of their own: ring_rows 8 on 64-column strips of
- * the smaller of the two-step default height and strip_rows rows; lbm_set_fusion drops that shape
+ * setting run as one two-step launch on a shape of their own: ring_rows 8 on strips (as in
+ * lbm_set_fusion) of the smaller of the two-step default height and strip_rows rows; lbm_set_fusion drops that shape
  * (its own shape then takes them), and lbm_autotune keeps its fastest two-step shape for them when
  * that beats single steps.  Bit-identical to single steps.  LBM_EUNSUPPORTED for 3 on an FP16
  * context or on a grid narrower or lower than 2; LBM_EINVAL for other values. */
