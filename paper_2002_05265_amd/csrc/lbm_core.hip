@@ -206,13 +206,13 @@ struct FusionPick {
 };
 constexpr FusionPick wide_default(int model) { return model == LBM_BGK ? FusionPick{8, 8} : FusionPick{4, 20}; }
 
-// Three steps per launch for a new FP32 or FP64 context (ring of 4 rows, 64-column strips) while
-// its strips number at least kDeepMinStrips.  The strip height is about gsx ny / sqrt(nx ny) rows
-// (n / 64 on an n x n grid: as many strips as columns), a multiple of 8 in [8, 64], and 80 in FP32
-// from 64 on.  Measured on MI355X (double shear layer, BGK / K): FP32 512^2 hs 8 77 / 66k MLUPS
-// (two steps per launch 59 / 54k), 1024^2 hs 16 129 / 118k (97 / 91k), 2048^2 hs 32 161 / 146k
-// (118 / 117k), 3072^2 hs 48 180 / 162k, 4096^2 hs 80 186 / 169k (hs 64: 1.5% less; two steps:
-// 145 / 138k); FP64 2048^2 75 / 72k (61 / 62k), 4096^2 hs 64 86 / 83k (75 / 74k).
+// Three steps per launch for a new FP32 or FP64 context while its 64-column strips number at least
+// kDeepMinStrips.  The strip height is about gsx ny / sqrt(nx ny) rows (n / 64 on an n x n grid: as
+// many strips as columns), a multiple of 8 in [8, 64], and 128 in place of 64 (deep_pick has the
+// ring and the final height).  Three steps against two per launch, first measured on MI355X with a
+// ring of 4 rows (double shear layer, BGK / K): FP32 512^2 77 / 66k MLUPS against 59 / 54k, 1024^2
+// 129 / 118k against 97 / 91k, 2048^2 161 / 146k against 118 / 117k, 4096^2 186 / 169k against
+// 145 / 138k; FP64 2048^2 75 / 72k against 61 / 62k, 4096^2 86 / 83k against 75 / 74k.
 constexpr long long kDeepMinStrips = 512;
 
 int deep_strip(int nx, int ny, int prec) {
@@ -304,8 +304,8 @@ __global__ __launch_bounds__(64 * step3_waves<RING>()) void k_step3(const typena
     // FP32: strips dealt to the XCDs by groups of 16 strip columns, so that neighbouring strips
     // share their edge lines in one L2 (in hardware order the traffic was 1.57x the algorithmic
     // bytes; bands of whole strip rows: 1.05x and 2-3% faster; column groups of 16 another 1-4%
-    // over bands, groups of 8 and 32 slightly less); FP64, bound by latency, measured 2% slower in
-    // bands and keeps the hardware order
+    // over bands, groups of 8 and 32 slightly less); FP64 on 64-column strips (not a default: FP64
+    // takes the 48-column k_step3n) measured 2% slower in bands and keeps the hardware order
     unsigned sx, sy;
     if constexpr (PREC == kF32)
         strip_of_block_grouped(blockIdx.x, gsx, gridDim.x, 16, sx, sy);
@@ -596,8 +596,9 @@ void launch_step3_w(lbm_ctx* ctx, const Coef<typename Store<PREC>::R>& c, int hs
                        ref_as<typename Store<PREC>::R>(ctx->ref), ctx->eq_order, step, ctx->d_flag, gsx, hs);
 }
 
-// FP64 three-step strips with a ring of 4 rows: 48 columns, the halo columns inside the wave (no halo
-// passes, 44 KiB of LDS: three workgroups per CU), each row segment three whole 128-byte lines.
+// FP64 three-step strips: 48 columns, the halo columns inside the wave (no halo passes), each row
+// segment three whole 128-byte lines; the rings take 74 KiB with a ring of 8 rows (two workgroups of
+// 8 waves per CU, the default) and 44 KiB with 4 (three workgroups of 4 waves).
 constexpr int kNarrowW = 48;
 
 // One launch of k_step3n (FP64 narrow strips) from the state src to dst.

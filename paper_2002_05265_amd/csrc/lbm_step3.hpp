@@ -209,7 +209,8 @@ namespace lbm {
 // takes column x0 - 2 + l in all three steps, the first step on lanes 0 .. WP + 3 (the strip and two
 // halo columns each side), the second on lanes 1 .. WP + 2, the third on lanes 2 .. WP + 1, which
 // write; there are no halo passes.  With WP = 48 in FP64 an output row segment is three whole
-// 128-byte lines and the rings take 44 KiB (three workgroups per CU against two for 64 columns).
+// 128-byte lines and the rings take 44 KiB with a ring of 4 rows (three workgroups per CU against two
+// for 64 columns), 74 KiB with a ring of 8 (two workgroups of 8 waves).
 // Same rows, ring slots and barriers as strip_three_steps; one wave per row, NW waves (4, or 8 with
 // a ring of 8 rows).  VIA_L2 selects L1-bypassing loads, NT streaming stores.
 template <int RING, int WP, bool VIA_L2 = false, bool NT = true, int NW = 4, typename S, typename R, typename Coll>
