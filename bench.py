@@ -62,14 +62,15 @@ def repeated_windows(sims, models, omega, cells: int, steps: int, k: int = 5):
 
     out = {}
     for m in models:
-        rates = []
-        for _ in range(k):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
+        # the windows back to back, one synchronisation after the last (an idle gap between
+        # windows would let the clocks drop)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(k + 1)]
+        ev[0].record()
+        for i in range(k):
             sims[m].step(m, omega, steps)
-            e1.record()
-            torch.cuda.synchronize()
-            rates.append(cells * steps / (e0.elapsed_time(e1) * 1e-3) / 1e6)
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        rates = [cells * steps / (ev[i].elapsed_time(ev[i + 1]) * 1e-3) / 1e6 for i in range(k)]
         med = statistics.median(rates)
         out[m] = {"median_mlups": round(med, 1), "spread": round((max(rates) - min(rates)) / med, 4)}
     return {"windows": k, "steps": steps, "per_model": out}
