@@ -60,34 +60,44 @@ def repeated_windows(sims, models, omega, cells: int, steps: int, k: int = 5):
 
     import torch
 
-    out = {}
+    # every window of every model back to back, one synchronisation after the last (an idle gap
+    # between windows would let the clocks drop)
+    evs = {}
     for m in models:
-        # the windows back to back, one synchronisation after the last (an idle gap between
-        # windows would let the clocks drop)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(k + 1)]
         ev[0].record()
         for i in range(k):
             sims[m].step(m, omega, steps)
             ev[i + 1].record()
-        torch.cuda.synchronize()
+        evs[m] = ev
+    torch.cuda.synchronize()
+    out = {}
+    for m in models:
+        ev = evs[m]
         rates = [cells * steps / (ev[i].elapsed_time(ev[i + 1]) * 1e-3) / 1e6 for i in range(k)]
         med = statistics.median(rates)
         out[m] = {"median_mlups": round(med, 1), "spread": round((max(rates) - min(rates)) / med, 4)}
     return {"windows": k, "steps": steps, "per_model": out}
 
 
-def fused_launch_us(sim, model: str, omega, launches: int) -> float:
-    """Average duration of `model`'s own launches on `sim`: `launches` whole fused launches (no
-    leftover launch of fewer steps) in one call, between two HIP events on the stream."""
+def fused_launch_us(sims, models, omega, steps: int):
+    """Average duration of each model's own launches: max(4, steps / steps per launch) whole fused
+    launches (no leftover launch of fewer steps) per model in one call, between two HIP events on
+    the stream, the models back to back with one synchronisation after the last."""
     import torch
 
-    spl = launch_steps(sim, model)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    sim.step(model, omega, launches * spl)
-    e1.record()
+    ev = {}
+    for m in models:
+        s = sims[m]
+        spl = launch_steps(s, m)
+        nl = max(4, steps // spl)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.step(m, omega, nl * spl)
+        e1.record()
+        ev[m] = (e0, e1, nl)
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) * 1e3 / launches
+    return {m: e0.elapsed_time(e1) * 1e3 / nl for m, (e0, e1, nl) in ev.items()}
 
 
 def launch_steps(sim, model: str) -> int:
@@ -1030,7 +1040,7 @@ def main():
     # each model's own launch duration: whole fused launches only, in a window right after the
     # timed region (an event between the launches inside it costs ~1.5% of the rate; the leftover
     # launch of a window, two steps of a 20-step window, is not one of these launches)
-    launch_us = {m: fused_launch_us(s, m, omega, max(4, args.steps // launch_steps(s, m))) for m, s in sims.items()}
+    launch_us = fused_launch_us(sims, models, omega, args.steps)
 
     cells = n * n
     bpc = bytes_per_cell(args.prec)
@@ -1060,7 +1070,7 @@ def main():
     repeats = repeated_windows(sims, models, omega, cells, args.steps)
     single = single_step_rates(sims, models, omega, cells, bpc, max(10, args.steps // 10))
     value = cells * args.steps * len(models) / wall / 1e6
-    dominant = max(models, key=lambda m: per_model[m]["us_per_step"])
+    dominant = max(models, key=lambda m: per_model[m]["launch_us"])  # the slowest kernel
     spl = per_model[dominant]["steps_per_launch"]
     dom_launch_us = per_model[dominant]["launch_us"]
     kname = {3: "k_step3n" if args.prec == "f64" else "k_step3", 2: "k_step2", 1: "k_step"}[spl]
