@@ -52,16 +52,12 @@ def step_kernel_keys(model: str, prec: str):
             ("k_step", f"k_step<{args}")]
 
 
-def repeated_windows(sims, models, omega, cells: int, steps: int, k: int = 5):
-    """Each model's rate over k more windows of `steps` steps, back to back on its own grid (the
-    grids keep advancing; the rate does not depend on the data): median and relative spread,
-    next to the one timed window of the headline figure."""
-    import statistics
-
+def repeated_windows(sims, models, omega, steps: int, k: int = 5):
+    """Issue k more windows of `steps` steps per model, back to back on each model's grid (the
+    grids keep advancing; the rate does not depend on the data), with a HIP event after each; read
+    them with repeats_from after a synchronisation."""
     import torch
 
-    # every window of every model back to back, one synchronisation after the last (an idle gap
-    # between windows would let the clocks drop)
     evs = {}
     for m in models:
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(k + 1)]
@@ -70,20 +66,26 @@ def repeated_windows(sims, models, omega, cells: int, steps: int, k: int = 5):
             sims[m].step(m, omega, steps)
             ev[i + 1].record()
         evs[m] = ev
-    torch.cuda.synchronize()
+    return evs
+
+
+def repeats_from(evs, cells: int, steps: int):
+    """Median and relative spread of each model's repeated windows, next to the one timed window of
+    the headline figure."""
+    import statistics
+
     out = {}
-    for m in models:
-        ev = evs[m]
-        rates = [cells * steps / (ev[i].elapsed_time(ev[i + 1]) * 1e-3) / 1e6 for i in range(k)]
+    for m, ev in evs.items():
+        rates = [cells * steps / (ev[i].elapsed_time(ev[i + 1]) * 1e-3) / 1e6 for i in range(len(ev) - 1)]
         med = statistics.median(rates)
         out[m] = {"median_mlups": round(med, 1), "spread": round((max(rates) - min(rates)) / med, 4)}
-    return {"windows": k, "steps": steps, "per_model": out}
+    return {"windows": len(next(iter(evs.values()))) - 1, "steps": steps, "per_model": out}
 
 
-def fused_launch_us(sims, models, omega, steps: int):
-    """Average duration of each model's own launches: max(4, steps / steps per launch) whole fused
-    launches (no leftover launch of fewer steps) per model in one call, between two HIP events on
-    the stream, the models back to back with one synchronisation after the last."""
+def fused_launch_windows(sims, models, omega, steps: int):
+    """Issue max(4, steps / steps per launch) whole fused launches (no leftover launch of fewer
+    steps) per model in one call each, between two HIP events; launch_us_from reads the average
+    launch duration after a synchronisation."""
     import torch
 
     ev = {}
@@ -96,7 +98,10 @@ def fused_launch_us(sims, models, omega, steps: int):
         s.step(m, omega, nl * spl)
         e1.record()
         ev[m] = (e0, e1, nl)
-    torch.cuda.synchronize()
+    return ev
+
+
+def launch_us_from(ev):
     return {m: e0.elapsed_time(e1) * 1e3 / nl for m, (e0, e1, nl) in ev.items()}
 
 
@@ -1037,10 +1042,23 @@ def main():
         ev[m][1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    # each model's own launch duration: whole fused launches only, in a window right after the
-    # timed region (an event between the launches inside it costs ~1.5% of the rate; the leftover
-    # launch of a window, two steps of a 20-step window, is not one of these launches)
-    launch_us = fused_launch_us(sims, models, omega, args.steps)
+    # right after the timed region, queued back to back with one synchronisation (an idle gap would
+    # let the clocks drop): each model's own launch duration over whole fused launches only (an
+    # event between the launches inside the timed region costs ~1.5% of the rate; the leftover
+    # launch of a window, two steps of a 20-step window, is not one of these launches), five more
+    # windows per model, and the same grid, layout and launches with the collision left out
+    lw = fused_launch_windows(sims, models, omega, args.steps)
+    rw = repeated_windows(sims, models, omega, args.steps)
+    ref_sim = next(iter(sims.values()))
+    sspl = launch_steps(ref_sim, "STREAM_ONLY")
+    nl = max(4, args.steps // sspl)  # whole fused launches only
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    ref_sim.step("STREAM_ONLY", omega, nl * sspl)
+    ev1.record()
+    torch.cuda.synchronize()
+    launch_us = launch_us_from(lw)
+    stream_launch_us = ev0.elapsed_time(ev1) * 1e3 / nl
 
     cells = n * n
     bpc = bytes_per_cell(args.prec)
@@ -1056,18 +1074,8 @@ def main():
                         "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                         "launch_us": round(launch_us[m], 2)}
     status = {m: s.status() for m, s in sims.items()}
-    # the same grid, layout and launches with the collision left out: the rate of this access pattern
-    ref_sim = next(iter(sims.values()))
-    sspl = launch_steps(ref_sim, "STREAM_ONLY")
-    nl = max(4, args.steps // sspl)  # whole fused launches only
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    ref_sim.step("STREAM_ONLY", omega, nl * sspl)
-    ev1.record()
-    torch.cuda.synchronize()
-    stream_launch_us = ev0.elapsed_time(ev1) * 1e3 / nl
-    # before single_step_rates, whose restoring lbm_set_fusion drops the contexts' two-step tail shape
-    repeats = repeated_windows(sims, models, omega, cells, args.steps)
+    repeats = repeats_from(rw, cells, args.steps)
+    # last: its restoring lbm_set_fusion drops the contexts' two-step tail shape
     single = single_step_rates(sims, models, omega, cells, bpc, max(10, args.steps // 10))
     value = cells * args.steps * len(models) / wall / 1e6
     dominant = max(models, key=lambda m: per_model[m]["launch_us"])  # the slowest kernel
