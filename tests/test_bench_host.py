@@ -114,3 +114,14 @@ def test_profile_summary_round_trip(tmp_path, monkeypatch):
     # a summary taken from other sources is not used
     (prof / "step_kernels_f32_dsl4096_counters.md").write_text(counters.replace(blob["step_source_hash"], "0" * 16))
     assert bench.measured_traffic("K", "f32") is None
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64", "f16"])
+def test_profiles_keyed_to_current_sources(prec):
+    # the committed counter summaries were taken from the step kernels as they are now: every
+    # model's record is found (the bench reports measured traffic from them only while the sources
+    # hash to the recorded value), so a kernel change without new counters fails here
+    for model in bench.MODEL_ORDER:
+        rec = bench.counter_record(model, prec)
+        assert rec is not None, (prec, model, bench.step_source_hash())
+        assert rec["hbm_bytes"] > 0
